@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark of the fork-processing hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one complete fork-processing run (state init + every pass of the
+buffered execution until all buffers are empty) over the workload's whole
+query batch, with the graph and sources already resident on the GPU.  The
+default workload is R-MAT scale 20 (1,048,576 vertices, 16,777,216 edges,
+a/b/c/d = 0.57/0.19/0.19/0.05, unweighted) with 4,096 PPR forward-push
+queries (alpha = 0.15, epsilon = 1e-6, push while r >= epsilon * outdeg) from
+seeded uniform sources.
+
+Prints one JSON line with queries/s, the dominant kernel's roofline figures
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "queries/sec for batched SSSP+PPR at 1 GPU; learned vs rule schedule speedup"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(st: dict, kind: str) -> float:
+    """Bytes the buffered pass must move for the work it did.
+
+    per edge scanned: 4 B target id (+ weight bytes for SSSP);
+    per edge whose target is in the same partition: 8 B state read+write;
+    per operation emitted: 8 B written; per operation consumed: 8 B read
+    + 8 B state read+write; per vertex expanded: 12 B (SSSP/BFS: row
+    bounds + distance) or 24 B (PPR: row bounds, r exchange, p update)."""
+    wb = st["weight_bytes"] if kind == "sssp" else 0
+    per_v = 24 if kind == "ppr" else 12
+    return (st["edges"] * (4 + wb) + st["intra_edges"] * 8 + st["ops_emitted"] * 8 + st["ops_consumed"] * 16
+            + st["vertex_pushes"] * per_v)
+
+
+def cpu_baseline(g, queries, spec, budget_s=15.0):
+    """The CPU oracle, untuned, one query per thread over all host cores."""
+    import oracle
+    threads = os.cpu_count() or 1
+    kinds = [(qt, s) for qt, s in queries]
+    done, t_total = 0, 0.0
+    rng = np.random.default_rng(0)
+    samples = []
+    while t_total < budget_s and done < sum(len(s) for _, s in kinds):
+        for qt, s in kinds:
+            batch = rng.choice(s, size=min(threads, len(s)), replace=False)
+            t0 = time.perf_counter()
+            if qt == "ppr":
+                oracle.forward_push(g, batch, spec.get("alpha", 0.15), spec.get("epsilon", 1e-6),
+                                    spec.get("eps_mode", 0), threads)
+            elif qt == "bfs":
+                oracle.bfs(g, batch, threads)
+            else:
+                oracle.sssp(g, batch, threads)
+            t_total += time.perf_counter() - t0
+            done += len(batch)
+            samples.append(f"{len(batch)} {qt}")
+    return {"value": done / t_total, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} queries ({', '.join(sorted(set(samples)))} per batch) of the same workload, "
+                      f"{t_total:.1f} s, fp64 forward push / Dijkstra / BFS, one query per thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat20_ppr4096")
+    ap.add_argument("--scheduler", default="priority")
+    ap.add_argument("--parts-per-pass", type=int, default=0)
+    ap.add_argument("--partition-vertices", type=int, default=0)
+    ap.add_argument("--delta", type=int, default=0)
+    ap.add_argument("--mu", type=float, default=0.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--scale", type=int, default=0, help="experiment: override the R-MAT scale")
+    ap.add_argument("--queries", type=int, default=0, help="experiment: use only the first N queries per type")
+    ap.add_argument("--max-queries", type=int, default=0, help="queries resident per wave (0 = auto)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(queries shard across GPUs with no exchange; see DESIGN.md)"}))
+        sys.exit(2)
+
+    import torch
+    import fpp_inputs as fi
+    import paper_2103_14915_amd as fork
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    spec = fi.WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    g = fi.make_graph(spec, scale_override=args.scale or None)
+    queries = fi.make_sources(g, spec)
+    if args.queries:
+        queries = [(qt, s[:args.queries]) for qt, s in queries]
+    t_gen = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=args.partition_vertices, max_queries=args.max_queries)
+    t_load = time.perf_counter() - t0
+    nq = 0
+    for qt, s in queries:
+        fg.submit(qt, s, alpha=spec.get("alpha", 0.15), epsilon=spec.get("epsilon", 1e-6),
+                  eps_mode=spec.get("eps_mode", 0))
+        nq += len(s)
+    kinds = sorted({qt for qt, _ in queries})
+    kind = kinds[0] if len(kinds) == 1 else "mixed"
+    run_kw = dict(scheduler=args.scheduler, parts_per_pass=args.parts_per_pass, delta=args.delta,
+                  edge_budget_mu=args.mu, stream=stream, profile=1)
+    for _ in range(args.warmup):
+        fg.run(**run_kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot = None
+    for _ in range(args.steps):
+        fg.run(**run_kw)
+        st = fg.stats()
+        tot = st if tot is None else {k: tot[k] + st[k] if isinstance(st[k], (int, float)) else st[k]
+                                      for k in st}
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for k in ("num_partitions", "weight_bytes"):
+        tot[k] = st[k]
+    value = nq * args.steps / dt
+    abytes = algorithmic_bytes(tot, kind if kind != "mixed" else "sssp")
+    launches = max(1, tot["process_launches"])
+    avg_ms = tot["process_ms"] / launches
+    achieved = (abytes / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if "ppr" in kinds else "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload + (f"@scale{args.scale}" if args.scale else "")
+                   + (f"@q{args.queries}" if args.queries else ""), "queries": nq, "types": kinds, "vertices": g.num_vertices,
+                   "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler,
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_process",
+                     "avg_launch_ms": avg_ms, "launches_per_step": launches / args.steps,
+                     "algorithmic_bytes_per_step": abytes / args.steps},
+        "detail": {"graph_gen_s": t_gen, "graph_load_s": t_load,
+                   "init_ms_per_step": tot["init_ms"] / args.steps, "run_ms_per_step": tot["run_ms"] / args.steps,
+                   "process_ms_per_step": tot["process_ms"] / args.steps,
+                   "passes_per_step": tot["passes"] / args.steps,
+                   "edges_per_step": tot["edges"] / args.steps,
+                   "ops_emitted_per_step": tot["ops_emitted"] / args.steps,
+                   "vertex_pushes_per_step": tot["vertex_pushes"] / args.steps,
+                   "work_items_per_step": tot["work_items"] / args.steps},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(g, queries, spec, args.cpu_budget)
+    fg.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -198,16 +198,16 @@ WORKLOADS = {
     "rmat12_sssp64": dict(kind="rmat", scale=12, weights=(1, 255), seeds=(1, 101, 201),
                           queries=[("sssp", 64, "uniform")]),
     "rmat20_ppr4096": dict(kind="rmat", scale=20, weights=None, seeds=(2, 102, 202),
-                           queries=[("ppr", 4096, "uniform")], alpha=0.15, epsilon=1e-6),
+                           queries=[("ppr", 4096, "uniform")], alpha=0.15, epsilon=1e-6, eps_mode=1),
     "grid2048_sssp1024_bfs1024": dict(kind="grid", rows=2048, cols=2048, weights=(1, 1000),
                                       seeds=(3, 103, 203),
                                       queries=[("sssp", 1024, "uniform"), ("bfs", 1024, "uniform")]),
     "rmat22_mixed16384": dict(kind="rmat", scale=22, weights=(1, 255), seeds=(4, 104, 204),
                               queries=[("sssp", 8192, "mixed"), ("bfs", 4096, "mixed"),
-                                       ("ppr", 4096, "mixed")], alpha=0.15, epsilon=1e-6),
+                                       ("ppr", 4096, "mixed")], alpha=0.15, epsilon=1e-6, eps_mode=1),
     "rmat23_sssp_ppr65536": dict(kind="rmat", scale=23, weights=(1, 255), seeds=(5, 105, 205),
                                  queries=[("sssp", 32768, "mixed"), ("ppr", 32768, "mixed")],
-                                 alpha=0.15, epsilon=1e-6),
+                                 alpha=0.15, epsilon=1e-6, eps_mode=1),
 }
 
 

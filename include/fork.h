@@ -1,0 +1,190 @@
+/*
+ * fork.h -- C ABI of the MI355X (gfx950) fork-processing library.
+ *
+ * A fork-processing pattern (FPP) launches many independent single-source
+ * queries on one shared graph (Algorithm 1; Definition 2.2).  This library
+ * runs them with the paper's buffered execution model (Section 3, Algorithm
+ * 2): the graph is cut into partitions (Definition 2.1), each partition keeps a
+ * buffer of pending operations <q, v, val> (Definition 2.3), and the
+ * scheduler repeatedly picks partitions (Section 5.2) whose buffered queries
+ * are then processed together, with yielding (Section 5.1), until every buffer
+ * is empty.
+ *
+ * Conventions for every entry point:
+ *   - Returns FORK_OK (0) or a negative fork_status.  No exception or abort
+ *     crosses the ABI.  fork_last_error() gives a message for the last failing
+ *     call on the calling thread.
+ *   - Pointers are plain host pointers unless a flag says "device".  Input
+ *     arrays are only borrowed for the duration of the call (copied).
+ *   - The context owns all device memory it allocates until fork_destroy.
+ *   - A context is not thread-safe: calls on one context must be serialised.
+ */
+#ifndef FORK_H
+#define FORK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fork_ctx fork_ctx;
+
+typedef enum {
+    FORK_OK = 0,
+    FORK_E_INVALID = -1,       /* bad argument; nothing changed              */
+    FORK_E_NOMEM = -2,         /* device or host allocation failed           */
+    FORK_E_DEVICE = -3,        /* HIP runtime error, or no usable GPU        */
+    FORK_E_STATE = -4,         /* call not valid in the context's state      */
+    FORK_E_CAPACITY = -5,      /* operation pool exhausted during a run      */
+    FORK_E_NOT_CONVERGED = -6  /* max_passes reached with work still pending */
+} fork_status;
+
+/* Query kinds (Section 3 lists the supported FPP queries). */
+typedef enum { FORK_SSSP = 1, FORK_BFS = 2, FORK_PPR = 3 } fork_query_type;
+
+/* Inter-partition scheduling policies (Section 5.2; the alternatives are the
+ * ones compared in the paper's priority-functor study).  LEARNED replaces the
+ * priority functor by an MLP score computed from buffer statistics. */
+typedef enum {
+    FORK_SCHED_FIFO = 0,      /* oldest pending operation first (paper default) */
+    FORK_SCHED_PRIORITY = 1,  /* best buffered-operation priority first        */
+    FORK_SCHED_LEARNED = 2,   /* MLP score over partition statistics           */
+    FORK_SCHED_RANDOM = 3,    /* any partition with pending work               */
+    FORK_SCHED_MAXOPS = 4     /* most buffered operations first                */
+} fork_sched;
+
+/* Graph-level configuration, fixed at fork_graph_load.  Zero = automatic. */
+typedef struct {
+    uint32_t partition_vertices; /* max vertices per partition (<= 65536)      */
+    uint32_t partition_edges;    /* max out-edges per partition (edge balance) */
+    uint32_t max_queries;        /* queries resident at once (a "wave")        */
+    uint64_t pool_bytes;         /* device bytes for the operation pool        */
+    int      inputs_on_device;   /* row_ptr/col/weight are device pointers     */
+    int      device;             /* HIP device ordinal                          */
+} fork_config;
+
+/* PPR parameters (passed to fork_submit for FORK_PPR).  A vertex is pushed
+ * while r[v] > 0 and r[v] >= thr(v), thr(v) = epsilon (eps_mode 0) or
+ * epsilon * outdeg(v) (eps_mode 1). */
+typedef struct {
+    float alpha;    /* teleport probability, in (0, 1) */
+    float epsilon;  /* push threshold, > 0             */
+    int   eps_mode; /* 0 = absolute, 1 = degree-scaled */
+} fork_ppr_params;
+
+/* Per-run options.  NULL = defaults (PRIORITY, automatic tuning, stream 0). */
+typedef struct {
+    int      scheduler;        /* fork_sched                                     */
+    uint32_t parts_per_pass;   /* partitions processed per pass (0 = auto)       */
+    uint32_t delta;            /* SSSP/BFS window width and yield range (0=auto) */
+    float    edge_budget_mu;   /* yield after mu*|E_P|/|Q_P| edges (0 = off)     */
+    uint64_t max_passes;       /* 0 = unlimited                                  */
+    void    *stream;           /* hipStream_t to run on (NULL = default stream)  */
+    const float *mlp_weights;  /* 5,313 fp32 (host), for FORK_SCHED_LEARNED      */
+    int      persistent;       /* 1 = one persistent kernel with a device queue  */
+    uint64_t seed;             /* for FORK_SCHED_RANDOM                          */
+    int      profile;          /* 1 = time every pass kernel with HIP events     */
+} fork_run_opts;
+
+/* Counters accumulated over the last fork_run (all waves). */
+typedef struct {
+    uint64_t passes;           /* scheduling steps                          */
+    uint64_t work_items;       /* (partition, query) items processed        */
+    uint64_t edges;            /* edges scanned (relaxations / edge pushes) */
+    uint64_t improved;         /* state writes that improved a value        */
+    uint64_t ops_emitted;      /* operations written to buffers             */
+    uint64_t ops_consumed;     /* operations read from buffers              */
+    uint64_t vertex_pushes;    /* PPR vertex pushes / SSSP vertex expansions*/
+    uint64_t yields;           /* work items that yielded                   */
+    uint64_t chunks;           /* pool chunks allocated                     */
+    uint64_t waves;            /* query waves                               */
+    double   init_ms;          /* state init + seeding, all waves           */
+    double   run_ms;           /* buffered processing, all waves            */
+    double   digest_ms;        /* digest computation                        */
+    double   process_ms;       /* sum of pass-kernel durations (profile=1)  */
+    uint64_t process_launches; /* pass kernels timed                        */
+    uint64_t intra_edges;      /* edges whose target is in the same partition */
+    uint32_t num_partitions;
+    uint32_t weight_bytes;     /* bytes per stored edge weight (0 = none)   */
+} fork_stats_t;
+
+/* Per-query digest (fork_fetch field FORK_FIELD_DIGEST).  For SSSP/BFS:
+ * count = reached vertices, sum = sum of finite values, hash = sum mod 2^64
+ * over reached v of mix64(v * 2^32 + value) with mix64 the SplitMix64
+ * finaliser.  For PPR: count = vertices with p > 0, fsum = sum of p,
+ * fres = sum of r, fmax = max p. */
+typedef struct {
+    uint64_t count;
+    uint64_t sum;
+    uint64_t hash;
+    double   fsum, fres, fmax;
+} fork_digest;
+
+enum {
+    FORK_FIELD_VALUE = 0,  /* int32[V] distance or level                     */
+    FORK_FIELD_P = 1,      /* float[V] PPR estimate p                        */
+    FORK_FIELD_R = 2,      /* float[V] PPR residual r                        */
+    FORK_FIELD_DIGEST = 3  /* fork_digest                                    */
+};
+
+/*
+ * Load a graph (Definition 2.1 fixes what a partition owns: the out-edges of
+ * its vertices).  row_ptr: uint64[num_vertices+1], col: uint32[num_edges],
+ * weight: uint32[num_edges] positive integers, or NULL for unit weights.
+ * Requires num_edges < 2^32, num_vertices >= 1, every col < num_vertices,
+ * row_ptr non-decreasing from 0 to num_edges.  cfg may be NULL.  On success
+ * *out owns a new context.
+ */
+int fork_graph_load(fork_ctx **out, uint32_t num_vertices, uint64_t num_edges,
+                    const uint64_t *row_ptr, const uint32_t *col,
+                    const uint32_t *weight, const fork_config *cfg);
+
+/*
+ * Add n queries of one type from the given source vertices (Algorithm 1:
+ * one query per source).  params: NULL for SSSP/BFS, a fork_ppr_params* for
+ * PPR.  All-or-nothing: any source >= V, a bad type or bad PPR parameters
+ * gives FORK_E_INVALID and enqueues nothing.  Query ids are dense, assigned in
+ * submit order from 0; *first_query_id (may be NULL) receives the first id.
+ * Submitting after a run starts a new batch (previous results are dropped).
+ */
+int fork_submit(fork_ctx *ctx, int query_type, const uint32_t *sources,
+                uint32_t n, const void *params, uint32_t *first_query_id);
+
+/*
+ * Run all submitted queries to completion (Algorithm 2: while any buffer
+ * holds operations, schedule a partition and process it).  Queries beyond
+ * max_queries run in successive waves; every query gets a digest, and full
+ * vectors stay available for the queries of the last wave.  Blocks until done.
+ * Results are exact for SSSP/BFS whatever the schedule (Section 5.1: yielded
+ * operations are retained, so correctness holds).
+ */
+int fork_run(fork_ctx *ctx, const fork_run_opts *opts);
+
+/*
+ * Copy one query's result: field FORK_FIELD_VALUE (int32[V]), _P or _R
+ * (float[V]) or _DIGEST (fork_digest).  dst_bytes must be large enough.
+ * dst_on_device != 0: dst is a device pointer (device-to-device copy).
+ * FORK_E_STATE if the query has not run, or its vectors are no longer
+ * resident (an earlier wave); FORK_E_INVALID for a field that does not match
+ * the query type.
+ */
+int fork_fetch(fork_ctx *ctx, uint32_t query_id, int field, void *dst,
+               uint64_t dst_bytes, int dst_on_device);
+
+/* Copy the counters of the last run into *dst (dst_bytes >= sizeof). */
+int fork_stats(fork_ctx *ctx, void *dst, uint64_t dst_bytes);
+
+/* Partition plan: writes up to cap+1 boundaries; *num_parts receives |P|. */
+int fork_partitions(fork_ctx *ctx, uint32_t *starts, uint32_t cap, uint32_t *num_parts);
+
+/* Free the context and all its device memory.  NULL is ignored. */
+void fork_destroy(fork_ctx *ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *fork_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FORK_H */

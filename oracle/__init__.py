@@ -161,8 +161,13 @@ def ppr_invariant_l1(g, source, p, r, alpha, threads=None) -> float:
     return float(np.abs(np.asarray(p, np.float64) - ref).sum())
 
 
-def push_terminal(g, r, eps, mode=0) -> bool:
-    """True if no vertex is active: r[u] < thr(u) or r[u] <= 0 for all u."""
-    r = np.asarray(r, np.float64)
-    thr = eps * g.out_degree().astype(np.float64) if mode else np.full(r.shape, eps)
+def push_terminal(g, r, eps, mode=0, dtype=np.float64) -> bool:
+    """True if no vertex is active: r[u] <= 0 or r[u] < thr(u) for all u.
+
+    ``dtype`` is the precision in which the threshold decision is taken: the
+    fp64 oracle decides in fp64; an fp32 push decides with
+    thr = fp32(eps) * fp32(outdeg) in fp32, so its result is checked that way."""
+    r = np.asarray(r, dtype)
+    e = dtype(eps)
+    thr = e * g.out_degree().astype(dtype) if mode else np.full(r.shape, e, dtype)
     return bool(np.all((r <= 0) | (r < thr)))

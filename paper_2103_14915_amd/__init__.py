@@ -1,0 +1,216 @@
+"""Python binding of the MI355X fork-processing library (``libfork.so``).
+
+Thin ctypes marshalling over the C ABI declared in ``include/fork.h``: every
+step of the fork-processing pass runs in the library's HIP kernels.  Inputs
+may be numpy arrays (host) or torch tensors (host or device); results come
+back as numpy arrays or are written into caller-provided torch tensors.
+
+The library must have been built (``python -m paper_2103_14915_amd.build``);
+importing this package without it raises ImportError, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfork.so")
+
+FORK_OK, FORK_E_INVALID, FORK_E_NOMEM, FORK_E_DEVICE, FORK_E_STATE, FORK_E_CAPACITY, FORK_E_NOT_CONVERGED = (
+    0, -1, -2, -3, -4, -5, -6)
+SSSP, BFS, PPR = 1, 2, 3
+SCHED_FIFO, SCHED_PRIORITY, SCHED_LEARNED, SCHED_RANDOM, SCHED_MAXOPS = 0, 1, 2, 3, 4
+FIELD_VALUE, FIELD_P, FIELD_R, FIELD_DIGEST = 0, 1, 2, 3
+QTYPES = {"sssp": SSSP, "bfs": BFS, "ppr": PPR}
+SCHEDS = {"fifo": SCHED_FIFO, "priority": SCHED_PRIORITY, "learned": SCHED_LEARNED, "random": SCHED_RANDOM,
+          "maxops": SCHED_MAXOPS}
+MLP_NPARAM = 5313
+INF = 0x7FFFFFFF
+
+
+class ForkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fork error {code}: {msg}")
+        self.code = code
+
+
+class fork_config(ctypes.Structure):
+    _fields_ = [("partition_vertices", ctypes.c_uint32), ("partition_edges", ctypes.c_uint32),
+                ("max_queries", ctypes.c_uint32), ("pool_bytes", ctypes.c_uint64),
+                ("inputs_on_device", ctypes.c_int), ("device", ctypes.c_int)]
+
+
+class fork_ppr_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_float), ("epsilon", ctypes.c_float), ("eps_mode", ctypes.c_int)]
+
+
+class fork_run_opts(ctypes.Structure):
+    _fields_ = [("scheduler", ctypes.c_int), ("parts_per_pass", ctypes.c_uint32), ("delta", ctypes.c_uint32),
+                ("edge_budget_mu", ctypes.c_float), ("max_passes", ctypes.c_uint64),
+                ("stream", ctypes.c_void_p), ("mlp_weights", ctypes.c_void_p), ("persistent", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("profile", ctypes.c_int)]
+
+
+class fork_stats_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("passes", "work_items", "edges", "improved", "ops_emitted",
+                                                "ops_consumed", "vertex_pushes", "yields", "chunks", "waves")] + \
+               [("init_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("digest_ms", ctypes.c_double),
+                ("process_ms", ctypes.c_double), ("process_launches", ctypes.c_uint64),
+                ("intra_edges", ctypes.c_uint64), ("num_partitions", ctypes.c_uint32),
+                ("weight_bytes", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class fork_digest(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint64), ("sum", ctypes.c_uint64), ("hash", ctypes.c_uint64),
+                ("fsum", ctypes.c_double), ("fres", ctypes.c_double), ("fmax", ctypes.c_double)]
+
+
+EXPORTS = ["fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions",
+           "fork_destroy", "fork_last_error"]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2103_14915_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    lib.fork_graph_load.argtypes = [ctypes.POINTER(ctypes.c_void_p), U32, U64, P, P, P,
+                                    ctypes.POINTER(fork_config)]
+    lib.fork_submit.argtypes = [P, I, P, U32, P, ctypes.POINTER(U32)]
+    lib.fork_run.argtypes = [P, ctypes.POINTER(fork_run_opts)]
+    lib.fork_fetch.argtypes = [P, U32, I, P, U64, I]
+    lib.fork_stats.argtypes = [P, P, U64]
+    lib.fork_partitions.argtypes = [P, P, U32, ctypes.POINTER(U32)]
+    lib.fork_destroy.argtypes = [P]
+    lib.fork_destroy.restype = None
+    lib.fork_last_error.restype = ctypes.c_char_p
+    for n in ("fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions"):
+        getattr(lib, n).restype = I
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc != FORK_OK:
+        raise ForkError(rc, lib.fork_last_error().decode())
+
+
+def _ptr(x):
+    """(pointer, on_device, keepalive) for a numpy array or torch tensor (None -> NULL)."""
+    if x is None:
+        return None, False, None
+    if isinstance(x, np.ndarray):
+        x = np.ascontiguousarray(x)
+        return ctypes.c_void_p(x.ctypes.data), False, x
+    # torch tensor
+    if not x.is_contiguous():
+        x = x.contiguous()
+    return ctypes.c_void_p(x.data_ptr()), x.is_cuda, x
+
+
+class ForkGraph:
+    """A graph loaded on the GPU plus the queries submitted against it."""
+
+    def __init__(self, num_vertices, row_ptr, col, weight=None, partition_vertices=0, partition_edges=0,
+                 max_queries=0, pool_bytes=0, device=0):
+        rp, dev_rp, k1 = _ptr(row_ptr if not isinstance(row_ptr, np.ndarray) else row_ptr.astype(np.uint64))
+        cp, dev_c, k2 = _ptr(col if not isinstance(col, np.ndarray) else col.astype(np.uint32))
+        wp, dev_w, k3 = _ptr(weight if (weight is None or not isinstance(weight, np.ndarray))
+                             else weight.astype(np.uint32))
+        on_dev = dev_rp or dev_c or dev_w
+        if on_dev and not (dev_rp and dev_c and (weight is None or dev_w)):
+            raise ValueError("row_ptr, col and weight must all be on the host or all on the device")
+        cfg = fork_config(partition_vertices, partition_edges, max_queries, pool_bytes, int(on_dev), device)
+        ne = int(k2.shape[0]) if k2 is not None else 0
+        self._ctx = ctypes.c_void_p()
+        self.num_vertices = int(num_vertices)
+        self.num_edges = ne
+        _check(lib.fork_graph_load(ctypes.byref(self._ctx), self.num_vertices, ne, rp, cp, wp, ctypes.byref(cfg)))
+        self.types = []
+
+    @classmethod
+    def from_graph(cls, g, **kw):
+        return cls(g.num_vertices, g.row_ptr, g.col, g.weight, **kw)
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib.fork_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def partitions(self) -> np.ndarray:
+        n = ctypes.c_uint32()
+        _check(lib.fork_partitions(self._ctx, None, 0, ctypes.byref(n)))
+        out = np.empty(n.value + 1, np.uint32)
+        _check(lib.fork_partitions(self._ctx, ctypes.c_void_p(out.ctypes.data), n.value, ctypes.byref(n)))
+        return out
+
+    def submit(self, qtype, sources, alpha=0.15, epsilon=1e-6, eps_mode=0) -> int:
+        t = QTYPES[qtype] if isinstance(qtype, str) else int(qtype)
+        src = np.ascontiguousarray(np.asarray(sources), np.uint32)
+        params = None
+        if t == PPR:
+            params = ctypes.byref(fork_ppr_params(alpha, epsilon, eps_mode))
+        first = ctypes.c_uint32()
+        _check(lib.fork_submit(self._ctx, t, ctypes.c_void_p(src.ctypes.data), src.size, params,
+                               ctypes.byref(first)))
+        if self.types and first.value == 0:
+            self.types = []
+        self.types.extend([t] * src.size)
+        return first.value
+
+    def run(self, scheduler="priority", parts_per_pass=0, delta=0, edge_budget_mu=0.0, max_passes=0,
+            stream=None, mlp_weights=None, persistent=0, seed=0, profile=0):
+        s = SCHEDS[scheduler] if isinstance(scheduler, str) else int(scheduler)
+        w = None
+        if mlp_weights is not None:
+            w = np.ascontiguousarray(np.asarray(mlp_weights, np.float32))
+            if w.size != MLP_NPARAM:
+                raise ValueError(f"mlp_weights must have {MLP_NPARAM} values")
+        sp = None
+        if stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        o = fork_run_opts(s, parts_per_pass, delta, edge_budget_mu, max_passes, sp,
+                          None if w is None else w.ctypes.data, persistent, seed, profile)
+        _check(lib.fork_run(self._ctx, ctypes.byref(o)))
+
+    def fetch(self, qid, field=None, out=None):
+        """Result vector of query qid (numpy), or written into a device tensor `out`."""
+        t = self.types[qid]
+        if field is None:
+            field = FIELD_VALUE if t != PPR else FIELD_P
+        dtype = np.int32 if field == FIELD_VALUE else np.float32
+        if out is not None:
+            p, on_dev, keep = _ptr(out)
+            _check(lib.fork_fetch(self._ctx, qid, field, p, out.numel() * out.element_size(), int(on_dev)))
+            return out
+        arr = np.empty(self.num_vertices, dtype)
+        _check(lib.fork_fetch(self._ctx, qid, field, ctypes.c_void_p(arr.ctypes.data), arr.nbytes, 0))
+        return arr
+
+    def digest(self, qid) -> dict:
+        d = fork_digest()
+        _check(lib.fork_fetch(self._ctx, qid, FIELD_DIGEST, ctypes.byref(d), ctypes.sizeof(d), 0))
+        return {n: getattr(d, n) for n, _ in d._fields_}
+
+    def stats(self) -> dict:
+        s = fork_stats_t()
+        _check(lib.fork_stats(self._ctx, ctypes.byref(s), ctypes.sizeof(s)))
+        return s.as_dict()
+
+
+def last_error() -> str:
+    return lib.fork_last_error().decode()

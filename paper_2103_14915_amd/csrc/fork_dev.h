@@ -1,0 +1,108 @@
+// Device-side data structures shared by the kernels and the host runtime of
+// the fork-processing library (gfx950).  Internal: not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fk {
+
+constexpr int WAVE = 64;
+constexpr int CH = 256;                   // operations per pool chunk
+constexpr uint32_t INF = 0x7fffffffu;     // unreachable distance / level
+constexpr uint32_t RETAIN = 0x80000000u;  // op flag: retained (yielded) work
+constexpr int NXCD = 8;                   // MI355X: 8 XCDs of 32 CUs
+constexpr uint32_t VPMAX = 16384;         // max vertices per partition
+constexpr int MLP_IN = 16, MLP_H = 64;
+constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;  // 5313
+
+enum QType : uint32_t { Q_SSSP = 1, Q_BFS = 2, Q_PPR = 3 };
+enum Sched : uint32_t { S_FIFO = 0, S_PRIORITY = 1, S_LEARNED = 2, S_RANDOM = 3, S_MAXOPS = 4 };
+
+// error flags in Ctl::err
+enum : uint32_t { ERR_CAPACITY = 1u, ERR_ITEMS = 2u, ERR_CORRUPT = 4u };
+
+// One device control block per context.  Counters are 64-bit.
+struct Ctl {
+    unsigned long long ring_head;   // next free-ring slot to pop
+    unsigned long long ring_tail;   // next free-ring slot to push
+    unsigned long long avail_end;   // pops in this pass must stay below this
+    unsigned int err;
+    unsigned int pass;              // pass counter (advanced by the select kernel)
+    unsigned int nsel;              // partitions selected for this pass
+    unsigned int pending_parts;     // partitions holding operations at select time
+    unsigned int nitems[NXCD];      // per-XCD work list lengths
+    unsigned int next[NXCD];        // per-XCD work list cursors
+    unsigned long long c_edges, c_improved, c_emitted, c_consumed, c_vpush, c_yields, c_chunks,
+        c_items, c_passes_nonempty, c_intra;
+    unsigned long long pending_ops; // operations buffered at select time
+};
+
+// A (partition, query) work item of one pass.
+struct Item {
+    uint32_t part;
+    uint32_t q;
+    int32_t head;    // first chunk of the detached buffer list (-1: none)
+    uint32_t count;  // operations in the list
+};
+
+struct GraphDev {
+    uint32_t nv, np, pshift, wbytes;
+    const uint32_t* rowptr;   // [nv+1]
+    const uint32_t* col;      // [ne]
+    const void* w;            // [ne] of wbytes (NULL if unweighted)
+    const uint32_t* pstart;   // [np+1]
+    const uint16_t* vpart;    // [(nv >> pshift) + 1] partition of each vertex block
+};
+
+struct QueryDev {
+    uint32_t nq, qc;          // queries in this wave, bucket stride (capacity)
+    const uint32_t* qtype;    // [qc]
+    const unsigned long long* qoff;  // [qc] word offset of the query's state
+    const float* qalpha;      // [qc]
+    const float* qeps;        // [qc]
+    const uint32_t* qmode;    // [qc]
+    uint32_t* state;          // state words; SSSP/BFS: int32[V]; PPR: p f32[V] then r f32[V]
+};
+
+struct BufDev {
+    int32_t* bhead;           // [np*qc] first chunk of the (partition, query) buffer
+    int32_t* btail;           // [np*qc] chunk with free slots (-1: none)
+    uint2* chunks;            // [nch*CH] (vertex, value) operations
+    int32_t* cnext;           // [nch]
+    uint32_t* ccount;         // [nch] slots reserved (valid ops = min(ccount, CH))
+    uint32_t* ring;           // [nch] free chunk ids
+    unsigned long long nch;
+    // partition summaries (maintained at emission, reset when a partition is scheduled)
+    uint32_t* pcount;         // [np] buffered ops
+    uint32_t* pbest_sp;       // [np] min buffered SSSP distance
+    uint32_t* pbest_lv;       // [np] min buffered BFS level
+    uint32_t* pbest_pr;       // [np] max buffered PPR residual mass (float bits)
+    uint32_t* pfirst;         // [np] pass of the oldest buffered op
+    uint32_t* plast;          // [np] pass of the last visit
+    uint32_t* pvisits;        // [np] visits
+    uint32_t* pn;             // [np] items of the partition in the current pass
+    uint32_t* sel;            // [max parts per pass] selected partitions
+    float* score;             // [np] learned score (LEARNED policy)
+    Item* items;              // [NXCD * item_cap]
+    uint32_t item_cap;
+    Ctl* ctl;
+};
+
+struct PassCfg {
+    uint32_t sched;
+    uint32_t kmax;            // partitions per pass
+    uint32_t win_sp, win_lv;  // batch window (SSSP, BFS)
+    uint32_t yld_sp, yld_lv;  // yield range H2 (0 = off)
+    float mu;                 // yield budget H1: mu * |E_P| / items_P (0 = off)
+    uint32_t seed;
+    uint32_t mixed;           // more than one query type in the wave
+};
+
+__host__ __device__ inline unsigned long long mix64(unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace fk

@@ -1,0 +1,758 @@
+// IntraPartProcess on gfx950: one workgroup processes one (partition, query)
+// work item at a time (Algorithm 2, the body of the parallel-for over the
+// queries of the scheduled partition).
+//
+// Mapping of the paper's cache design onto the MI355X:
+//   * the scheduled partition's edges are read from L2, shared by the
+//     workgroups of the XCD that process other queries of the same partition
+//     (the paper keeps the partition in the LLC shared by all cores);
+//   * the query's state slice for the partition (distances, or PPR
+//     residuals) is staged in LDS for the whole visit, so every relaxation
+//     inside the partition is an LDS atomic (the paper keeps the query's
+//     state in contiguous memory owned by one thread, Section 4.2);
+//   * one workgroup owns the slice, so no other workgroup touches it during
+//     the pass; lanes combine concurrent updates with LDS atomics.
+// Inside the visit, work is taken in priority order (Section 4.2): SSSP in
+// distance windows [lo, lo + win) smallest first (Dijkstra order, batched),
+// BFS level by level, PPR by pushing every vertex above its threshold.
+// Yielding (Section 5.1): heuristic 2 stops once the window start passes the
+// first value plus a range; heuristic 1 stops after an edge budget.  The
+// unfinished frontier is retained as operations in the partition's own buffer.
+// Operations for other partitions are staged in LDS, consolidated per target
+// vertex (min value / summed mass), grouped by target partition and appended
+// to the target buffers with one chunk reservation per flush (Algorithm 2:
+// send after processing; Appendix B.1: reserve a range, then copy).
+#include "fork_util.h"
+
+namespace fk {
+
+constexpr int NT = 512;           // threads per workgroup
+constexpr int NW = NT / WAVE;     // waves per workgroup
+constexpr int FCAP = 2048;        // frontier capacity (two buffers)
+constexpr int BCAP = 1024;        // vertices expanded per batch
+constexpr int SCAP = 1024;        // staged outgoing operations
+constexpr int CCAP = 256;         // chunk ids gathered per consume round
+constexpr int SE = (SCAP + NT - 1) / NT;
+
+struct PassShared {
+    uint32_t fq[2][FCAP];         // frontier (partition-local ids), double-buffered
+    uint32_t bv[BCAP];            // batch vertex
+    uint32_t bval[BCAP];          // batch distance, or PPR share (float bits)
+    uint32_t brow[BCAP];          // batch first edge
+    uint32_t bpre[BCAP];          // batch exclusive degree prefix
+    unsigned long long sk[SCAP];  // staged ops (vertex << 32 | value)
+    uint32_t tp[SCAP];            // target partition of compacted staged op
+    int32_t rt[SCAP];             // per run: tail chunk (-1: none)
+    uint32_t rp[SCAP];            // per run: slot | taken << 9 | fresh-chunk base << 18
+    int32_t clist[CCAP];          // chunk ids of the consume round
+    uint32_t wred[NW];
+    uint32_t nf, nk, nb, ns, ncl, cur;
+    int32_t chnext;
+    unsigned long long base;
+    Item it;
+};
+
+// -------------------------------------------------------- block helpers
+
+// Exclusive prefix sum over the block; *total gets the sum.
+__device__ __forceinline__ uint32_t block_excl(PassShared& S, uint32_t v, uint32_t* total) {
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t incl = wscan_incl(v, lane);
+    if (lane == 63) S.wred[wid] = incl;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        uint32_t x = S.wred[w];
+        before += (w < (int)wid) ? x : 0u;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+__device__ __forceinline__ uint32_t block_min(PassShared& S, uint32_t v) {
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wmin(v);
+    if (lane == 0) S.wred[wid] = v;
+    __syncthreads();
+    uint32_t r = S.wred[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) r = S.wred[w] < r ? S.wred[w] : r;
+    __syncthreads();
+    return r;
+}
+
+// Exclusive max-scan over the block (0 for thread 0).
+__device__ __forceinline__ uint32_t block_max_excl(PassShared& S, uint32_t v) {
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t incl = wscan_max_incl(v, lane);
+    if (lane == 63) S.wred[wid] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+        if (w < (int)wid) before = S.wred[w] > before ? S.wred[w] : before;
+    __syncthreads();
+    uint32_t ex = __shfl_up(incl, 1);
+    if (lane == 0) ex = 0;
+    return ex > before ? ex : before;
+}
+
+// Position in an LDS list for lanes with `want` (one LDS atomic per wave).
+__device__ __forceinline__ uint32_t block_append(bool want, uint32_t* counter) {
+    unsigned long long mask = wballot(want);
+    uint32_t n = __popcll(mask);
+    uint32_t base = 0;
+    if ((threadIdx.x & 63) == 0 && n) base = atomicAdd(counter, n);
+    base = __shfl(base, 0);
+    return base + rank_in(mask);
+}
+
+__device__ __forceinline__ bool tas(uint32_t* bits, uint32_t v) {
+    uint32_t bit = 1u << (v & 31);
+    return !(atomicOr(&bits[v >> 5], bit) & bit);
+}
+
+struct ItemCtx {
+    GraphDev g;
+    QueryDev Q;
+    BufDev B;
+    uint32_t P, q, qt, v0, nvp, pass, mode;
+    float alpha, eps;
+    uint32_t* gstate;   // global state of the query (dist, or r for PPR)
+    float* gp;          // PPR p
+    uint32_t* st;       // LDS slice
+    uint32_t* bits;     // LDS in-frontier flags
+    // per-thread counters
+    unsigned long long c_edges, c_intra, c_improved, c_emitted, c_consumed, c_vpush, c_chunks;
+};
+
+__device__ __forceinline__ float thr_of(const ItemCtx& c, uint32_t gv) {
+    if (!c.mode) return c.eps;
+    return c.eps * (float)(c.g.rowptr[gv + 1] - c.g.rowptr[gv]);
+}
+
+// ------------------------------------------------------------ flush
+// Send the staged operations (block-collective; call with uniform control flow).
+__device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
+    __syncthreads();
+    const uint32_t ns = S.ns;
+    if (ns == 0) return;
+    const uint32_t t = threadIdx.x;
+    uint32_t N = 2;
+    while (N < ns) N <<= 1;
+    for (uint32_t i = ns + t; i < N; i += NT) S.sk[i] = ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= N; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t x = t; x < N / 2; x += NT) {
+                uint32_t i = ((x & ~(j - 1)) << 1) | (x & (j - 1));
+                uint32_t l = i + j;
+                bool up = (i & k) == 0;
+                unsigned long long a = S.sk[i], b = S.sk[l];
+                if ((a > b) == up) { S.sk[i] = b; S.sk[l] = a; }
+            }
+            __syncthreads();
+        }
+    }
+    const bool is_ppr = c.qt == Q_PPR;
+    // consolidate equal target vertices; thread owns elements [t*SE, t*SE+SE)
+    unsigned long long key[SE];
+    bool kept[SE];
+    uint32_t nk_l = 0;
+#pragma unroll
+    for (int k = 0; k < SE; ++k) {
+        uint32_t i = t * SE + k;
+        kept[k] = false;
+        key[k] = 0;
+        if (i < ns) {
+            unsigned long long s = S.sk[i];
+            uint32_t u = (uint32_t)(s >> 32);
+            if (i == 0 || (uint32_t)(S.sk[i - 1] >> 32) != u) {
+                if (is_ppr) {
+                    float acc = __uint_as_float((uint32_t)s);
+                    for (uint32_t j = i + 1; j < ns && (uint32_t)(S.sk[j] >> 32) == u; ++j)
+                        acc += __uint_as_float((uint32_t)S.sk[j]);
+                    s = ((unsigned long long)u << 32) | __float_as_uint(acc);
+                }
+                kept[k] = true;
+                key[k] = s;
+                ++nk_l;
+            }
+        }
+    }
+    uint32_t nk = 0;
+    uint32_t pos = block_excl(S, nk_l, &nk);  // has barriers: all reads above are done
+#pragma unroll
+    for (int k = 0; k < SE; ++k) {
+        if (kept[k]) {
+            uint32_t u = (uint32_t)(key[k] >> 32);
+            S.sk[pos] = key[k];
+            S.tp[pos] = c.g.vpart[u >> c.g.pshift];
+            ++pos;
+        }
+    }
+    __syncthreads();
+    // runs of equal target partition; the thread holding a run's last element owns it
+    const uint32_t lo = t * SE, hi = (lo + SE < nk) ? lo + SE : nk;
+    uint32_t rsmax = 0;
+    for (uint32_t i = lo; i < hi; ++i)
+        if (i == 0 || S.tp[i] != S.tp[i - 1]) rsmax = i;
+    // start of the run still open where my block begins
+    const uint32_t rstart_prev = block_max_excl(S, rsmax);
+    // owners: reserve in the tail chunk, count fresh chunks
+    uint32_t need_l = 0;
+    {
+        uint32_t rsv = rstart_prev;
+        for (uint32_t i = lo; i < hi; ++i) {
+            uint32_t T = S.tp[i];
+            if (i == 0 || T != S.tp[i - 1]) rsv = i;
+            bool end = (i + 1 == nk) || (S.tp[i + 1] != T);
+            if (!end) continue;
+            uint32_t len = i - rsv + 1;
+            unsigned long long b = (unsigned long long)T * c.Q.qc + c.q;
+            int32_t tl = __hip_atomic_load(&c.B.btail[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t s = CH, kk = 0;
+            if (tl >= 0) {
+                s = dev_add(&c.B.ccount[tl], len);
+                if (s < (uint32_t)CH) kk = ((uint32_t)CH - s) < len ? ((uint32_t)CH - s) : len;
+                else s = CH;
+            }
+            S.rt[rsv] = tl;
+            S.rp[rsv] = s | (kk << 9) | (need_l << 18);
+            need_l += (len - kk + CH - 1) / CH;
+        }
+    }
+    uint32_t nnew = 0;
+    uint32_t my_base = block_excl(S, need_l, &nnew);
+    if (need_l) {
+        uint32_t rsv = rstart_prev;
+        for (uint32_t i = lo; i < hi; ++i) {
+            uint32_t T = S.tp[i];
+            if (i == 0 || T != S.tp[i - 1]) rsv = i;
+            bool end = (i + 1 == nk) || (S.tp[i + 1] != T);
+            if (end) S.rp[rsv] += my_base << 18;
+        }
+    }
+    if (t == 0) {
+        unsigned long long base = 0;
+        if (nnew) {
+            base = dev_add(&c.B.ctl->ring_head, (unsigned long long)nnew);
+            if (base + nnew > c.B.ctl->avail_end) {
+                dev_or(&c.B.ctl->err, (uint32_t)ERR_CAPACITY);
+                base = ~0ull;
+            }
+        }
+        S.base = base;
+    }
+    __syncthreads();
+    const unsigned long long base = S.base;
+    if (base == ~0ull) {
+        if (t == 0) S.ns = 0;
+        __syncthreads();
+        return;
+    }
+    const unsigned long long nch = c.B.nch;
+    // every element writes its operation
+    {
+        uint32_t rsv = rstart_prev;
+        for (uint32_t i = lo; i < hi; ++i) {
+            if (i == 0 || S.tp[i] != S.tp[i - 1]) rsv = i;
+            uint32_t off = i - rsv;
+            uint32_t info = S.rp[rsv];
+            uint32_t s = info & 0x1ffu, kk = (info >> 9) & 0x1ffu, cb = info >> 18;
+            unsigned long long sv = S.sk[i];
+            uint2 op = make_uint2((uint32_t)(sv >> 32), (uint32_t)sv);
+            if (off < kk) {
+                c.B.chunks[(unsigned long long)(uint32_t)S.rt[rsv] * CH + s + off] = op;
+            } else {
+                uint32_t j = (off - kk) / CH;
+                uint32_t ch = c.B.ring[(base + cb + j) % nch];
+                c.B.chunks[(unsigned long long)ch * CH + (off - kk) % CH] = op;
+            }
+        }
+    }
+    // owners link fresh chunks, publish the new tail, update partition summaries
+    {
+        uint32_t rsv = rstart_prev;
+        for (uint32_t i = lo; i < hi; ++i) {
+            uint32_t T = S.tp[i];
+            if (i == 0 || T != S.tp[i - 1]) rsv = i;
+            bool end = (i + 1 == nk) || (S.tp[i + 1] != T);
+            if (!end) continue;
+            uint32_t len = i - rsv + 1;
+            uint32_t info = S.rp[rsv];
+            uint32_t kk = (info >> 9) & 0x1ffu, cb = info >> 18;
+            uint32_t need = (len - kk + CH - 1) / CH;
+            unsigned long long b = (unsigned long long)T * c.Q.qc + c.q;
+            if (need) {
+                uint32_t first = c.B.ring[(base + cb) % nch];
+                uint32_t prev = first;
+                for (uint32_t j = 0; j < need; ++j) {
+                    uint32_t ch = j ? c.B.ring[(base + cb + j) % nch] : first;
+                    if (j) c.B.cnext[prev] = (int32_t)ch;
+                    uint32_t fill = (j + 1 < need) ? (uint32_t)CH : (len - kk) - j * CH;
+                    uint32_t r0 = dev_add(&c.B.ccount[ch], fill);
+                    if (j + 1 == need) {
+                        int32_t old = dev_xchg(&c.B.bhead[b], (int32_t)first);
+                        c.B.cnext[ch] = old;
+                        // publish the tail only after its slots are reserved
+                        if (r0 == 0) dev_xchg(&c.B.btail[b], (int32_t)ch);
+                        else dev_or(&c.B.ctl->err, (uint32_t)ERR_CORRUPT);
+                    }
+                    prev = ch;
+                }
+            }
+            dev_add(&c.B.pcount[T], len);
+            dev_min(&c.B.pfirst[T], c.pass);
+            if (!is_ppr) {
+                uint32_t mn = INF;
+                for (uint32_t j = rsv; j <= i; ++j) {
+                    uint32_t v = (uint32_t)S.sk[j] & ~RETAIN;
+                    mn = v < mn ? v : mn;
+                }
+                dev_min(c.qt == Q_BFS ? &c.B.pbest_lv[T] : &c.B.pbest_sp[T], mn);
+            } else {
+                float mx = 0.f;
+                for (uint32_t j = rsv; j <= i; ++j) {
+                    float f = __uint_as_float((uint32_t)S.sk[j]);
+                    mx = f > mx ? f : mx;
+                }
+                dev_max(&c.B.pbest_pr[T], __float_as_uint(mx));
+            }
+            c.c_emitted += len;
+        }
+    }
+    if (t == 0) {
+        c.c_chunks += nnew;
+        S.ns = 0;
+    }
+    __syncthreads();
+}
+
+// Make room for one staged op per thread (block-collective).
+__device__ __forceinline__ void stage_room(ItemCtx& c, PassShared& S) {
+    __syncthreads();
+    if (S.ns + NT > SCAP) flush(c, S);
+}
+
+__device__ __forceinline__ void stage(PassShared& S, bool want, uint32_t u, uint32_t val) {
+    uint32_t p = block_append(want, &S.ns);
+    if (want) S.sk[p] = ((unsigned long long)u << 32) | val;
+}
+
+// Add activated vertices to the frontier buffer `cur`; beyond its capacity
+// they are retained as operations (requires stage room for them).
+__device__ __forceinline__ void push_frontier(ItemCtx& c, PassShared& S, uint32_t cur, bool want, uint32_t vloc,
+                                              uint32_t retain_val) {
+    uint32_t p = block_append(want, &S.nf);
+    bool fits = want && p < (uint32_t)FCAP;
+    if (fits) S.fq[cur][p] = vloc;
+    stage(S, want && !fits, c.v0 + vloc, retain_val);
+}
+
+// ------------------------------------------------------------ consume
+// Apply the work item's buffered operations to the LDS slice (consolidation
+// of the buffer into the query's state) and free the chunks.
+__device__ __forceinline__ void consume(ItemCtx& c, PassShared& S, int32_t head) {
+    const uint32_t t = threadIdx.x;
+    if (t == 0) { S.chnext = head; }
+    __syncthreads();
+    while (true) {
+        if (t == 0) {
+            int32_t ch = S.chnext;
+            uint32_t n = 0;
+            while (ch >= 0 && n < (uint32_t)CCAP) {
+                S.clist[n++] = ch;
+                ch = c.B.cnext[ch];
+            }
+            S.ncl = n;
+            S.chnext = ch;
+        }
+        __syncthreads();
+        const uint32_t ncl = S.ncl;
+        if (ncl == 0) break;
+        const uint32_t slots = ncl * CH;
+        for (uint32_t s0 = 0; s0 < slots; s0 += NT) {
+            stage_room(c, S);
+            const uint32_t cur = S.cur;
+            uint32_t s = s0 + t;
+            bool valid = false;
+            uint2 op = make_uint2(0, 0);
+            if (s < slots) {
+                uint32_t ch = (uint32_t)S.clist[s / CH];
+                uint32_t cnt = c.B.ccount[ch];
+                cnt = cnt < (uint32_t)CH ? cnt : (uint32_t)CH;
+                if (s % CH < cnt) {
+                    op = c.B.chunks[(unsigned long long)ch * CH + s % CH];
+                    valid = true;
+                }
+            }
+            uint32_t vloc = op.x - c.v0;
+            if (valid && vloc >= c.nvp) {
+                dev_or(&c.B.ctl->err, (uint32_t)ERR_CORRUPT);
+                valid = false;
+            }
+            bool act = false;
+            uint32_t rv = 0;
+            if (valid) {
+                ++c.c_consumed;
+                if (c.qt == Q_PPR) {
+                    float mass = __uint_as_float(op.y);
+                    float nr = atomicAdd((float*)&c.st[vloc], mass) + mass;
+                    act = ppr_active(nr, thr_of(c, op.x));
+                } else {
+                    uint32_t val = op.y & ~RETAIN;
+                    uint32_t old = atomicMin(&c.st[vloc], val);
+                    bool imp = val < old;
+                    c.c_improved += imp;
+                    act = imp || (op.y & RETAIN);
+                    rv = (imp ? val : old) | RETAIN;
+                }
+            }
+            bool win = act && tas(c.bits, vloc);
+            push_frontier(c, S, cur, win, vloc, rv);
+        }
+        __syncthreads();
+        // free this round's chunks
+        if (t == 0) S.base = dev_add(&c.B.ctl->ring_tail, (unsigned long long)ncl);
+        __syncthreads();
+        for (uint32_t i = t; i < ncl; i += NT) {
+            uint32_t ch = (uint32_t)S.clist[i];
+            c.B.ccount[ch] = 0;
+            c.B.ring[(S.base + i) % c.B.nch] = ch;
+        }
+        __syncthreads();
+    }
+    if (t == 0 && S.nf > (uint32_t)FCAP) S.nf = FCAP;
+    __syncthreads();
+}
+
+// Split the frontier: vertices with value < hi (all for PPR) go to the
+// batch (up to BCAP), the rest stay in the other frontier buffer.
+__device__ __forceinline__ uint32_t extract(ItemCtx& c, PassShared& S, uint32_t hi, bool by_value) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t cur = S.cur, nf = S.nf;
+    __syncthreads();
+    if (t == 0) { S.nb = 0; S.nk = 0; }
+    __syncthreads();
+    for (uint32_t i0 = 0; i0 < nf; i0 += NT) {
+        uint32_t i = i0 + t;
+        bool valid = i < nf;
+        uint32_t v = valid ? S.fq[cur][i] : 0u;
+        bool take = valid && (!by_value || c.st[v] < hi);
+        uint32_t p = block_append(take, &S.nb);
+        bool tk = take && p < (uint32_t)BCAP;
+        if (tk) S.bv[p] = v;
+        bool keep = valid && !tk;
+        uint32_t kp = block_append(keep, &S.nk);
+        if (keep) S.fq[cur ^ 1][kp] = v;
+    }
+    __syncthreads();
+    uint32_t nb = S.nb < (uint32_t)BCAP ? S.nb : (uint32_t)BCAP;
+    __syncthreads();
+    if (t == 0) { S.nf = S.nk; S.cur = cur ^ 1; S.nb = nb; }
+    __syncthreads();
+    return nb;
+}
+
+// Exclusive prefix of the batch degrees (in bpre) -> returns total edges.
+__device__ __forceinline__ uint32_t batch_scan(PassShared& S, uint32_t nb) {
+    constexpr uint32_t PE = BCAP / NT;
+    const uint32_t t = threadIdx.x;
+    uint32_t d[PE];
+    uint32_t s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < PE; ++k) {
+        uint32_t j = t * PE + k;
+        d[k] = j < nb ? S.bpre[j] : 0u;
+        s += d[k];
+    }
+    uint32_t total = 0;
+    uint32_t run = block_excl(S, s, &total);
+#pragma unroll
+    for (uint32_t k = 0; k < PE; ++k) {
+        uint32_t j = t * PE + k;
+        if (j < nb) S.bpre[j] = run;
+        run += d[k];
+    }
+    __syncthreads();
+    return total;
+}
+
+__device__ __forceinline__ uint32_t find_b(const PassShared& S, uint32_t nb, uint32_t j) {
+    uint32_t lo = 0, hi = nb;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (S.bpre[mid] <= j) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------ SSSP / BFS
+template <int WB>
+__device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win, uint32_t yld, uint32_t budget) {
+    const uint32_t t = threadIdx.x;
+    uint32_t first_lo = INF;
+    unsigned long long edges = 0;
+    while (true) {
+        __syncthreads();
+        const uint32_t nf = S.nf;
+        if (nf == 0) break;
+        uint32_t lo = INF;
+        for (uint32_t i = t; i < nf; i += NT) { uint32_t d = c.st[S.fq[S.cur][i]]; lo = d < lo ? d : lo; }
+        lo = block_min(S, lo);
+        if (first_lo == INF) first_lo = lo;
+        if ((yld && (unsigned long long)lo >= (unsigned long long)first_lo + yld) || (budget && edges >= budget)) break;
+        uint32_t hi = lo + win;
+        if (hi < lo || hi > INF) hi = INF;
+        const uint32_t nb = extract(c, S, hi, true);
+        for (uint32_t j = t; j < nb; j += NT) {
+            uint32_t v = S.bv[j];
+            atomicAnd(&c.bits[v >> 5], ~(1u << (v & 31)));
+            uint32_t gv = c.v0 + v;
+            uint32_t r0 = c.g.rowptr[gv], r1 = c.g.rowptr[gv + 1];
+            S.bval[j] = c.st[v];
+            S.brow[j] = r0;
+            S.bpre[j] = r1 - r0;
+        }
+        __syncthreads();
+        if (t == 0) c.c_vpush += nb;
+        const uint32_t total = batch_scan(S, nb);
+        edges += total;
+        for (uint32_t k0 = 0; k0 < total; k0 += NT) {
+            stage_room(c, S);
+            const uint32_t cur = S.cur;
+            uint32_t j = k0 + t;
+            bool valid = j < total;
+            uint32_t u = 0, nd = 0;
+            if (valid) {
+                uint32_t b = find_b(S, nb, j);
+                uint32_t e = S.brow[b] + (j - S.bpre[b]);
+                u = c.g.col[e];
+                unsigned long long sum = (unsigned long long)S.bval[b] + edge_w<WB>(c.g.w, e);
+                nd = sum >= INF ? INF - 1 : (uint32_t)sum;
+            }
+            uint32_t ul = u - c.v0;
+            bool intra = valid && ul < c.nvp;
+            bool win_ = false;
+            if (intra) {
+                ++c.c_intra;
+                uint32_t old = atomicMin(&c.st[ul], nd);
+                if (nd < old) { ++c.c_improved; win_ = tas(c.bits, ul); }
+            }
+            push_frontier(c, S, cur, win_, ul, nd | RETAIN);
+            stage(S, valid && !intra, u, nd);
+        }
+        __syncthreads();
+        if (t == 0 && S.nf > (uint32_t)FCAP) S.nf = FCAP;
+    }
+    // retain the unprocessed frontier in the partition's own buffer
+    __syncthreads();
+    const uint32_t nf = S.nf;
+    if (nf) {
+        const uint32_t cur = S.cur;
+        for (uint32_t i0 = 0; i0 < nf; i0 += NT) {
+            stage_room(c, S);
+            uint32_t i = i0 + t;
+            bool valid = i < nf;
+            uint32_t v = valid ? S.fq[cur][i] : 0u;
+            stage(S, valid, c.v0 + v, valid ? (c.st[v] | RETAIN) : 0u);
+        }
+        __syncthreads();
+        if (t == 0) { S.nf = 0; dev_add(&c.B.ctl->c_yields, 1ull); }
+    }
+    if (t == 0) c.c_edges += edges;
+}
+
+// ------------------------------------------------------------ PPR
+__device__ __forceinline__ void ppr_visit(ItemCtx& c, PassShared& S, uint32_t budget) {
+    const uint32_t t = threadIdx.x;
+    unsigned long long edges = 0;
+    const float a = c.alpha;
+    while (true) {
+        __syncthreads();
+        if (S.nf == 0) break;
+        if (budget && edges >= budget) break;
+        const uint32_t nb = extract(c, S, ~0u, false);
+        uint32_t pushed = 0;
+        for (uint32_t j = t; j < nb; j += NT) {
+            uint32_t v = S.bv[j];
+            atomicAnd(&c.bits[v >> 5], ~(1u << (v & 31)));
+            uint32_t gv = c.v0 + v;
+            uint32_t r0 = c.g.rowptr[gv], r1 = c.g.rowptr[gv + 1];
+            uint32_t deg = r1 - r0;
+            float thr = c.mode ? c.eps * (float)deg : c.eps;
+            float mass = __uint_as_float(c.st[v]);
+            uint32_t push_deg = 0;
+            float share = 0.f;
+            if (ppr_active(mass, thr)) {
+                c.st[v] = 0u;
+                atomicAdd(&c.gp[gv], a * mass);
+                ++pushed;
+                if (deg) { share = (1.f - a) * mass / (float)deg; push_deg = deg; }
+            }
+            S.bval[j] = __float_as_uint(share);
+            S.brow[j] = r0;
+            S.bpre[j] = push_deg;
+        }
+        c.c_vpush += pushed;
+        __syncthreads();
+        const uint32_t total = batch_scan(S, nb);
+        edges += total;
+        for (uint32_t k0 = 0; k0 < total; k0 += NT) {
+            stage_room(c, S);
+            const uint32_t cur = S.cur;
+            uint32_t j = k0 + t;
+            bool valid = j < total;
+            uint32_t u = 0;
+            float share = 0.f;
+            if (valid) {
+                uint32_t b = find_b(S, nb, j);
+                uint32_t e = S.brow[b] + (j - S.bpre[b]);
+                u = c.g.col[e];
+                share = __uint_as_float(S.bval[b]);
+            }
+            uint32_t ul = u - c.v0;
+            bool intra = valid && ul < c.nvp;
+            bool win_ = false;
+            if (intra) {
+                ++c.c_intra;
+                float old = atomicAdd((float*)&c.st[ul], share);
+                float nr = old + share;
+                float thr = thr_of(c, u);
+                if (ppr_active(nr, thr) && !ppr_active(old, thr)) win_ = tas(c.bits, ul);
+            }
+            push_frontier(c, S, cur, win_, ul, 0u);
+            stage(S, valid && !intra, u, __float_as_uint(share));
+        }
+        __syncthreads();
+        if (t == 0 && S.nf > (uint32_t)FCAP) S.nf = FCAP;
+    }
+    __syncthreads();
+    const uint32_t nf = S.nf;
+    if (nf) {
+        const uint32_t cur = S.cur;
+        for (uint32_t i0 = 0; i0 < nf; i0 += NT) {
+            stage_room(c, S);
+            uint32_t i = i0 + t;
+            bool valid = i < nf;
+            stage(S, valid, valid ? c.v0 + S.fq[cur][i] : 0u, 0u);
+        }
+        __syncthreads();
+        if (t == 0) { S.nf = 0; dev_add(&c.B.ctl->c_yields, 1ull); }
+    }
+    if (t == 0) c.c_edges += edges;
+}
+
+// ------------------------------------------------------------ kernel
+template <int WB>
+__global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B, PassCfg cfg, uint32_t slice_words) {
+    __shared__ PassShared S;
+    extern __shared__ uint32_t dyn[];
+    const uint32_t t = threadIdx.x;
+    ItemCtx c;
+    c.g = g;
+    c.Q = Q;
+    c.B = B;
+    c.st = dyn;
+    c.bits = dyn + slice_words;
+    c.pass = B.ctl->pass;
+    c.c_edges = c.c_intra = c.c_improved = c.c_emitted = c.c_consumed = c.c_vpush = c.c_chunks = 0;
+    unsigned long long items = 0;
+    const uint32_t xcd = blockIdx.x % NXCD;
+    for (;;) {
+        if (t == 0) {
+            Item it;
+            it.part = ~0u;
+            if (!__hip_atomic_load(&B.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                for (uint32_t k = 0; k < NXCD; ++k) {
+                    uint32_t x = (xcd + k) % NXCD;
+                    uint32_t n = B.ctl->nitems[x];
+                    n = n < B.item_cap ? n : B.item_cap;
+                    if (__hip_atomic_load(&B.ctl->next[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) continue;
+                    uint32_t idx = dev_add(&B.ctl->next[x], 1u);
+                    if (idx < n) { it = B.items[(unsigned long long)x * B.item_cap + idx]; break; }
+                }
+            }
+            S.it = it;
+        }
+        __syncthreads();
+        const Item it = S.it;
+        if (it.part == ~0u) break;
+        ++items;
+        c.P = it.part;
+        c.q = it.q;
+        c.v0 = g.pstart[c.P];
+        c.nvp = g.pstart[c.P + 1] - c.v0;
+        c.qt = Q.qtype[c.q];
+        const unsigned long long off = Q.qoff[c.q];
+        c.alpha = Q.qalpha[c.q];
+        c.eps = Q.qeps[c.q];
+        c.mode = Q.qmode[c.q];
+        const bool ppr = c.qt == Q_PPR;
+        c.gp = (float*)(Q.state + off);
+        c.gstate = ppr ? Q.state + off + g.nv : Q.state + off;
+        // stage the slice into LDS
+        for (uint32_t i = t; i < c.nvp; i += NT) c.st[i] = c.gstate[c.v0 + i];
+        for (uint32_t i = t; i < (c.nvp + 31) / 32; i += NT) c.bits[i] = 0u;
+        if (t == 0) { S.nf = 0; S.ns = 0; S.cur = 0; }
+        __syncthreads();
+        uint32_t budget = 0;
+        if (cfg.mu > 0.f) {
+            uint32_t np_items = B.pn[c.P];
+            float e_p = (float)(g.rowptr[c.v0 + c.nvp] - g.rowptr[c.v0]);
+            float bgt = cfg.mu * e_p / (float)(np_items ? np_items : 1u);
+            budget = bgt < 256.f ? 256u : (bgt > 4.0e9f ? 4000000000u : (uint32_t)bgt);
+        }
+        consume(c, S, it.head);
+        if (ppr) ppr_visit(c, S, budget);
+        else if (c.qt == Q_BFS) sp_visit<0>(c, S, cfg.win_lv, cfg.yld_lv, budget);
+        else sp_visit<WB>(c, S, cfg.win_sp, cfg.yld_sp, budget);
+        flush(c, S);
+        // write the slice back
+        for (uint32_t i = t; i < c.nvp; i += NT) c.gstate[c.v0 + i] = c.st[i];
+        __syncthreads();
+    }
+    // publish counters (block reduction, then one atomic per counter)
+    unsigned long long v[7] = {c.c_edges, c.c_intra, c.c_improved, c.c_emitted, c.c_consumed, c.c_vpush, c.c_chunks};
+    unsigned long long* dst[7] = {&B.ctl->c_edges, &B.ctl->c_intra, &B.ctl->c_improved, &B.ctl->c_emitted,
+                                  &B.ctl->c_consumed, &B.ctl->c_vpush, &B.ctl->c_chunks};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        unsigned long long x = v[k];
+#pragma unroll
+        for (int o = 32; o; o >>= 1) x += __shfl_xor(x, o);
+        if ((t & 63) == 0 && x) dev_add(dst[k], x);
+    }
+    if (t == 0 && items) dev_add(&B.ctl->c_items, items);
+}
+
+size_t process_dyn_lds(uint32_t vpmax) { return ((size_t)vpmax + (vpmax + 31) / 32) * 4; }
+
+hipError_t launch_process(const GraphDev& g, const QueryDev& Q, const BufDev& B, const PassCfg& cfg,
+                          uint32_t blocks, uint32_t vpmax, hipStream_t s) {
+    size_t dyn = process_dyn_lds(vpmax);
+    switch (g.wbytes) {
+    case 0: hipLaunchKernelGGL((k_process<0>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax); break;
+    case 1: hipLaunchKernelGGL((k_process<1>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax); break;
+    case 2: hipLaunchKernelGGL((k_process<2>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax); break;
+    default: hipLaunchKernelGGL((k_process<4>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax); break;
+    }
+    return hipGetLastError();
+}
+
+const void* process_kernel_ptr(int wbytes) {
+    switch (wbytes) {
+    case 0: return (const void*)k_process<0>;
+    case 1: return (const void*)k_process<1>;
+    case 2: return (const void*)k_process<2>;
+    default: return (const void*)k_process<4>;
+    }
+}
+int process_threads() { return NT; }
+size_t process_static_lds() { return sizeof(PassShared); }
+
+}  // namespace fk

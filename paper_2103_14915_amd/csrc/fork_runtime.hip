@@ -1,0 +1,696 @@
+// Host runtime of the fork-processing library: graph ingest and partition
+// plan, query waves, the pass loop of Algorithm 2, results and digests.
+// Everything behind the C ABI of include/fork.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cmath>
+#include <cstdio>
+#include <cstdarg>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fork.h"
+#include "fork_dev.h"
+
+namespace fk {
+hipError_t launch_select(const GraphDev&, const BufDev&, const PassCfg&, hipStream_t);
+hipError_t launch_worklist(const BufDev&, const QueryDev&, uint32_t, hipStream_t);
+hipError_t launch_process(const GraphDev&, const QueryDev&, const BufDev&, const PassCfg&, uint32_t, uint32_t, hipStream_t);
+size_t process_dyn_lds(uint32_t vpmax);
+int process_threads();
+hipError_t launch_ring_init(uint32_t*, unsigned long long, hipStream_t);
+hipError_t launch_seed(const GraphDev&, const QueryDev&, const BufDev&, const uint32_t*, hipStream_t);
+hipError_t launch_digest(const QueryDev&, uint32_t, unsigned long long*, hipStream_t);
+hipError_t launch_mlp_score(const GraphDev&, const BufDev&, const float*, float*, float*, void*, uint32_t, hipStream_t);
+size_t gstat_bytes();
+const void* process_kernel_ptr(int wbytes);
+}  // namespace fk
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(FORK_E_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                                \
+    } while (0)
+
+struct QueryRec {
+    uint32_t type, src, mode;
+    float alpha, eps;
+};
+
+struct fork_ctx {
+    int device = 0;
+    uint32_t nv = 0;
+    uint64_t ne = 0;
+    int wbytes = 0;
+    uint32_t np = 0, pshift = 0;
+    std::vector<uint32_t> h_pstart;
+    std::vector<uint32_t> h_rowptr;  // host copy (partition planning, statistics)
+    // graph
+    uint32_t* d_rowptr = nullptr;
+    uint32_t* d_col = nullptr;
+    void* d_w = nullptr;
+    uint32_t* d_pstart = nullptr;
+    uint16_t* d_vpart = nullptr;
+    // operation pool
+    unsigned long long nch = 0;
+    uint2* d_chunks = nullptr;
+    int32_t* d_cnext = nullptr;
+    uint32_t* d_ccount = nullptr;
+    uint32_t* d_ring = nullptr;
+    // partition summaries
+    uint32_t *d_pcount = nullptr, *d_pbest_sp = nullptr, *d_pbest_lv = nullptr, *d_pbest_pr = nullptr,
+             *d_pfirst = nullptr, *d_plast = nullptr, *d_pvisits = nullptr, *d_pn = nullptr,
+             *d_sel = nullptr;
+    float* d_score = nullptr;
+    float* d_mlp = nullptr;
+    unsigned char* d_gstat = nullptr;
+    fk::Ctl* d_ctl = nullptr;
+    fk::Ctl* h_ctl = nullptr;  // pinned
+    // queries
+    std::vector<QueryRec> queries;
+    uint32_t max_queries = 0;
+    // wave buffers (sized for the largest wave)
+    uint32_t qcap = 0;           // bucket stride
+    size_t state_words_cap = 0;
+    uint32_t* d_state = nullptr;
+    int32_t* d_bhead = nullptr;
+    int32_t* d_btail = nullptr;
+    fk::Item* d_items = nullptr;
+    uint32_t item_cap = 0, kmax_cap = 0;
+    uint32_t *d_qtype = nullptr, *d_qsrc = nullptr, *d_qmode = nullptr;
+    unsigned long long* d_qoff = nullptr;
+    float *d_qalpha = nullptr, *d_qeps = nullptr;
+    unsigned long long* d_digest = nullptr;
+    // results
+    std::vector<fork_digest> digests;
+    bool ran = false;
+    uint32_t res_first = 0, res_n = 0;
+    std::vector<unsigned long long> res_off;
+    fork_stats_t stats{};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> pev;  // pass-kernel timing events (profile mode)
+    int blocks_per_cu = 1, num_cu = 1;
+    uint32_t vpmax = 1;  // largest partition (vertices)
+};
+
+extern "C" const char* fork_last_error(void) { return g_err.c_str(); }
+
+template <class T> static int dalloc(T** p, size_t n) {
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(FORK_E_NOMEM, "hipMalloc(%zu bytes) failed: %s", n * sizeof(T), hipGetErrorString(e));
+    }
+    return FORK_OK;
+}
+#define ALLOC(p, n)                       \
+    do {                                  \
+        int rc_ = dalloc(&(p), (n));      \
+        if (rc_) return rc_;              \
+    } while (0)
+
+static void free_wave(fork_ctx* c) {
+    hipFree(c->d_state); c->d_state = nullptr;
+    hipFree(c->d_bhead); c->d_bhead = nullptr;
+    hipFree(c->d_btail); c->d_btail = nullptr;
+    hipFree(c->d_items); c->d_items = nullptr;
+    hipFree(c->d_qtype); c->d_qtype = nullptr;
+    hipFree(c->d_qsrc); c->d_qsrc = nullptr;
+    hipFree(c->d_qmode); c->d_qmode = nullptr;
+    hipFree(c->d_qoff); c->d_qoff = nullptr;
+    hipFree(c->d_qalpha); c->d_qalpha = nullptr;
+    hipFree(c->d_qeps); c->d_qeps = nullptr;
+    hipFree(c->d_digest); c->d_digest = nullptr;
+    c->qcap = 0;
+    c->state_words_cap = 0;
+    c->kmax_cap = 0;
+}
+
+extern "C" void fork_destroy(fork_ctx* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    free_wave(c);
+    void* ptrs[] = {c->d_rowptr, c->d_col, c->d_w, c->d_pstart, c->d_vpart, c->d_chunks, c->d_cnext,
+                    c->d_ccount, c->d_ring, c->d_pcount, c->d_pbest_sp, c->d_pbest_lv, c->d_pbest_pr,
+                    c->d_pfirst, c->d_plast, c->d_pvisits, c->d_pn, c->d_sel, c->d_score, c->d_mlp,
+                    c->d_ctl, c->d_gstat};
+    for (void* p : ptrs) if (p) hipFree(p);
+    if (c->h_ctl) hipHostFree(c->h_ctl);
+    for (auto& e : c->ev) if (e) hipEventDestroy(e);
+    for (auto& e : c->pev) if (e) hipEventDestroy(e);
+    delete c;
+}
+
+// Partition plan (Definition 2.1): contiguous vertex ranges, boundaries on
+// multiples of 2^pshift vertices, at most pv vertices and (unless a single
+// block exceeds it) at most pe out-edges each.
+static void plan_partitions(const std::vector<uint32_t>& rp, uint32_t nv, uint32_t pv, uint32_t pe,
+                            uint32_t pshift, std::vector<uint32_t>& starts) {
+    starts.clear();
+    const uint32_t g = 1u << pshift;
+    uint32_t s = 0;
+    while (s < nv) {
+        uint32_t e = std::min<uint64_t>((uint64_t)s + g, nv);
+        while (e < nv) {
+            uint32_t e2 = std::min<uint64_t>((uint64_t)e + g, nv);
+            if (e2 - s > pv) break;
+            if (rp[e2] - rp[s] > pe) break;
+            e = e2;
+        }
+        starts.push_back(s);
+        s = e;
+    }
+    starts.push_back(nv);
+}
+
+extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const uint64_t* row_ptr,
+                               const uint32_t* col, const uint32_t* weight, const fork_config* cfg_in) {
+    g_err.clear();
+    if (!out) return fail(FORK_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (nv == 0) return fail(FORK_E_INVALID, "num_vertices must be >= 1");
+    if (ne >= 0xffffffffull) return fail(FORK_E_INVALID, "num_edges must be < 2^32");
+    if (!row_ptr || (ne && !col)) return fail(FORK_E_INVALID, "row_ptr/col is NULL");
+    fork_config cfg{};
+    if (cfg_in) cfg = *cfg_in;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(FORK_E_DEVICE, "no HIP device");
+    if (cfg.device < 0 || cfg.device >= ndev) return fail(FORK_E_INVALID, "bad device ordinal %d", cfg.device);
+    // host copies of the inputs (validated)
+    std::vector<uint64_t> rp64(nv + 1);
+    std::vector<uint32_t> hcol, hw;
+    const uint64_t* rps = row_ptr;
+    const uint32_t* cols = col;
+    const uint32_t* ws = weight;
+    if (cfg.inputs_on_device) {
+        if (hipSetDevice(cfg.device) != hipSuccess) return fail(FORK_E_DEVICE, "hipSetDevice failed");
+        HIPCHK(hipMemcpy(rp64.data(), row_ptr, (nv + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        hcol.resize(ne);
+        if (ne) HIPCHK(hipMemcpy(hcol.data(), col, ne * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        if (weight) {
+            hw.resize(ne);
+            if (ne) HIPCHK(hipMemcpy(hw.data(), weight, ne * sizeof(uint32_t), hipMemcpyDeviceToHost));
+            ws = hw.data();
+        }
+        rps = rp64.data();
+        cols = hcol.data();
+    }
+    if (rps[0] != 0 || rps[nv] != ne) return fail(FORK_E_INVALID, "row_ptr must run from 0 to num_edges");
+    for (uint32_t v = 0; v < nv; ++v)
+        if (rps[v + 1] < rps[v]) return fail(FORK_E_INVALID, "row_ptr decreases at %u", v);
+    uint32_t wmax = 0;
+    for (uint64_t e = 0; e < ne; ++e) {
+        if (cols[e] >= nv) return fail(FORK_E_INVALID, "col[%llu] = %u out of range", (unsigned long long)e, cols[e]);
+        if (ws) {
+            if (ws[e] == 0) return fail(FORK_E_INVALID, "weight[%llu] is 0 (weights must be >= 1)", (unsigned long long)e);
+            wmax = std::max(wmax, ws[e]);
+        }
+    }
+    if (ws && wmax > 0x7fffffffu) return fail(FORK_E_INVALID, "weights must be < 2^31");
+
+    fork_ctx* c = new fork_ctx();
+    c->device = cfg.device;
+    if (hipSetDevice(c->device) != hipSuccess) { delete c; return fail(FORK_E_DEVICE, "hipSetDevice failed"); }
+    c->nv = nv;
+    c->ne = ne;
+    c->wbytes = !ws ? 0 : (wmax <= 0xff ? 1 : (wmax <= 0xffff ? 2 : 4));
+    c->h_rowptr.resize(nv + 1);
+    for (uint32_t v = 0; v <= nv; ++v) c->h_rowptr[v] = (uint32_t)rps[v];
+    int rc = FORK_OK;
+    auto cleanup = [&](int r) { fork_destroy(c); return r; };
+    // partition plan
+    uint32_t pv = cfg.partition_vertices ? cfg.partition_vertices : fk::VPMAX;
+    if (pv > fk::VPMAX) return cleanup(fail(FORK_E_INVALID, "partition_vertices must be <= %u", fk::VPMAX));
+    uint32_t pe = cfg.partition_edges ? cfg.partition_edges : (uint32_t)std::min<uint64_t>(0xffffffffu, std::max<uint64_t>(4096, (uint64_t)pv * 64));
+    uint32_t pshift = 0;
+    while (pshift < 8 && (2u << pshift) <= pv / 4) ++pshift;
+    plan_partitions(c->h_rowptr, nv, pv, pe, pshift, c->h_pstart);
+    c->np = (uint32_t)c->h_pstart.size() - 1;
+    c->pshift = pshift;
+    if (c->np > 65535) return cleanup(fail(FORK_E_INVALID, "too many partitions (%u); raise partition_vertices", c->np));
+    std::vector<uint16_t> vpart(((size_t)nv >> pshift) + 1);
+    for (uint32_t P = 0; P < c->np; ++P)
+        for (uint32_t b = c->h_pstart[P] >> pshift; b < ((c->h_pstart[P + 1] + (1u << pshift) - 1) >> pshift); ++b)
+            vpart[b] = (uint16_t)P;
+    // device graph
+    if ((rc = dalloc(&c->d_rowptr, nv + 1))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_col, ne))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_pstart, c->np + 1))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_vpart, vpart.size()))) return cleanup(rc);
+    auto cp = [&](void* d, const void* h, size_t bytes) -> int {
+        hipError_t e = hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);
+        return e == hipSuccess ? FORK_OK : fail(FORK_E_DEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+    };
+    if ((rc = cp(c->d_rowptr, c->h_rowptr.data(), (nv + 1) * 4ull))) return cleanup(rc);
+    if (ne && (rc = cp(c->d_col, cols, ne * 4ull))) return cleanup(rc);
+    if ((rc = cp(c->d_pstart, c->h_pstart.data(), (c->np + 1) * 4ull))) return cleanup(rc);
+    if ((rc = cp(c->d_vpart, vpart.data(), vpart.size() * 2ull))) return cleanup(rc);
+    if (ws) {
+        std::vector<uint8_t> packed(ne * (size_t)c->wbytes);
+        for (uint64_t e = 0; e < ne; ++e) {
+            if (c->wbytes == 1) packed[e] = (uint8_t)ws[e];
+            else if (c->wbytes == 2) ((uint16_t*)packed.data())[e] = (uint16_t)ws[e];
+            else ((uint32_t*)packed.data())[e] = ws[e];
+        }
+        uint8_t* dw = nullptr;
+        if ((rc = dalloc(&dw, packed.size()))) return cleanup(rc);
+        c->d_w = dw;
+        if ((rc = cp(c->d_w, packed.data(), packed.size()))) return cleanup(rc);
+    }
+    // operation pool
+    uint64_t pool = cfg.pool_bytes;
+    if (!pool) {
+        size_t fr = 0, tot = 0;
+        hipMemGetInfo(&fr, &tot);
+        pool = std::min<uint64_t>((uint64_t)24 << 30, std::max<uint64_t>((uint64_t)64 << 20, fr / 8));
+    }
+    const uint64_t per_chunk = sizeof(uint2) * fk::CH + 4 + 4 + 4;
+    c->nch = std::max<uint64_t>(1024, pool / per_chunk);
+    if (c->nch > 0xfffffff0ull) c->nch = 0xfffffff0ull;
+    if ((rc = dalloc(&c->d_chunks, c->nch * fk::CH))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_cnext, c->nch))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_ccount, c->nch))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_ring, c->nch))) return cleanup(rc);
+    // partition summaries
+    uint32_t** parr[] = {&c->d_pcount, &c->d_pbest_sp, &c->d_pbest_lv, &c->d_pbest_pr, &c->d_pfirst,
+                         &c->d_plast, &c->d_pvisits, &c->d_pn, &c->d_sel};
+    for (auto pp : parr) if ((rc = dalloc(pp, c->np + 1))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_score, c->np + 1))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_mlp, fk::MLP_NPARAM))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_gstat, fk::gstat_bytes()))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_ctl, 1))) return cleanup(rc);
+    if (hipHostMalloc((void**)&c->h_ctl, sizeof(fk::Ctl), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(FORK_E_NOMEM, "hipHostMalloc failed"));
+    for (auto& e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(FORK_E_DEVICE, "hipEventCreate failed"));
+    c->max_queries = cfg.max_queries;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    for (uint32_t P = 0; P < c->np; ++P) c->vpmax = std::max(c->vpmax, c->h_pstart[P + 1] - c->h_pstart[P]);
+    {
+        size_t dyn = fk::process_dyn_lds(c->vpmax);
+        const void* kp = fk::process_kernel_ptr(c->wbytes);
+        if (hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess)
+            return cleanup(fail(FORK_E_DEVICE, "partition slice of %u vertices does not fit in LDS", c->vpmax));
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, fk::process_threads(), dyn) == hipSuccess && occ > 0)
+            c->blocks_per_cu = occ;
+    }
+    *out = c;
+    return FORK_OK;
+}
+
+extern "C" int fork_partitions(fork_ctx* c, uint32_t* starts, uint32_t cap, uint32_t* num_parts) {
+    if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
+    if (num_parts) *num_parts = c->np;
+    if (starts) {
+        uint32_t n = std::min<uint32_t>(cap + 1, c->np + 1);
+        memcpy(starts, c->h_pstart.data(), n * sizeof(uint32_t));
+    }
+    return FORK_OK;
+}
+
+extern "C" int fork_submit(fork_ctx* c, int type, const uint32_t* sources, uint32_t n, const void* params,
+                           uint32_t* first_id) {
+    g_err.clear();
+    if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
+    if (type != FORK_SSSP && type != FORK_BFS && type != FORK_PPR) return fail(FORK_E_INVALID, "bad query type %d", type);
+    if (n && !sources) return fail(FORK_E_INVALID, "sources is NULL");
+    QueryRec base{(uint32_t)type, 0, 0, 0.f, 0.f};
+    if (type == FORK_PPR) {
+        if (!params) return fail(FORK_E_INVALID, "PPR needs fork_ppr_params");
+        const fork_ppr_params* pp = (const fork_ppr_params*)params;
+        if (!(pp->alpha > 0.f && pp->alpha < 1.f)) return fail(FORK_E_INVALID, "alpha must be in (0,1)");
+        if (!(pp->epsilon > 0.f)) return fail(FORK_E_INVALID, "epsilon must be > 0");
+        if (pp->eps_mode != 0 && pp->eps_mode != 1) return fail(FORK_E_INVALID, "eps_mode must be 0 or 1");
+        base.alpha = pp->alpha;
+        base.eps = pp->epsilon;
+        base.mode = (uint32_t)pp->eps_mode;
+    }
+    for (uint32_t i = 0; i < n; ++i)
+        if (sources[i] >= c->nv) return fail(FORK_E_INVALID, "source %u out of range (V=%u)", sources[i], c->nv);
+    if (c->ran) {  // a new batch
+        c->queries.clear();
+        c->digests.clear();
+        c->ran = false;
+        c->res_n = 0;
+    }
+    if (first_id) *first_id = (uint32_t)c->queries.size();
+    for (uint32_t i = 0; i < n; ++i) {
+        QueryRec r = base;
+        r.src = sources[i];
+        c->queries.push_back(r);
+    }
+    return FORK_OK;
+}
+
+static uint64_t qwords(const fork_ctx* c, uint32_t type) { return (type == FORK_PPR ? 2ull : 1ull) * c->nv; }
+
+// Allocate per-wave buffers for `nq` queries needing `words` state words.
+static int ensure_wave(fork_ctx* c, uint32_t nq, size_t words, uint32_t kmax) {
+    int rc;
+    if (nq > c->qcap || kmax > c->kmax_cap) {
+        hipFree(c->d_bhead); hipFree(c->d_btail); hipFree(c->d_items);
+        hipFree(c->d_qtype); hipFree(c->d_qsrc); hipFree(c->d_qmode); hipFree(c->d_qoff);
+        hipFree(c->d_qalpha); hipFree(c->d_qeps); hipFree(c->d_digest);
+        c->d_bhead = nullptr; c->d_btail = nullptr; c->d_items = nullptr;
+        uint32_t qc = std::max(nq, c->qcap);
+        uint32_t kc = std::max(kmax, c->kmax_cap);
+        size_t nb = (size_t)c->np * qc;
+        if ((rc = dalloc(&c->d_bhead, nb))) return rc;
+        if ((rc = dalloc(&c->d_btail, nb))) return rc;
+        c->item_cap = ((kc + fk::NXCD - 1) / fk::NXCD) * qc;
+        if ((rc = dalloc(&c->d_items, (size_t)fk::NXCD * c->item_cap))) return rc;
+        if ((rc = dalloc(&c->d_qtype, qc))) return rc;
+        if ((rc = dalloc(&c->d_qsrc, qc))) return rc;
+        if ((rc = dalloc(&c->d_qmode, qc))) return rc;
+        if ((rc = dalloc(&c->d_qoff, qc))) return rc;
+        if ((rc = dalloc(&c->d_qalpha, qc))) return rc;
+        if ((rc = dalloc(&c->d_qeps, qc))) return rc;
+        if ((rc = dalloc(&c->d_digest, (size_t)qc * 6))) return rc;
+        c->qcap = qc;
+        c->kmax_cap = kc;
+    }
+    if (words > c->state_words_cap) {
+        hipFree(c->d_state);
+        c->d_state = nullptr;
+        if ((rc = dalloc(&c->d_state, words))) return rc;
+        c->state_words_cap = words;
+    }
+    return FORK_OK;
+}
+
+static fk::GraphDev graph_dev(const fork_ctx* c) {
+    fk::GraphDev g;
+    g.nv = c->nv; g.np = c->np; g.pshift = c->pshift; g.wbytes = c->wbytes;
+    g.rowptr = c->d_rowptr; g.col = c->d_col; g.w = c->d_w; g.pstart = c->d_pstart; g.vpart = c->d_vpart;
+    return g;
+}
+
+static fk::BufDev buf_dev(const fork_ctx* c) {
+    fk::BufDev B;
+    B.bhead = c->d_bhead; B.btail = c->d_btail; B.chunks = c->d_chunks; B.cnext = c->d_cnext;
+    B.ccount = c->d_ccount; B.ring = c->d_ring; B.nch = c->nch; B.pcount = c->d_pcount;
+    B.pbest_sp = c->d_pbest_sp; B.pbest_lv = c->d_pbest_lv; B.pbest_pr = c->d_pbest_pr;
+    B.pfirst = c->d_pfirst; B.plast = c->d_plast; B.pvisits = c->d_pvisits; B.pn = c->d_pn;
+    B.sel = c->d_sel; B.score = c->d_score; B.items = c->d_items; B.item_cap = c->item_cap; B.ctl = c->d_ctl;
+    return B;
+}
+
+static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& o, hipStream_t s,
+                    const fk::PassCfg& cfg, uint64_t& passes_left) {
+    // layout of the wave's state
+    std::vector<uint32_t> qt(nq), qs(nq), qm(nq);
+    std::vector<unsigned long long> qo(nq);
+    std::vector<float> qa(nq), qe(nq);
+    size_t words = 0;
+    bool mixed = false;
+    for (uint32_t i = 0; i < nq; ++i) {
+        const QueryRec& r = c->queries[q0 + i];
+        qt[i] = r.type; qs[i] = r.src; qm[i] = r.mode; qa[i] = r.alpha; qe[i] = r.eps;
+        qo[i] = words;
+        words += qwords(c, r.type);
+        if (r.type != c->queries[q0].type) mixed = true;
+    }
+    int rc = ensure_wave(c, nq, words, cfg.kmax);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(c->d_qtype, qt.data(), nq * 4ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_qsrc, qs.data(), nq * 4ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_qmode, qm.data(), nq * 4ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_qoff, qo.data(), nq * 8ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_qalpha, qa.data(), nq * 4ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_qeps, qe.data(), nq * 4ull, hipMemcpyHostToDevice, s));
+    fk::PassCfg pc = cfg;
+    pc.mixed = mixed ? 1u : 0u;
+    fk::QueryDev Q;
+    Q.nq = nq; Q.qc = c->qcap; Q.qtype = c->d_qtype; Q.qoff = c->d_qoff; Q.qalpha = c->d_qalpha;
+    Q.qeps = c->d_qeps; Q.qmode = c->d_qmode; Q.state = c->d_state;
+    fk::GraphDev g = graph_dev(c);
+    fk::BufDev B = buf_dev(c);
+    HIPCHK(hipEventRecord(c->ev[0], s));
+    // state init: distances/levels = INF, p = r = 0
+    for (uint32_t i = 0; i < nq;) {
+        uint32_t j = i;
+        while (j < nq && (qt[j] == FORK_PPR) == (qt[i] == FORK_PPR)) ++j;
+        size_t w0 = qo[i], w1 = (j < nq) ? qo[j] : words;
+        if (qt[i] == FORK_PPR) HIPCHK(hipMemsetAsync(c->d_state + w0, 0, (w1 - w0) * 4, s));
+        else HIPCHK(hipMemsetD32Async((hipDeviceptr_t)(c->d_state + w0), (int)fk::INF, w1 - w0, s));
+        i = j;
+    }
+    HIPCHK(hipMemsetAsync(c->d_bhead, 0xff, (size_t)c->np * c->qcap * 4, s));
+    HIPCHK(hipMemsetAsync(c->d_btail, 0xff, (size_t)c->np * c->qcap * 4, s));
+    HIPCHK(hipMemsetAsync(c->d_ccount, 0, (size_t)c->nch * 4, s));
+    HIPCHK(hipMemsetAsync(c->d_pcount, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->d_pbest_sp, (int)fk::INF, c->np + 1, s));
+    HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->d_pbest_lv, (int)fk::INF, c->np + 1, s));
+    HIPCHK(hipMemsetAsync(c->d_pbest_pr, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->d_pfirst, (int)fk::INF, c->np + 1, s));
+    HIPCHK(hipMemsetAsync(c->d_plast, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetAsync(c->d_pvisits, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetAsync(c->d_pn, 0, (c->np + 1) * 4ull, s));
+    if (c->nch < nq + 64ull) return fail(FORK_E_CAPACITY, "operation pool too small for %u queries", nq);
+    fk::Ctl ctl0{};
+    ctl0.ring_head = nq;
+    ctl0.ring_tail = c->nch;
+    ctl0.avail_end = c->nch;
+    *c->h_ctl = ctl0;
+    HIPCHK(hipMemcpyAsync(c->d_ctl, c->h_ctl, sizeof(fk::Ctl), hipMemcpyHostToDevice, s));
+    HIPCHK(fk::launch_ring_init(c->d_ring, c->nch, s));
+    HIPCHK(hipMemcpyAsync(c->d_qsrc, qs.data(), nq * 4ull, hipMemcpyHostToDevice, s));
+    HIPCHK(fk::launch_seed(g, Q, B, c->d_qsrc, s));
+    HIPCHK(hipEventRecord(c->ev[1], s));
+    // pass loop (Algorithm 2): select -> detach -> process, until no buffer holds work
+    const uint32_t blocks = (uint32_t)std::max(1, c->num_cu * c->blocks_per_cu);
+    uint32_t batch = 1;
+    bool done = false;
+    const char* prog = getenv("FORK_PROGRESS");
+    const double prog_every = prog ? atof(prog) : 0.0;  // seconds between progress lines (0 = off)
+    auto t_start = std::chrono::steady_clock::now();
+    auto t_last = t_start;
+    while (!done) {
+        uint32_t nb = batch;
+        if (passes_left != ~0ull) nb = (uint32_t)std::min<uint64_t>(nb, passes_left);
+        if (nb == 0) return fail(FORK_E_NOT_CONVERGED, "max_passes reached with work pending");
+        if (o.profile && c->pev.size() < 2 * nb) {
+            size_t old = c->pev.size();
+            c->pev.resize(2 * nb, nullptr);
+            for (size_t k = old; k < c->pev.size(); ++k) HIPCHK(hipEventCreate(&c->pev[k]));
+        }
+        for (uint32_t k = 0; k < nb; ++k) {
+            if (pc.sched == fk::S_LEARNED) HIPCHK(fk::launch_mlp_score(g, B, c->d_mlp, c->d_score, nullptr, c->d_gstat, 0, s));
+            HIPCHK(fk::launch_select(g, B, pc, s));
+            HIPCHK(fk::launch_worklist(B, Q, pc.kmax, s));
+            if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k], s));
+            HIPCHK(fk::launch_process(g, Q, B, pc, blocks, c->vpmax, s));
+            if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k + 1], s));
+        }
+        if (passes_left != ~0ull) passes_left -= nb;
+        HIPCHK(hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(fk::Ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (o.profile) {
+            for (uint32_t k = 0; k < nb; ++k) {
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, c->pev[2 * k], c->pev[2 * k + 1]));
+                c->stats.process_ms += ms;
+            }
+            c->stats.process_launches += nb;
+        }
+        const fk::Ctl& h = *c->h_ctl;
+        if (h.err & fk::ERR_CORRUPT) return fail(FORK_E_DEVICE, "device consistency check failed (flags 0x%x)", h.err);
+        if (h.err & fk::ERR_CAPACITY)
+            return fail(FORK_E_CAPACITY, "operation pool exhausted (%llu chunks) with %u queries in flight",
+                        c->nch, nq);
+        if (h.err) return fail(FORK_E_DEVICE, "device error flags 0x%x", h.err);
+        if (h.pending_parts == 0) done = true;
+        batch = std::min<uint32_t>(batch * 2, 64);
+        if (prog_every > 0) {
+            auto now = std::chrono::steady_clock::now();
+            if (std::chrono::duration<double>(now - t_last).count() >= prog_every) {
+                t_last = now;
+                fprintf(stderr, "[fork] wave q%u+%u pass %u pending_parts %u pending_ops %llu edges %llu emitted %llu t=%.1fs\n",
+                        q0, nq, h.pass, h.pending_parts, h.pending_ops, h.c_edges, h.c_emitted,
+                        std::chrono::duration<double>(now - t_start).count());
+                fflush(stderr);
+            }
+        }
+    }
+    HIPCHK(hipEventRecord(c->ev[2], s));
+    HIPCHK(fk::launch_digest(Q, c->nv, c->d_digest, s));
+    HIPCHK(hipEventRecord(c->ev[3], s));
+    std::vector<unsigned long long> dg((size_t)nq * 6);
+    HIPCHK(hipMemcpyAsync(dg.data(), c->d_digest, dg.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < nq; ++i) {
+        fork_digest& d = c->digests[q0 + i];
+        d.count = dg[i * 6 + 0];
+        d.sum = dg[i * 6 + 1];
+        d.hash = dg[i * 6 + 2];
+        memcpy(&d.fsum, &dg[i * 6 + 3], 8);
+        memcpy(&d.fres, &dg[i * 6 + 4], 8);
+        memcpy(&d.fmax, &dg[i * 6 + 5], 8);
+    }
+    float t_init = 0, t_run = 0, t_dig = 0;
+    hipEventElapsedTime(&t_init, c->ev[0], c->ev[1]);
+    hipEventElapsedTime(&t_run, c->ev[1], c->ev[2]);
+    hipEventElapsedTime(&t_dig, c->ev[2], c->ev[3]);
+    const fk::Ctl& h = *c->h_ctl;
+    fork_stats_t& st = c->stats;
+    st.init_ms += t_init;
+    st.run_ms += t_run;
+    st.digest_ms += t_dig;
+    st.passes += h.pass;
+    st.work_items += h.c_items;
+    st.edges += h.c_edges;
+    st.improved += h.c_improved;
+    st.ops_emitted += h.c_emitted;
+    st.ops_consumed += h.c_consumed;
+    st.vertex_pushes += h.c_vpush;
+    st.yields += h.c_yields;
+    st.chunks += h.c_chunks;
+    st.intra_edges += h.c_intra;
+    st.waves += 1;
+    c->res_first = q0;
+    c->res_n = nq;
+    c->res_off.assign(qo.begin(), qo.end());
+    return FORK_OK;
+}
+
+extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
+    g_err.clear();
+    if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
+    if (c->queries.empty()) return fail(FORK_E_STATE, "no queries submitted");
+    fork_run_opts o{};
+    o.scheduler = FORK_SCHED_PRIORITY;
+    if (opts) o = *opts;
+    if (o.scheduler < 0 || o.scheduler > FORK_SCHED_MAXOPS) return fail(FORK_E_INVALID, "bad scheduler %d", o.scheduler);
+    if (o.scheduler == FORK_SCHED_LEARNED && !o.mlp_weights) return fail(FORK_E_INVALID, "LEARNED needs mlp_weights");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(FORK_E_DEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)o.stream;
+    const uint32_t nq_total = (uint32_t)c->queries.size();
+    // wave capacity from free device memory
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    size_t reserve = (size_t)c->state_words_cap * 4;  // memory we already hold for state
+    size_t budget = (fr + reserve) > ((size_t)2 << 30) ? (fr + reserve) - ((size_t)2 << 30) : 0;
+    budget = (size_t)(budget * 0.9);
+    uint32_t cap_q = c->max_queries ? c->max_queries : nq_total;
+    // per-query bytes beyond state: buckets (8B per partition) + items
+    const size_t per_q_extra = (size_t)c->np * 8 + 64;
+    fk::PassCfg cfg{};
+    cfg.sched = (uint32_t)o.scheduler;
+    cfg.seed = (uint32_t)o.seed;
+    cfg.mu = o.edge_budget_mu;
+    // value windows / yield ranges (heuristic 2): SSSP in weight units, BFS in levels
+    uint32_t delta = o.delta ? o.delta : (c->wbytes ? 1024u : 4u);
+    cfg.win_sp = std::max(1u, delta / 4);
+    cfg.yld_sp = delta;
+    cfg.win_lv = 1;
+    cfg.yld_lv = c->wbytes ? 4u : std::max(1u, delta);
+    if (o.scheduler == FORK_SCHED_LEARNED) {
+        HIPCHK(hipMemcpyAsync(c->d_mlp, o.mlp_weights, fk::MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+    }
+    // waves: greedy in submit order under the memory budget
+    std::vector<std::pair<uint32_t, uint32_t>> waves;
+    for (uint32_t q0 = 0; q0 < nq_total;) {
+        size_t bytes = 0;
+        uint32_t n = 0;
+        while (q0 + n < nq_total && n < cap_q) {
+            size_t b = qwords(c, c->queries[q0 + n].type) * 4 + per_q_extra;
+            if (n > 0 && bytes + b > budget) break;
+            bytes += b;
+            ++n;
+        }
+        if (bytes > budget) return fail(FORK_E_NOMEM, "one query's state does not fit in device memory");
+        waves.push_back({q0, n});
+        q0 += n;
+    }
+    uint32_t wmax = 0;
+    for (auto& w : waves) wmax = std::max(wmax, w.second);
+    cfg.kmax = o.parts_per_pass ? o.parts_per_pass
+                                : std::min<uint32_t>(c->np, std::max<uint32_t>(8, (16384 + wmax - 1) / wmax));
+    if (cfg.kmax == 0 || cfg.kmax > c->np) cfg.kmax = c->np;
+    c->stats = fork_stats_t{};
+    c->stats.num_partitions = c->np;
+    c->stats.weight_bytes = (uint32_t)c->wbytes;
+    c->digests.assign(nq_total, fork_digest{});
+    c->res_n = 0;
+    uint64_t passes_left = o.max_passes ? o.max_passes : ~0ull;
+    // A wave whose pending operations overflow the pool is split in two and
+    // re-run (state is re-initialised per wave, so a retry is exact).
+    uint32_t wave_cap = 0;
+    for (size_t wi = 0; wi < waves.size(); ++wi) {
+        uint32_t q0 = waves[wi].first, n = waves[wi].second;
+        if (wave_cap && n > wave_cap) {
+            waves.insert(waves.begin() + wi + 1, {q0 + wave_cap, n - wave_cap});
+            n = waves[wi].second = wave_cap;
+        }
+        uint64_t saved = passes_left;
+        fork_stats_t saved_st = c->stats;
+        int rc = run_wave(c, q0, n, o, s, cfg, passes_left);
+        if (rc == FORK_E_CAPACITY && n > 1) {
+            passes_left = saved;
+            c->stats = saved_st;
+            wave_cap = n / 2;
+            waves[wi].second = wave_cap;
+            waves.insert(waves.begin() + wi + 1, {q0 + wave_cap, n - wave_cap});
+            --wi;
+            continue;
+        }
+        if (rc) return rc;
+    }
+    c->ran = true;
+    return FORK_OK;
+}
+
+extern "C" int fork_fetch(fork_ctx* c, uint32_t qid, int field, void* dst, uint64_t dst_bytes, int dst_on_device) {
+    g_err.clear();
+    if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
+    if (!dst) return fail(FORK_E_INVALID, "dst is NULL");
+    if (qid >= c->queries.size()) return fail(FORK_E_INVALID, "query id %u out of range", qid);
+    if (!c->ran) return fail(FORK_E_STATE, "query %u has not run", qid);
+    const uint32_t type = c->queries[qid].type;
+    if (field == FORK_FIELD_DIGEST) {
+        if (dst_bytes < sizeof(fork_digest)) return fail(FORK_E_INVALID, "dst too small");
+        if (dst_on_device) HIPCHK(hipMemcpy(dst, &c->digests[qid], sizeof(fork_digest), hipMemcpyHostToDevice));
+        else memcpy(dst, &c->digests[qid], sizeof(fork_digest));
+        return FORK_OK;
+    }
+    if (field == FORK_FIELD_VALUE && type == FORK_PPR) return fail(FORK_E_INVALID, "VALUE field needs SSSP/BFS");
+    if ((field == FORK_FIELD_P || field == FORK_FIELD_R) && type != FORK_PPR)
+        return fail(FORK_E_INVALID, "P/R fields need PPR");
+    if (field < 0 || field > FORK_FIELD_DIGEST) return fail(FORK_E_INVALID, "bad field %d", field);
+    if (qid < c->res_first || qid >= c->res_first + c->res_n)
+        return fail(FORK_E_STATE, "query %u is not resident (only the last wave keeps vectors)", qid);
+    if (dst_bytes < (uint64_t)c->nv * 4) return fail(FORK_E_INVALID, "dst too small");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(FORK_E_DEVICE, "hipSetDevice failed");
+    const uint32_t* src = c->d_state + c->res_off[qid - c->res_first] + (field == FORK_FIELD_R ? c->nv : 0);
+    HIPCHK(hipMemcpy(dst, src, (size_t)c->nv * 4, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return FORK_OK;
+}
+
+extern "C" int fork_stats(fork_ctx* c, void* dst, uint64_t dst_bytes) {
+    if (!c || !dst) return fail(FORK_E_INVALID, "NULL argument");
+    if (dst_bytes < sizeof(fork_stats_t)) return fail(FORK_E_INVALID, "dst too small");
+    memcpy(dst, &c->stats, sizeof(fork_stats_t));
+    return FORK_OK;
+}

@@ -1,0 +1,225 @@
+"""GPU parity: the HIP fork-processing path against the CPU oracle.
+
+SSSP and BFS must match bit-for-bit (int32, INT32_MAX = unreachable) and pass
+the optimality certificate; PPR outputs must satisfy the push invariant
+p + PPR(r) = PPR(e_s) within 1e-4 in L1 against fp64 power iteration, and the
+termination rule max r/thr < 1, with p, r >= 0.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import fpp_inputs as fi
+import oracle
+from golden_io import load_sp_fixture
+
+pytestmark = pytest.mark.gpu
+
+ALPHA = 0.15
+
+
+def _fork():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2103_14915_amd as fork
+    return fork
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_sp(fork, g, srcs, qtype="sssp", sched="priority", **kw):
+    load_kw = {k: kw.pop(k) for k in list(kw) if k in ("partition_vertices", "partition_edges", "pool_bytes",
+                                                       "max_queries")}
+    fg = fork.ForkGraph.from_graph(g, **load_kw)
+    fg.submit(qtype, srcs)
+    fg.run(scheduler=sched, max_passes=kw.pop("max_passes", 200000), **kw)
+    out = []
+    for i in range(len(srcs)):
+        try:
+            out.append(fg.fetch(i))
+        except fork.ForkError as e:  # earlier waves keep digests only
+            assert e.code == fork.FORK_E_STATE
+            out.append(np.full(g.num_vertices, -1, np.int32))
+    out = np.stack(out)
+    st = fg.stats()
+    fg.close()
+    return out, st
+
+
+def test_hand_fixture_all_sources_tiny_partitions():
+    fork = _fork()
+    nv, edges, expect = load_sp_fixture("sssp_bfs_hand8.txt")
+    s, d, w = zip(*edges)
+    g = fi.from_edges(nv, s, d, w)
+    for pv in (1, 2, 8):
+        say("hand fixture pv", pv)
+        got, _ = run_sp(fork, g, np.arange(nv), "sssp", partition_vertices=pv)
+        np.testing.assert_array_equal(got, oracle.sssp(g, np.arange(nv)))
+        got, _ = run_sp(fork, g, np.arange(nv), "bfs", partition_vertices=pv)
+        np.testing.assert_array_equal(got, oracle.bfs(g, np.arange(nv)))
+        for (kind, src), vec in expect.items():
+            ref = oracle.sssp(g, [src])[0] if kind == "sssp" else oracle.bfs(g, [src])[0]
+            np.testing.assert_array_equal(ref, vec)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_small_graphs(seed):
+    fork = _fork()
+    n = [10, 64, 200, 700][seed]
+    g = fi.random_small(n, 4 * n, 40 + seed, wmax=[3, 50, 255, 1000][seed])
+    srcs = np.arange(min(n, 48))
+    for pv in (4, 64):
+        say("random small", seed, "pv", pv)
+        got, _ = run_sp(fork, g, srcs, "sssp", partition_vertices=pv)
+        np.testing.assert_array_equal(got, oracle.sssp(g, srcs))
+        got, _ = run_sp(fork, g, srcs, "bfs", partition_vertices=pv)
+        np.testing.assert_array_equal(got, oracle.bfs(g, srcs))
+
+
+@pytest.mark.parametrize("sched", ["priority", "fifo", "random", "maxops"])
+def test_rmat12_sssp64_bit_exact(sched):
+    """R-MAT scale 12, 64 SSSP queries: bit-exact under every schedule."""
+    fork = _fork()
+    spec = fi.WORKLOADS["rmat12_sssp64"]
+    g = fi.make_graph(spec)
+    srcs = fi.make_sources(g, spec)[0][1]
+    say("rmat12", sched)
+    got, st = run_sp(fork, g, srcs, "sssp", sched=sched)
+    ref = oracle.sssp(g, srcs)
+    np.testing.assert_array_equal(got, ref)
+    for i in range(0, 64, 16):
+        assert oracle.sp_certificate(g, srcs[i], got[i]) == 0
+    assert st["passes"] > 0 and st["edges"] > 0
+
+
+def test_rmat12_tiny_partition_stress():
+    """Partitions of 1..16 vertices exercise the cross-partition machinery."""
+    fork = _fork()
+    spec = fi.WORKLOADS["rmat12_sssp64"]
+    g = fi.make_graph(spec)
+    srcs = fi.make_sources(g, spec)[0][1][:16]
+    ref = oracle.sssp(g, srcs)
+    for pv in (1, 16):
+        say("tiny partitions", pv)
+        got, st = run_sp(fork, g, srcs, "sssp", partition_vertices=pv)
+        np.testing.assert_array_equal(got, ref)
+
+
+def test_grid_sssp_bfs_mixed_batch():
+    fork = _fork()
+    g = fi.grid(96, 80, weights=(1, 1000), weight_seed=7)
+    s1 = fi.sources_uniform(g, 24, 1)
+    s2 = fi.sources_uniform(g, 24, 2)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=640)
+    fg.submit("sssp", s1)
+    fg.submit("bfs", s2)
+    say("grid mixed")
+    fg.run(max_passes=500000)
+    d = np.stack([fg.fetch(i) for i in range(24)])
+    lv = np.stack([fg.fetch(24 + i) for i in range(24)])
+    np.testing.assert_array_equal(d, oracle.sssp(g, s1))
+    np.testing.assert_array_equal(lv, oracle.bfs(g, s2))
+    fg.close()
+
+
+def check_ppr(g, srcs, P, R, eps, mode=0, tol=1e-4):
+    for i, s in enumerate(srcs):
+        p = P[i].astype(np.float64)
+        r = R[i].astype(np.float64)
+        assert np.all(p >= 0) and np.all(r >= 0)
+        assert oracle.push_terminal(g, R[i], eps, mode, dtype=np.float32), f"query {i}: not terminal"
+        inv = oracle.ppr_invariant_l1(g, s, p, r, ALPHA)
+        assert inv <= tol, f"query {i}: invariant L1 {inv}"
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ppr_small_invariant(mode):
+    fork = _fork()
+    g = fi.rmat(10, seed=12)
+    srcs = fi.sources_uniform(g, 32, 3)
+    eps = 1e-6 if mode == 0 else 1e-7
+    for pv in (16, 128):
+        say("ppr small mode", mode, "pv", pv)
+        fg = fork.ForkGraph.from_graph(g, partition_vertices=pv)
+        fg.submit("ppr", srcs, alpha=ALPHA, epsilon=eps, eps_mode=mode)
+        fg.run(max_passes=200000)
+        P = np.stack([fg.fetch(i, fork.FIELD_P) for i in range(len(srcs))])
+        R = np.stack([fg.fetch(i, fork.FIELD_R) for i in range(len(srcs))])
+        fg.close()
+        check_ppr(g, srcs, P, R, eps, mode)
+
+
+def mix64(z):
+    """SplitMix64 finaliser (Steele, Lea, Flood 2014), vectorised over uint64."""
+    with np.errstate(over="ignore"):
+        z = (z + np.uint64(0x9E3779B97F4A7C15)).astype(np.uint64)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def sp_digest(vec):
+    """(count, sum, hash) of an int32 distance vector, as the fork_digest docs define it."""
+    v = np.flatnonzero(vec != fork_inf())
+    x = vec[v].astype(np.uint64)
+    with np.errstate(over="ignore"):
+        h = np.sum(mix64((v.astype(np.uint64) << np.uint64(32)) | x), dtype=np.uint64)
+    return int(v.size), int(x.sum()), int(h)
+
+
+def fork_inf():
+    return np.int32(0x7FFFFFFF)
+
+
+def test_pool_exhaustion_splits_waves():
+    """A pool too small for all queries at once: the run splits the wave, every
+    query's digest matches the oracle and the resident vectors are exact."""
+    fork = _fork()
+    spec = fi.WORKLOADS["rmat12_sssp64"]
+    g = fi.make_graph(spec)
+    srcs = fi.make_sources(g, spec)[0][1]
+    say("small pool")
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=256, pool_bytes=1 << 22)
+    fg.submit("sssp", srcs)
+    fg.run(max_passes=200000)
+    st = fg.stats()
+    ref = oracle.sssp(g, srcs)
+    resident = 0
+    for i in range(len(srcs)):
+        d = fg.digest(i)
+        assert (d["count"], d["sum"], d["hash"]) == sp_digest(ref[i]), i
+        try:
+            np.testing.assert_array_equal(fg.fetch(i), ref[i])
+            resident += 1
+        except fork.ForkError as e:
+            assert e.code == fork.FORK_E_STATE
+    fg.close()
+    assert resident >= 1
+    say("waves", st["waves"])
+
+
+def test_explicit_waves_digests():
+    """max_queries forces waves; digests of all waves match the oracle."""
+    fork = _fork()
+    g = fi.rmat(11, seed=5, weights=(1, 255), weight_seed=6)
+    srcs = fi.sources_uniform(g, 40, 8)
+    fg = fork.ForkGraph.from_graph(g, max_queries=16)
+    fg.submit("bfs", srcs[:20])
+    fg.submit("sssp", srcs[20:])
+    fg.run(max_passes=200000)
+    st = fg.stats()
+    assert st["waves"] == 3
+    ref = np.concatenate([oracle.bfs(g, srcs[:20]), oracle.sssp(g, srcs[20:])])
+    for i in range(40):
+        d = fg.digest(i)
+        assert (d["count"], d["sum"], d["hash"]) == sp_digest(ref[i]), i
+    for i in range(32, 40):
+        np.testing.assert_array_equal(fg.fetch(i), ref[i])
+    with pytest.raises(fork.ForkError):
+        fg.fetch(0)
+    fg.close()
