@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--scale", type=int, default=0, help="experiment: override the R-MAT scale")
     ap.add_argument("--queries", type=int, default=0, help="experiment: use only the first N queries per type")
     ap.add_argument("--max-queries", type=int, default=0, help="queries resident per wave (0 = auto)")
+    ap.add_argument("--persistent", action="store_true", help="one persistent cooperative kernel per batch of passes")
+    ap.add_argument("--items-per-pass", type=int, default=0, help="work items queued per pass (0 = auto)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -117,7 +119,8 @@ def main():
     kinds = sorted({qt for qt, _ in queries})
     kind = kinds[0] if len(kinds) == 1 else "mixed"
     run_kw = dict(scheduler=args.scheduler, parts_per_pass=args.parts_per_pass, delta=args.delta,
-                  edge_budget_mu=args.mu, stream=stream, profile=1)
+                  edge_budget_mu=args.mu, stream=stream, profile=1, persistent=int(args.persistent),
+                  items_per_pass=args.items_per_pass)
     for _ in range(args.warmup):
         fg.run(**run_kw)
     torch.cuda.synchronize()
@@ -152,7 +155,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload + (f"@scale{args.scale}" if args.scale else "")
                    + (f"@q{args.queries}" if args.queries else ""), "queries": nq, "types": kinds, "vertices": g.num_vertices,
-                   "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler,
+                   "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler, "persistent": bool(args.persistent),
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_process",

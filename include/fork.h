@@ -85,6 +85,8 @@ typedef struct {
     int      persistent;       /* 1 = one persistent kernel with a device queue  */
     uint64_t seed;             /* for FORK_SCHED_RANDOM                          */
     int      profile;          /* 1 = time every pass kernel with HIP events     */
+    uint32_t items_per_pass;   /* (partition, query) items queued per pass when
+                                  parts_per_pass is 0 (0 = auto)                 */
 } fork_run_opts;
 
 /* Counters accumulated over the last fork_run (all waves). */

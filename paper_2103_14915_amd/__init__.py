@@ -51,7 +51,7 @@ class fork_run_opts(ctypes.Structure):
     _fields_ = [("scheduler", ctypes.c_int), ("parts_per_pass", ctypes.c_uint32), ("delta", ctypes.c_uint32),
                 ("edge_budget_mu", ctypes.c_float), ("max_passes", ctypes.c_uint64),
                 ("stream", ctypes.c_void_p), ("mlp_weights", ctypes.c_void_p), ("persistent", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("profile", ctypes.c_int)]
+                ("seed", ctypes.c_uint64), ("profile", ctypes.c_int), ("items_per_pass", ctypes.c_uint32)]
 
 
 class fork_stats_t(ctypes.Structure):
@@ -173,7 +173,7 @@ class ForkGraph:
         return first.value
 
     def run(self, scheduler="priority", parts_per_pass=0, delta=0, edge_budget_mu=0.0, max_passes=0,
-            stream=None, mlp_weights=None, persistent=0, seed=0, profile=0):
+            stream=None, mlp_weights=None, persistent=0, seed=0, profile=0, items_per_pass=0):
         s = SCHEDS[scheduler] if isinstance(scheduler, str) else int(scheduler)
         w = None
         if mlp_weights is not None:
@@ -184,7 +184,7 @@ class ForkGraph:
         if stream is not None:
             sp = stream if isinstance(stream, int) else stream.cuda_stream
         o = fork_run_opts(s, parts_per_pass, delta, edge_budget_mu, max_passes, sp,
-                          None if w is None else w.ctypes.data, persistent, seed, profile)
+                          None if w is None else w.ctypes.data, persistent, seed, profile, items_per_pass)
         _check(lib.fork_run(self._ctx, ctypes.byref(o)))
 
     def fetch(self, qid, field=None, out=None):

@@ -81,6 +81,7 @@ struct BufDev {
     uint32_t* plast;          // [np] pass of the last visit
     uint32_t* pvisits;        // [np] visits
     uint32_t* pn;             // [np] items of the partition in the current pass
+    uint32_t* pqn;            // [np] (partition, query) buffers holding operations
     uint32_t* sel;            // [max parts per pass] selected partitions
     float* score;             // [np] learned score (LEARNED policy)
     Item* items;              // [NXCD * item_cap]
@@ -90,7 +91,8 @@ struct BufDev {
 
 struct PassCfg {
     uint32_t sched;
-    uint32_t kmax;            // partitions per pass
+    uint32_t kmax;            // max partitions per pass
+    uint32_t target_items;    // pick partitions until this many work items (0: exactly kmax)
     uint32_t win_sp, win_lv;  // batch window (SSSP, BFS)
     uint32_t yld_sp, yld_lv;  // yield range H2 (0 = off)
     float mu;                 // yield budget H1: mu * |E_P| / items_P (0 = off)

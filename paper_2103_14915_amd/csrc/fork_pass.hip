@@ -22,16 +22,19 @@
 // vertex (min value / summed mass), grouped by target partition and appended
 // to the target buffers with one chunk reservation per flush (Algorithm 2:
 // send after processing; Appendix B.1: reserve a range, then copy).
-#include "fork_util.h"
+#include <hip/hip_cooperative_groups.h>
+
+#include "fork_mlp.h"
+#include "fork_sched.h"
 
 namespace fk {
 
-constexpr int NT = 512;           // threads per workgroup
+constexpr int NT = 256;           // threads per workgroup
 constexpr int NW = NT / WAVE;     // waves per workgroup
-constexpr int FCAP = 2048;        // frontier capacity (two buffers)
-constexpr int BCAP = 1024;        // vertices expanded per batch
-constexpr int SCAP = 1024;        // staged outgoing operations
-constexpr int CCAP = 256;         // chunk ids gathered per consume round
+constexpr int FCAP = 1024;        // frontier capacity (two buffers)
+constexpr int BCAP = 512;         // vertices expanded per batch
+constexpr int SCAP = 512;         // staged outgoing operations
+constexpr int CCAP = 128;         // chunk ids gathered per consume round
 constexpr int SE = (SCAP + NT - 1) / NT;
 
 struct PassShared {
@@ -128,6 +131,14 @@ struct ItemCtx {
     // per-thread counters
     unsigned long long c_edges, c_intra, c_improved, c_emitted, c_consumed, c_vpush, c_chunks;
 };
+
+// LDS slice entries are fetched on first touch, so a visit moves HBM traffic
+// in proportion to the vertices it touches, not to the partition size.
+constexpr uint32_t UNLOADED = 0xffffffffu;  // no distance or residual has this value
+
+__device__ __forceinline__ void touch(const ItemCtx& c, uint32_t vloc) {
+    if (c.st[vloc] == UNLOADED) atomicCAS(&c.st[vloc], UNLOADED, c.gstate[c.v0 + vloc]);
+}
 
 __device__ __forceinline__ float thr_of(const ItemCtx& c, uint32_t gv) {
     if (!c.mode) return c.eps;
@@ -298,6 +309,7 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
                     if (j + 1 == need) {
                         int32_t old = dev_xchg(&c.B.bhead[b], (int32_t)first);
                         c.B.cnext[ch] = old;
+                        if (old < 0) dev_add(&c.B.pqn[T], 1u);  // the buffer became non-empty
                         // publish the tail only after its slots are reserved
                         if (r0 == 0) dev_xchg(&c.B.btail[b], (int32_t)ch);
                         else dev_or(&c.B.ctl->err, (uint32_t)ERR_CORRUPT);
@@ -399,6 +411,7 @@ __device__ __forceinline__ void consume(ItemCtx& c, PassShared& S, int32_t head)
             uint32_t rv = 0;
             if (valid) {
                 ++c.c_consumed;
+                touch(c, vloc);
                 if (c.qt == Q_PPR) {
                     float mass = __uint_as_float(op.y);
                     float nr = atomicAdd((float*)&c.st[vloc], mass) + mass;
@@ -540,6 +553,7 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
             bool win_ = false;
             if (intra) {
                 ++c.c_intra;
+                touch(c, ul);
                 uint32_t old = atomicMin(&c.st[ul], nd);
                 if (nd < old) { ++c.c_improved; win_ = tas(c.bits, ul); }
             }
@@ -620,6 +634,7 @@ __device__ __forceinline__ void ppr_visit(ItemCtx& c, PassShared& S, uint32_t bu
             bool win_ = false;
             if (intra) {
                 ++c.c_intra;
+                touch(c, ul);
                 float old = atomicAdd((float*)&c.st[ul], share);
                 float nr = old + share;
                 float thr = thr_of(c, u);
@@ -647,22 +662,17 @@ __device__ __forceinline__ void ppr_visit(ItemCtx& c, PassShared& S, uint32_t bu
     if (t == 0) c.c_edges += edges;
 }
 
-// ------------------------------------------------------------ kernel
+// ------------------------------------------------------------ kernels
+// Pop work items of the current pass (own XCD's list first) and process
+// them until every list is exhausted.
 template <int WB>
-__global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B, PassCfg cfg, uint32_t slice_words) {
-    __shared__ PassShared S;
-    extern __shared__ uint32_t dyn[];
+__device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const PassCfg& cfg, unsigned long long& items) {
     const uint32_t t = threadIdx.x;
-    ItemCtx c;
-    c.g = g;
-    c.Q = Q;
-    c.B = B;
-    c.st = dyn;
-    c.bits = dyn + slice_words;
-    c.pass = B.ctl->pass;
-    c.c_edges = c.c_intra = c.c_improved = c.c_emitted = c.c_consumed = c.c_vpush = c.c_chunks = 0;
-    unsigned long long items = 0;
+    const GraphDev& g = c.g;
+    const QueryDev& Q = c.Q;
+    const BufDev& B = c.B;
     const uint32_t xcd = blockIdx.x % NXCD;
+    c.pass = B.ctl->pass;
     for (;;) {
         if (t == 0) {
             Item it;
@@ -695,8 +705,8 @@ __global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B
         const bool ppr = c.qt == Q_PPR;
         c.gp = (float*)(Q.state + off);
         c.gstate = ppr ? Q.state + off + g.nv : Q.state + off;
-        // stage the slice into LDS
-        for (uint32_t i = t; i < c.nvp; i += NT) c.st[i] = c.gstate[c.v0 + i];
+        // the slice is staged into LDS on first touch
+        for (uint32_t i = t; i < c.nvp; i += NT) c.st[i] = UNLOADED;
         for (uint32_t i = t; i < (c.nvp + 31) / 32; i += NT) c.bits[i] = 0u;
         if (t == 0) { S.nf = 0; S.ns = 0; S.cur = 0; }
         __syncthreads();
@@ -712,11 +722,28 @@ __global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B
         else if (c.qt == Q_BFS) sp_visit<0>(c, S, cfg.win_lv, cfg.yld_lv, budget);
         else sp_visit<WB>(c, S, cfg.win_sp, cfg.yld_sp, budget);
         flush(c, S);
-        // write the slice back
-        for (uint32_t i = t; i < c.nvp; i += NT) c.gstate[c.v0 + i] = c.st[i];
+        // write the touched part of the slice back
+        for (uint32_t i = t; i < c.nvp; i += NT) {
+            uint32_t x = c.st[i];
+            if (x != UNLOADED) c.gstate[c.v0 + i] = x;
+        }
         __syncthreads();
     }
-    // publish counters (block reduction, then one atomic per counter)
+}
+
+__device__ __forceinline__ void init_ctx(ItemCtx& c, const GraphDev& g, const QueryDev& Q, const BufDev& B,
+                                         uint32_t* dyn, uint32_t slice_words) {
+    c.g = g;
+    c.Q = Q;
+    c.B = B;
+    c.st = dyn;
+    c.bits = dyn + slice_words;
+    c.c_edges = c.c_intra = c.c_improved = c.c_emitted = c.c_consumed = c.c_vpush = c.c_chunks = 0;
+}
+
+__device__ __forceinline__ void publish_counters(const ItemCtx& c, unsigned long long items) {
+    const uint32_t t = threadIdx.x;
+    const BufDev& B = c.B;
     unsigned long long v[7] = {c.c_edges, c.c_intra, c.c_improved, c.c_emitted, c.c_consumed, c.c_vpush, c.c_chunks};
     unsigned long long* dst[7] = {&B.ctl->c_edges, &B.ctl->c_intra, &B.ctl->c_improved, &B.ctl->c_emitted,
                                   &B.ctl->c_consumed, &B.ctl->c_vpush, &B.ctl->c_chunks};
@@ -728,6 +755,71 @@ __global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B
         if ((t & 63) == 0 && x) dev_add(dst[k], x);
     }
     if (t == 0 && items) dev_add(&B.ctl->c_items, items);
+}
+
+// One pass (Algorithm 2's IntraPartProcess over the selected partitions).
+template <int WB>
+__global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B, PassCfg cfg, uint32_t slice_words) {
+    __shared__ PassShared S;
+    extern __shared__ uint32_t dyn[];
+    ItemCtx c;
+    init_ctx(c, g, Q, B, dyn, slice_words);
+    unsigned long long items = 0;
+    process_items<WB>(c, S, cfg, items);
+    publish_counters(c, items);
+}
+
+// Persistent form: one cooperative launch runs up to max_passes passes of
+// Algorithm 2 -- [learned scoring], selection (block 0), detachment into the
+// per-XCD work queues (all blocks), processing (all blocks) -- separated by
+// grid-wide barriers, and stops by itself when no buffer holds work.
+template <int WB>
+__global__ __launch_bounds__(NT) void k_persistent(GraphDev g, QueryDev Q, BufDev B, PassCfg cfg, uint32_t slice_words,
+                                                   uint32_t max_passes, const float* theta, float* score, GStat* gs) {
+    __shared__ PassShared S;
+    extern __shared__ uint32_t dyn[];
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    ItemCtx c;
+    init_ctx(c, g, Q, B, dyn, slice_words);
+    unsigned long long items = 0;
+    const uint32_t t = threadIdx.x;
+    const uint32_t dyn_words = slice_words + (slice_words + 31) / 32;
+    for (uint32_t pass = 0; pass < max_passes; ++pass) {
+        if (cfg.sched == S_LEARNED) {
+            if (blockIdx.x == 0) gstat_body(g, B, gs);
+            grid.sync();
+            // stage the weights in LDS when they fit, score partitions grid-wide
+            const bool lds_w = dyn_words >= (uint32_t)MLP_NPARAM;
+            if (lds_w)
+                for (uint32_t i = t; i < (uint32_t)MLP_NPARAM; i += NT) ((float*)dyn)[i] = theta[i];
+            __syncthreads();
+            const float* w = lds_w ? (const float*)dyn : theta;
+            const GStat s = *gs;
+            const uint32_t pnext = B.ctl->pass + 1;
+            for (uint32_t P = blockIdx.x * NT + t; P < g.np; P += gridDim.x * NT) {
+                float x[MLP_IN];
+                partition_features(g, B, s, pnext, P, x);
+                float y = mlp_forward(w, x);
+                score[P] = B.pcount[P] ? y : -3.0e38f;
+            }
+            grid.sync();
+        }
+        if (blockIdx.x == 0) {
+            const uint32_t cap = (dyn_words * 4u) / 12u;
+            select_body<NT>(g, B, cfg, (unsigned long long*)dyn, (unsigned int*)((unsigned long long*)dyn + cap), cap);
+        }
+        grid.sync();
+        if (B.ctl->pending_parts == 0 || B.ctl->err) break;
+        const uint32_t nsel = B.ctl->nsel;
+        const uint32_t nqp = (Q.nq + WAVE - 1) / WAVE * WAVE;
+        const unsigned long long total = (unsigned long long)nsel * nqp;
+        for (unsigned long long i = (unsigned long long)blockIdx.x * NT + t; i < total; i += (unsigned long long)gridDim.x * NT)
+            worklist_one(B, Q, (uint32_t)(i / nqp), (uint32_t)(i % nqp));
+        grid.sync();
+        process_items<WB>(c, S, cfg, items);
+        grid.sync();
+    }
+    publish_counters(c, items);
 }
 
 size_t process_dyn_lds(uint32_t vpmax) { return ((size_t)vpmax + (vpmax + 31) / 32) * 4; }
@@ -751,6 +843,25 @@ const void* process_kernel_ptr(int wbytes) {
     case 2: return (const void*)k_process<2>;
     default: return (const void*)k_process<4>;
     }
+}
+const void* persistent_kernel_ptr(int wbytes) {
+    switch (wbytes) {
+    case 0: return (const void*)k_persistent<0>;
+    case 1: return (const void*)k_persistent<1>;
+    case 2: return (const void*)k_persistent<2>;
+    default: return (const void*)k_persistent<4>;
+    }
+}
+
+hipError_t launch_persistent(const GraphDev& g, const QueryDev& Q, const BufDev& B, const PassCfg& cfg,
+                             uint32_t blocks, uint32_t vpmax, uint32_t max_passes, const float* theta, float* score,
+                             void* gstat, hipStream_t s) {
+    size_t dyn = process_dyn_lds(vpmax);
+    uint32_t sw = vpmax;
+    GStat* gs = (GStat*)gstat;
+    void* args[] = {(void*)&g, (void*)&Q, (void*)&B, (void*)&cfg, (void*)&sw, (void*)&max_passes,
+                    (void*)&theta, (void*)&score, (void*)&gs};
+    return hipLaunchCooperativeKernel(persistent_kernel_ptr(g.wbytes), dim3(blocks), dim3(NT), args, dyn, s);
 }
 int process_threads() { return NT; }
 size_t process_static_lds() { return sizeof(PassShared); }

@@ -28,6 +28,9 @@ hipError_t launch_digest(const QueryDev&, uint32_t, unsigned long long*, hipStre
 hipError_t launch_mlp_score(const GraphDev&, const BufDev&, const float*, float*, float*, void*, uint32_t, hipStream_t);
 size_t gstat_bytes();
 const void* process_kernel_ptr(int wbytes);
+const void* persistent_kernel_ptr(int wbytes);
+hipError_t launch_persistent(const GraphDev&, const QueryDev&, const BufDev&, const PassCfg&, uint32_t, uint32_t,
+                             uint32_t, const float*, float*, void*, hipStream_t);
 }  // namespace fk
 
 static thread_local std::string g_err;
@@ -79,7 +82,7 @@ struct fork_ctx {
     // partition summaries
     uint32_t *d_pcount = nullptr, *d_pbest_sp = nullptr, *d_pbest_lv = nullptr, *d_pbest_pr = nullptr,
              *d_pfirst = nullptr, *d_plast = nullptr, *d_pvisits = nullptr, *d_pn = nullptr,
-             *d_sel = nullptr;
+             *d_sel = nullptr, *d_pqn = nullptr;
     float* d_score = nullptr;
     float* d_mlp = nullptr;
     unsigned char* d_gstat = nullptr;
@@ -108,8 +111,9 @@ struct fork_ctx {
     fork_stats_t stats{};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> pev;  // pass-kernel timing events (profile mode)
-    int blocks_per_cu = 1, num_cu = 1;
+    int blocks_per_cu = 1, num_cu = 1, pers_blocks_per_cu = 0;
     uint32_t vpmax = 1;  // largest partition (vertices)
+    double wmean = 1.0;  // mean edge weight
 };
 
 extern "C" const char* fork_last_error(void) { return g_err.c_str(); }
@@ -152,7 +156,7 @@ extern "C" void fork_destroy(fork_ctx* c) {
     free_wave(c);
     void* ptrs[] = {c->d_rowptr, c->d_col, c->d_w, c->d_pstart, c->d_vpart, c->d_chunks, c->d_cnext,
                     c->d_ccount, c->d_ring, c->d_pcount, c->d_pbest_sp, c->d_pbest_lv, c->d_pbest_pr,
-                    c->d_pfirst, c->d_plast, c->d_pvisits, c->d_pn, c->d_sel, c->d_score, c->d_mlp,
+                    c->d_pfirst, c->d_plast, c->d_pvisits, c->d_pn, c->d_sel, c->d_pqn, c->d_score, c->d_mlp,
                     c->d_ctl, c->d_gstat};
     for (void* p : ptrs) if (p) hipFree(p);
     if (c->h_ctl) hipHostFree(c->h_ctl);
@@ -227,6 +231,8 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
         }
     }
     if (ws && wmax > 0x7fffffffu) return fail(FORK_E_INVALID, "weights must be < 2^31");
+    double wsum = 0;
+    if (ws) for (uint64_t e = 0; e < ne; ++e) wsum += ws[e];
 
     fork_ctx* c = new fork_ctx();
     c->device = cfg.device;
@@ -234,6 +240,7 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     c->nv = nv;
     c->ne = ne;
     c->wbytes = !ws ? 0 : (wmax <= 0xff ? 1 : (wmax <= 0xffff ? 2 : 4));
+    c->wmean = (ws && ne) ? wsum / (double)ne : 1.0;
     c->h_rowptr.resize(nv + 1);
     for (uint32_t v = 0; v <= nv; ++v) c->h_rowptr[v] = (uint32_t)rps[v];
     int rc = FORK_OK;
@@ -293,7 +300,7 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     if ((rc = dalloc(&c->d_ring, c->nch))) return cleanup(rc);
     // partition summaries
     uint32_t** parr[] = {&c->d_pcount, &c->d_pbest_sp, &c->d_pbest_lv, &c->d_pbest_pr, &c->d_pfirst,
-                         &c->d_plast, &c->d_pvisits, &c->d_pn, &c->d_sel};
+                         &c->d_plast, &c->d_pvisits, &c->d_pn, &c->d_sel, &c->d_pqn};
     for (auto pp : parr) if ((rc = dalloc(pp, c->np + 1))) return cleanup(rc);
     if ((rc = dalloc(&c->d_score, c->np + 1))) return cleanup(rc);
     if ((rc = dalloc(&c->d_mlp, fk::MLP_NPARAM))) return cleanup(rc);
@@ -315,6 +322,11 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, fk::process_threads(), dyn) == hipSuccess && occ > 0)
             c->blocks_per_cu = occ;
+        const void* pk = fk::persistent_kernel_ptr(c->wbytes);
+        occ = 0;
+        if (hipFuncSetAttribute(pk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pk, fk::process_threads(), dyn) == hipSuccess)
+            c->pers_blocks_per_cu = occ;
     }
     *out = c;
     return FORK_OK;
@@ -413,7 +425,7 @@ static fk::BufDev buf_dev(const fork_ctx* c) {
     B.ccount = c->d_ccount; B.ring = c->d_ring; B.nch = c->nch; B.pcount = c->d_pcount;
     B.pbest_sp = c->d_pbest_sp; B.pbest_lv = c->d_pbest_lv; B.pbest_pr = c->d_pbest_pr;
     B.pfirst = c->d_pfirst; B.plast = c->d_plast; B.pvisits = c->d_pvisits; B.pn = c->d_pn;
-    B.sel = c->d_sel; B.score = c->d_score; B.items = c->d_items; B.item_cap = c->item_cap; B.ctl = c->d_ctl;
+    B.sel = c->d_sel; B.pqn = c->d_pqn; B.score = c->d_score; B.items = c->d_items; B.item_cap = c->item_cap; B.ctl = c->d_ctl;
     return B;
 }
 
@@ -468,6 +480,7 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
     HIPCHK(hipMemsetAsync(c->d_plast, 0, (c->np + 1) * 4ull, s));
     HIPCHK(hipMemsetAsync(c->d_pvisits, 0, (c->np + 1) * 4ull, s));
     HIPCHK(hipMemsetAsync(c->d_pn, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetAsync(c->d_pqn, 0, (c->np + 1) * 4ull, s));
     if (c->nch < nq + 64ull) return fail(FORK_E_CAPACITY, "operation pool too small for %u queries", nq);
     fk::Ctl ctl0{};
     ctl0.ring_head = nq;
@@ -483,6 +496,7 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
     const uint32_t blocks = (uint32_t)std::max(1, c->num_cu * c->blocks_per_cu);
     uint32_t batch = 1;
     bool done = false;
+    uint32_t pass_mark = 0;
     const char* prog = getenv("FORK_PROGRESS");
     const double prog_every = prog ? atof(prog) : 0.0;  // seconds between progress lines (0 = off)
     auto t_start = std::chrono::steady_clock::now();
@@ -496,15 +510,29 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
             c->pev.resize(2 * nb, nullptr);
             for (size_t k = old; k < c->pev.size(); ++k) HIPCHK(hipEventCreate(&c->pev[k]));
         }
-        for (uint32_t k = 0; k < nb; ++k) {
-            if (pc.sched == fk::S_LEARNED) HIPCHK(fk::launch_mlp_score(g, B, c->d_mlp, c->d_score, nullptr, c->d_gstat, 0, s));
-            HIPCHK(fk::launch_select(g, B, pc, s));
-            HIPCHK(fk::launch_worklist(B, Q, pc.kmax, s));
-            if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k], s));
-            HIPCHK(fk::launch_process(g, Q, B, pc, blocks, c->vpmax, s));
-            if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k + 1], s));
+        if (o.persistent) {
+            // one cooperative launch runs up to 64 passes per batch slot on the device
+            if (c->pers_blocks_per_cu <= 0) return fail(FORK_E_DEVICE, "persistent kernel does not fit on a CU");
+            const uint32_t pblocks = (uint32_t)(c->num_cu * c->pers_blocks_per_cu);
+            if (o.profile) HIPCHK(hipEventRecord(c->pev[0], s));
+            uint64_t lp = 64ull * batch;
+            if (passes_left != ~0ull) lp = std::min<uint64_t>(lp, passes_left);
+            HIPCHK(fk::launch_persistent(g, Q, B, pc, pblocks, c->vpmax, (uint32_t)lp, c->d_mlp, c->d_score,
+                                         c->d_gstat, s));
+            if (o.profile) HIPCHK(hipEventRecord(c->pev[1], s));
+            nb = 1;
+        } else {
+            for (uint32_t k = 0; k < nb; ++k) {
+                if (pc.sched == fk::S_LEARNED)
+                    HIPCHK(fk::launch_mlp_score(g, B, c->d_mlp, c->d_score, nullptr, c->d_gstat, 0, s));
+                HIPCHK(fk::launch_select(g, B, pc, s));
+                HIPCHK(fk::launch_worklist(B, Q, pc.kmax, s));
+                if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k], s));
+                HIPCHK(fk::launch_process(g, Q, B, pc, blocks, c->vpmax, s));
+                if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k + 1], s));
+            }
         }
-        if (passes_left != ~0ull) passes_left -= nb;
+        if (passes_left != ~0ull && !o.persistent) passes_left -= nb;
         HIPCHK(hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(fk::Ctl), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (o.profile) {
@@ -522,6 +550,11 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
                         c->nch, nq);
         if (h.err) return fail(FORK_E_DEVICE, "device error flags 0x%x", h.err);
         if (h.pending_parts == 0) done = true;
+        if (o.persistent && passes_left != ~0ull) {
+            uint64_t used = h.pass - pass_mark;
+            pass_mark = h.pass;
+            passes_left = used >= passes_left ? 0 : passes_left - used;
+        }
         batch = std::min<uint32_t>(batch * 2, 64);
         if (prog_every > 0) {
             auto now = std::chrono::steady_clock::now();
@@ -601,11 +634,15 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     cfg.seed = (uint32_t)o.seed;
     cfg.mu = o.edge_budget_mu;
     // value windows / yield ranges (heuristic 2): SSSP in weight units, BFS in levels
-    uint32_t delta = o.delta ? o.delta : (c->wbytes ? 1024u : 4u);
-    cfg.win_sp = std::max(1u, delta / 4);
+    // Heuristic 2 (Section 5.1) with the paper's Delta-stepping guidance:
+    // process in windows of about two mean edge weights, yield once a visit
+    // has advanced `delta` past its first value (default: 64 mean weights).
+    const double wm = c->wbytes ? c->wmean : 1.0;
+    uint32_t delta = o.delta ? o.delta : (uint32_t)std::min(1.0e9, 64.0 * wm);
+    cfg.win_sp = std::max<uint32_t>(1u, (uint32_t)(2.0 * wm));
     cfg.yld_sp = delta;
     cfg.win_lv = 1;
-    cfg.yld_lv = c->wbytes ? 4u : std::max(1u, delta);
+    cfg.yld_lv = o.delta ? std::max<uint32_t>(1u, (uint32_t)(o.delta / wm)) : 64u;
     if (o.scheduler == FORK_SCHED_LEARNED) {
         HIPCHK(hipMemcpyAsync(c->d_mlp, o.mlp_weights, fk::MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
     }
@@ -624,11 +661,11 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
         waves.push_back({q0, n});
         q0 += n;
     }
-    uint32_t wmax = 0;
-    for (auto& w : waves) wmax = std::max(wmax, w.second);
-    cfg.kmax = o.parts_per_pass ? o.parts_per_pass
-                                : std::min<uint32_t>(c->np, std::max<uint32_t>(8, (16384 + wmax - 1) / wmax));
-    if (cfg.kmax == 0 || cfg.kmax > c->np) cfg.kmax = c->np;
+    // partitions per pass: a fixed count if asked for, else as many as it
+    // takes to queue items_per_pass work items (default: 16 per workgroup slot)
+    const uint32_t slots = (uint32_t)std::max(1, c->num_cu * c->blocks_per_cu);
+    cfg.kmax = o.parts_per_pass ? std::min<uint32_t>(o.parts_per_pass, c->np) : c->np;
+    cfg.target_items = o.parts_per_pass ? 0u : (o.items_per_pass ? o.items_per_pass : 16u * slots);
     c->stats = fork_stats_t{};
     c->stats.num_partitions = c->np;
     c->stats.weight_bytes = (uint32_t)c->wbytes;

@@ -223,3 +223,43 @@ def test_explicit_waves_digests():
     with pytest.raises(fork.ForkError):
         fg.fetch(0)
     fg.close()
+
+
+@pytest.mark.parametrize("sched", ["priority", "fifo"])
+def test_persistent_kernel_parity(sched):
+    """The persistent cooperative kernel gives the same exact SSSP/BFS results
+    and valid PPR results as the per-pass kernels."""
+    fork = _fork()
+    g = fi.rmat(12, seed=1, weights=(1, 255), weight_seed=101)
+    s1 = fi.sources_uniform(g, 24, 4)
+    s2 = fi.sources_uniform(g, 16, 5)
+    s3 = fi.sources_uniform(g, 16, 6)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=512)
+    fg.submit("sssp", s1)
+    fg.submit("bfs", s2)
+    fg.submit("ppr", s3, alpha=ALPHA, epsilon=1e-6, eps_mode=1)
+    say("persistent", sched)
+    fg.run(scheduler=sched, persistent=1, max_passes=100000)
+    d = np.stack([fg.fetch(i) for i in range(24)])
+    lv = np.stack([fg.fetch(24 + i) for i in range(16)])
+    np.testing.assert_array_equal(d, oracle.sssp(g, s1))
+    np.testing.assert_array_equal(lv, oracle.bfs(g, s2))
+    P = np.stack([fg.fetch(40 + i, fork.FIELD_P) for i in range(16)])
+    R = np.stack([fg.fetch(40 + i, fork.FIELD_R) for i in range(16)])
+    st = fg.stats()
+    fg.close()
+    check_ppr(g, s3, P, R, 1e-6, 1)
+    assert st["passes"] > 1
+
+
+def test_persistent_grid():
+    fork = _fork()
+    g = fi.grid(128, 96, weights=(1, 1000), weight_seed=9)
+    s1 = fi.sources_uniform(g, 32, 11)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=1024)
+    fg.submit("sssp", s1)
+    say("persistent grid")
+    fg.run(persistent=1, max_passes=1000000)
+    d = np.stack([fg.fetch(i) for i in range(32)])
+    fg.close()
+    np.testing.assert_array_equal(d, oracle.sssp(g, s1))
