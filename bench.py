@@ -69,6 +69,31 @@ def cpu_baseline(g, queries, spec, budget_s=15.0):
                       f"{t_total:.1f} s, fp64 forward push / Dijkstra / BFS, one query per thread"}
 
 
+def compare_learned(fg, args, run_kw, nq, rule_value):
+    """Time the learned scheduler on the same queries; SSSP/BFS digests must match the rule run's."""
+    import paper_2103_14915_amd as fork
+    import torch
+    theta = np.load(args.compare_learned)
+    kinds = fg.types
+    rule_dig = [fg.digest(i) for i in range(nq)]
+    kw = dict(run_kw, scheduler="learned", mlp_weights=theta)
+    fg.run(**kw)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fg.run(**kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = fg.stats()
+    learned_value = nq * args.steps / dt
+    same = all((fg.digest(i)["hash"], fg.digest(i)["count"]) == (rule_dig[i]["hash"], rule_dig[i]["count"])
+               for i in range(nq) if kinds[i] != fork.PPR)
+    return {"rule_queries_per_s": rule_value, "learned_queries_per_s": learned_value,
+            "speedup": learned_value / rule_value, "sssp_bfs_digests_identical": bool(same),
+            "learned_passes_per_step": st["passes"], "learned_edges_per_step": st["edges"],
+            "weights": os.path.basename(args.compare_learned)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +112,8 @@ def main():
     ap.add_argument("--max-queries", type=int, default=0, help="queries resident per wave (0 = auto)")
     ap.add_argument("--persistent", action="store_true", help="one persistent cooperative kernel per batch of passes")
     ap.add_argument("--items-per-pass", type=int, default=0, help="work items queued per pass (0 = auto)")
+    ap.add_argument("--compare-learned", default="", help="MLP weights (.npy): also time the learned scheduler "
+                    "on the same workload and report the speedup over the rule-based one")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -170,6 +197,8 @@ def main():
                    "vertex_pushes_per_step": tot["vertex_pushes"] / args.steps,
                    "work_items_per_step": tot["work_items"] / args.steps},
     }
+    if args.compare_learned:
+        line["learned_vs_rule"] = compare_learned(fg, args, run_kw, nq, value)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, queries, spec, args.cpu_budget)
     fg.close()

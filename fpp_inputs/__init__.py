@@ -205,6 +205,10 @@ WORKLOADS = {
     "rmat22_mixed16384": dict(kind="rmat", scale=22, weights=(1, 255), seeds=(4, 104, 204),
                               queries=[("sssp", 8192, "mixed"), ("bfs", 4096, "mixed"),
                                        ("ppr", 4096, "mixed")], alpha=0.15, epsilon=1e-6, eps_mode=1),
+    # scaled-down stand-in of the scale-23 SSSP+PPR mix (same generator, same mix, fewer vertices/queries)
+    "rmat20_sssp_ppr2048": dict(kind="rmat", scale=20, weights=(1, 255), seeds=(6, 106, 206),
+                                queries=[("sssp", 1024, "mixed"), ("ppr", 1024, "mixed")],
+                                alpha=0.15, epsilon=1e-6, eps_mode=1),
     "rmat23_sssp_ppr65536": dict(kind="rmat", scale=23, weights=(1, 255), seeds=(5, 105, 205),
                                  queries=[("sssp", 32768, "mixed"), ("ppr", 32768, "mixed")],
                                  alpha=0.15, epsilon=1e-6, eps_mode=1),

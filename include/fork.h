@@ -87,6 +87,7 @@ typedef struct {
     int      profile;          /* 1 = time every pass kernel with HIP events     */
     uint32_t items_per_pass;   /* (partition, query) items queued per pass when
                                   parts_per_pass is 0 (0 = auto)                 */
+    int      trace;            /* 1 = record scheduler traces (see fork_trace)   */
 } fork_run_opts;
 
 /* Counters accumulated over the last fork_run (all waves). */
@@ -173,6 +174,41 @@ int fork_run(fork_ctx *ctx, const fork_run_opts *opts);
  */
 int fork_fetch(fork_ctx *ctx, uint32_t query_id, int field, void *dst,
                uint64_t dst_bytes, int dst_on_device);
+
+/*
+ * Scheduler trace of the last run made with opts.trace = 1 (the run is done
+ * twice per wave: once to learn the final state, once traced).  One record
+ * per visited partition per pass, FORK_TRACE_WIDTH floats each:
+ *   [0..15] the partition's 16 buffer-statistics features at selection,
+ *   [16] useful work of the visits (SSSP/BFS: vertex expansions whose
+ *        distance was already final; PPR: vertex pushes),
+ *   [17] all work of the visits (expansions / pushes), [18] pass, [19] partition.
+ * Writes min(cap, available) records to dst (host); *n gets the available count.
+ */
+#define FORK_TRACE_WIDTH 20
+int fork_trace(fork_ctx *ctx, float *dst, uint64_t cap, uint64_t *n);
+
+/*
+ * Learned scheduler network (an addition to the paper's priority functor,
+ * Section 5.2): y = W3 relu(W2 relu(W1 x + b1) + b2) + b3, sizes
+ * 16 -> 64 -> 64 -> 1, fp32, flat parameters theta[5313] laid out
+ * W1[64][16] | b1[64] | W2[64][64] | b2[64] | W3[64] | b3.  All pointers are
+ * host pointers; the work runs on the current HIP device.  x is [n][16].
+ *
+ * fork_mlp_forward: y[n] = scores.
+ * fork_mlp_grad:    loss = mean (y - t)^2 over the n samples and its gradient
+ *                   grad[5313] (forward and backward kernels on the GPU).
+ * fork_mlp_train:   `steps` Adam steps (lr, beta 0.9/0.999, eps 1e-8) on
+ *                   mini-batches of `batch` samples drawn as seeded epochs;
+ *                   theta is updated in place; losses[steps] (may be NULL)
+ *                   receives each step's batch loss.
+ */
+int fork_mlp_forward(const float *theta, const float *x, uint64_t n, float *y);
+int fork_mlp_grad(const float *theta, const float *x, const float *t, uint64_t n,
+                  float *grad, float *loss);
+int fork_mlp_train(float *theta, const float *x, const float *t, uint64_t n,
+                   uint32_t steps, uint32_t batch, float lr, uint64_t seed,
+                   float *losses);
 
 /* Copy the counters of the last run into *dst (dst_bytes >= sizeof). */
 int fork_stats(fork_ctx *ctx, void *dst, uint64_t dst_bytes);

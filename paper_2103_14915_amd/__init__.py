@@ -51,7 +51,8 @@ class fork_run_opts(ctypes.Structure):
     _fields_ = [("scheduler", ctypes.c_int), ("parts_per_pass", ctypes.c_uint32), ("delta", ctypes.c_uint32),
                 ("edge_budget_mu", ctypes.c_float), ("max_passes", ctypes.c_uint64),
                 ("stream", ctypes.c_void_p), ("mlp_weights", ctypes.c_void_p), ("persistent", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("profile", ctypes.c_int), ("items_per_pass", ctypes.c_uint32)]
+                ("seed", ctypes.c_uint64), ("profile", ctypes.c_int), ("items_per_pass", ctypes.c_uint32),
+                ("trace", ctypes.c_int)]
 
 
 class fork_stats_t(ctypes.Structure):
@@ -72,7 +73,8 @@ class fork_digest(ctypes.Structure):
 
 
 EXPORTS = ["fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions",
-           "fork_destroy", "fork_last_error"]
+           "fork_trace", "fork_destroy", "fork_last_error", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train"]
+TRACE_WIDTH = 20
 
 
 def _load():
@@ -87,10 +89,15 @@ def _load():
     lib.fork_fetch.argtypes = [P, U32, I, P, U64, I]
     lib.fork_stats.argtypes = [P, P, U64]
     lib.fork_partitions.argtypes = [P, P, U32, ctypes.POINTER(U32)]
+    lib.fork_trace.argtypes = [P, P, U64, ctypes.POINTER(U64)]
+    lib.fork_mlp_forward.argtypes = [P, P, U64, P]
+    lib.fork_mlp_grad.argtypes = [P, P, P, U64, P, P]
+    lib.fork_mlp_train.argtypes = [P, P, P, U64, U32, U32, ctypes.c_float, U64, P]
     lib.fork_destroy.argtypes = [P]
     lib.fork_destroy.restype = None
     lib.fork_last_error.restype = ctypes.c_char_p
-    for n in ("fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions"):
+    for n in ("fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions",
+              "fork_trace", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train"):
         getattr(lib, n).restype = I
     return lib
 
@@ -173,7 +180,7 @@ class ForkGraph:
         return first.value
 
     def run(self, scheduler="priority", parts_per_pass=0, delta=0, edge_budget_mu=0.0, max_passes=0,
-            stream=None, mlp_weights=None, persistent=0, seed=0, profile=0, items_per_pass=0):
+            stream=None, mlp_weights=None, persistent=0, seed=0, profile=0, items_per_pass=0, trace=0):
         s = SCHEDS[scheduler] if isinstance(scheduler, str) else int(scheduler)
         w = None
         if mlp_weights is not None:
@@ -184,7 +191,7 @@ class ForkGraph:
         if stream is not None:
             sp = stream if isinstance(stream, int) else stream.cuda_stream
         o = fork_run_opts(s, parts_per_pass, delta, edge_budget_mu, max_passes, sp,
-                          None if w is None else w.ctypes.data, persistent, seed, profile, items_per_pass)
+                          None if w is None else w.ctypes.data, persistent, seed, profile, items_per_pass, trace)
         _check(lib.fork_run(self._ctx, ctypes.byref(o)))
 
     def fetch(self, qid, field=None, out=None):
@@ -206,6 +213,15 @@ class ForkGraph:
         _check(lib.fork_fetch(self._ctx, qid, FIELD_DIGEST, ctypes.byref(d), ctypes.sizeof(d), 0))
         return {n: getattr(d, n) for n, _ in d._fields_}
 
+    def trace(self) -> np.ndarray:
+        """Scheduler trace of the last run(trace=1): [records, 20] float32."""
+        n = ctypes.c_uint64()
+        _check(lib.fork_trace(self._ctx, None, 0, ctypes.byref(n)))
+        out = np.empty((n.value, TRACE_WIDTH), np.float32)
+        if n.value:
+            _check(lib.fork_trace(self._ctx, ctypes.c_void_p(out.ctypes.data), n.value, ctypes.byref(n)))
+        return out
+
     def stats(self) -> dict:
         s = fork_stats_t()
         _check(lib.fork_stats(self._ctx, ctypes.byref(s), ctypes.sizeof(s)))
@@ -214,3 +230,34 @@ class ForkGraph:
 
 def last_error() -> str:
     return lib.fork_last_error().decode()
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, np.float32))
+
+
+def mlp_forward(theta, x) -> np.ndarray:
+    """Scores of the partition-scoring MLP, computed on the GPU."""
+    th, xx = _f32(theta), _f32(x).reshape(-1, 16)
+    y = np.empty(xx.shape[0], np.float32)
+    _check(lib.fork_mlp_forward(th.ctypes.data, xx.ctypes.data, xx.shape[0], y.ctypes.data))
+    return y
+
+
+def mlp_grad(theta, x, t):
+    """(loss, grad) of the mean squared error, forward and backward on the GPU."""
+    th, xx, tt = _f32(theta), _f32(x).reshape(-1, 16), _f32(t)
+    g = np.empty(MLP_NPARAM, np.float32)
+    loss = np.zeros(1, np.float32)
+    _check(lib.fork_mlp_grad(th.ctypes.data, xx.ctypes.data, tt.ctypes.data, xx.shape[0], g.ctypes.data,
+                             loss.ctypes.data))
+    return float(loss[0]), g
+
+
+def mlp_train(theta, x, t, steps, batch=256, lr=1e-3, seed=0):
+    """Adam training on the GPU; returns (theta, per-step losses)."""
+    th, xx, tt = _f32(theta).copy(), _f32(x).reshape(-1, 16), _f32(t)
+    losses = np.empty(max(steps, 1), np.float32)
+    _check(lib.fork_mlp_train(th.ctypes.data, xx.ctypes.data, tt.ctypes.data, xx.shape[0], steps, batch, lr, seed,
+                              losses.ctypes.data))
+    return th, losses[:steps]

@@ -62,6 +62,7 @@ struct QueryDev {
     const float* qeps;        // [qc]
     const uint32_t* qmode;    // [qc]
     uint32_t* state;          // state words; SSSP/BFS: int32[V]; PPR: p f32[V] then r f32[V]
+    const uint32_t* final_state;  // trace runs: final state of the same wave (same layout), else NULL
 };
 
 struct BufDev {
@@ -84,6 +85,8 @@ struct BufDev {
     uint32_t* pqn;            // [np] (partition, query) buffers holding operations
     uint32_t* sel;            // [max parts per pass] selected partitions
     float* score;             // [np] learned score (LEARNED policy)
+    float* tr_useful;         // trace runs: [np] useful work of the pass's visits
+    float* tr_work;           // trace runs: [np] vertex expansions / pushes of the visits
     Item* items;              // [NXCD * item_cap]
     uint32_t item_cap;
     Ctl* ctl;
@@ -98,6 +101,7 @@ struct PassCfg {
     float mu;                 // yield budget H1: mu * |E_P| / items_P (0 = off)
     uint32_t seed;
     uint32_t mixed;           // more than one query type in the wave
+    uint32_t trace;           // record per-partition usefulness of each visit
 };
 
 __host__ __device__ inline unsigned long long mix64(unsigned long long z) {

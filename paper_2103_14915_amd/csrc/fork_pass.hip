@@ -130,6 +130,9 @@ struct ItemCtx {
     uint32_t* bits;     // LDS in-frontier flags
     // per-thread counters
     unsigned long long c_edges, c_intra, c_improved, c_emitted, c_consumed, c_vpush, c_chunks;
+    // per-item usefulness (trace runs): work units whose value was final / all
+    float it_useful, it_work;
+    const uint32_t* gfinal;  // final state of the query (trace runs), else NULL
 };
 
 // LDS slice entries are fetched on first touch, so a visit moves HBM traffic
@@ -527,9 +530,14 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
             atomicAnd(&c.bits[v >> 5], ~(1u << (v & 31)));
             uint32_t gv = c.v0 + v;
             uint32_t r0 = c.g.rowptr[gv], r1 = c.g.rowptr[gv + 1];
-            S.bval[j] = c.st[v];
+            uint32_t dv = c.st[v];
+            S.bval[j] = dv;
             S.brow[j] = r0;
             S.bpre[j] = r1 - r0;
+            if (c.gfinal) {  // trace run: an expansion is useful when its distance is final
+                c.it_work += 1.f;
+                c.it_useful += (dv == c.gfinal[gv]) ? 1.f : 0.f;
+            }
         }
         __syncthreads();
         if (t == 0) c.c_vpush += nb;
@@ -606,6 +614,7 @@ __device__ __forceinline__ void ppr_visit(ItemCtx& c, PassShared& S, uint32_t bu
                 c.st[v] = 0u;
                 atomicAdd(&c.gp[gv], a * mass);
                 ++pushed;
+                if (c.gfinal) { c.it_work += 1.f; c.it_useful += 1.f; }  // a push always moves mass to p
                 if (deg) { share = (1.f - a) * mass / (float)deg; push_deg = deg; }
             }
             S.bval[j] = __float_as_uint(share);
@@ -705,6 +714,9 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
         const bool ppr = c.qt == Q_PPR;
         c.gp = (float*)(Q.state + off);
         c.gstate = ppr ? Q.state + off + g.nv : Q.state + off;
+        c.gfinal = (cfg.trace && Q.final_state) ? Q.final_state + off : nullptr;
+        c.it_useful = 0.f;
+        c.it_work = 0.f;
         // the slice is staged into LDS on first touch
         for (uint32_t i = t; i < c.nvp; i += NT) c.st[i] = UNLOADED;
         for (uint32_t i = t; i < (c.nvp + 31) / 32; i += NT) c.bits[i] = 0u;
@@ -726,6 +738,15 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
         for (uint32_t i = t; i < c.nvp; i += NT) {
             uint32_t x = c.st[i];
             if (x != UNLOADED) c.gstate[c.v0 + i] = x;
+        }
+        if (c.gfinal) {
+            float u = c.it_useful, w = c.it_work;
+#pragma unroll
+            for (int o = 32; o; o >>= 1) { u += __shfl_xor(u, o); w += __shfl_xor(w, o); }
+            if ((t & 63) == 0 && w > 0.f) {
+                atomicAdd(&B.tr_useful[c.P], u);
+                atomicAdd(&B.tr_work[c.P], w);
+            }
         }
         __syncthreads();
     }

@@ -27,6 +27,10 @@ hipError_t launch_seed(const GraphDev&, const QueryDev&, const BufDev&, const ui
 hipError_t launch_digest(const QueryDev&, uint32_t, unsigned long long*, hipStream_t);
 hipError_t launch_mlp_score(const GraphDev&, const BufDev&, const float*, float*, float*, void*, uint32_t, hipStream_t);
 size_t gstat_bytes();
+hipError_t launch_mlp_grad(const float*, const float*, const float*, const uint32_t*, uint32_t, float*, float*,
+                           hipStream_t);
+hipError_t launch_adam(float*, const float*, float*, float*, uint32_t, float, hipStream_t);
+hipError_t launch_mlp_forward(const float*, const float*, uint32_t, float*, hipStream_t);
 const void* process_kernel_ptr(int wbytes);
 const void* persistent_kernel_ptr(int wbytes);
 hipError_t launch_persistent(const GraphDev&, const QueryDev&, const BufDev&, const PassCfg&, uint32_t, uint32_t,
@@ -85,6 +89,11 @@ struct fork_ctx {
              *d_sel = nullptr, *d_pqn = nullptr;
     float* d_score = nullptr;
     float* d_mlp = nullptr;
+    float* d_feat = nullptr;       // [np*16] features (trace runs)
+    float* d_tr = nullptr;         // [2*np] useful / work per partition (trace runs)
+    uint32_t* d_final = nullptr;   // final state of the traced wave
+    size_t final_words = 0;
+    std::vector<float> trace;      // records of FORK_TRACE_WIDTH floats
     unsigned char* d_gstat = nullptr;
     fk::Ctl* d_ctl = nullptr;
     fk::Ctl* h_ctl = nullptr;  // pinned
@@ -157,7 +166,7 @@ extern "C" void fork_destroy(fork_ctx* c) {
     void* ptrs[] = {c->d_rowptr, c->d_col, c->d_w, c->d_pstart, c->d_vpart, c->d_chunks, c->d_cnext,
                     c->d_ccount, c->d_ring, c->d_pcount, c->d_pbest_sp, c->d_pbest_lv, c->d_pbest_pr,
                     c->d_pfirst, c->d_plast, c->d_pvisits, c->d_pn, c->d_sel, c->d_pqn, c->d_score, c->d_mlp,
-                    c->d_ctl, c->d_gstat};
+                    c->d_ctl, c->d_gstat, c->d_feat, c->d_tr, c->d_final};
     for (void* p : ptrs) if (p) hipFree(p);
     if (c->h_ctl) hipHostFree(c->h_ctl);
     for (auto& e : c->ev) if (e) hipEventDestroy(e);
@@ -305,6 +314,8 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     if ((rc = dalloc(&c->d_score, c->np + 1))) return cleanup(rc);
     if ((rc = dalloc(&c->d_mlp, fk::MLP_NPARAM))) return cleanup(rc);
     if ((rc = dalloc(&c->d_gstat, fk::gstat_bytes()))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_feat, (size_t)(c->np + 1) * fk::MLP_IN))) return cleanup(rc);
+    if ((rc = dalloc(&c->d_tr, (size_t)(c->np + 1) * 2))) return cleanup(rc);
     if ((rc = dalloc(&c->d_ctl, 1))) return cleanup(rc);
     if (hipHostMalloc((void**)&c->h_ctl, sizeof(fk::Ctl), hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(FORK_E_NOMEM, "hipHostMalloc failed"));
@@ -425,12 +436,13 @@ static fk::BufDev buf_dev(const fork_ctx* c) {
     B.ccount = c->d_ccount; B.ring = c->d_ring; B.nch = c->nch; B.pcount = c->d_pcount;
     B.pbest_sp = c->d_pbest_sp; B.pbest_lv = c->d_pbest_lv; B.pbest_pr = c->d_pbest_pr;
     B.pfirst = c->d_pfirst; B.plast = c->d_plast; B.pvisits = c->d_pvisits; B.pn = c->d_pn;
-    B.sel = c->d_sel; B.pqn = c->d_pqn; B.score = c->d_score; B.items = c->d_items; B.item_cap = c->item_cap; B.ctl = c->d_ctl;
+    B.sel = c->d_sel; B.pqn = c->d_pqn; B.score = c->d_score;
+    B.tr_useful = c->d_tr; B.tr_work = c->d_tr + c->np; B.items = c->d_items; B.item_cap = c->item_cap; B.ctl = c->d_ctl;
     return B;
 }
 
 static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& o, hipStream_t s,
-                    const fk::PassCfg& cfg, uint64_t& passes_left) {
+                    const fk::PassCfg& cfg, uint64_t& passes_left, bool trace) {
     // layout of the wave's state
     std::vector<uint32_t> qt(nq), qs(nq), qm(nq);
     std::vector<unsigned long long> qo(nq);
@@ -457,6 +469,8 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
     fk::QueryDev Q;
     Q.nq = nq; Q.qc = c->qcap; Q.qtype = c->d_qtype; Q.qoff = c->d_qoff; Q.qalpha = c->d_qalpha;
     Q.qeps = c->d_qeps; Q.qmode = c->d_qmode; Q.state = c->d_state;
+    Q.final_state = trace ? c->d_final : nullptr;
+    pc.trace = trace ? 1u : 0u;
     fk::GraphDev g = graph_dev(c);
     fk::BufDev B = buf_dev(c);
     HIPCHK(hipEventRecord(c->ev[0], s));
@@ -502,7 +516,7 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
     auto t_start = std::chrono::steady_clock::now();
     auto t_last = t_start;
     while (!done) {
-        uint32_t nb = batch;
+        uint32_t nb = trace ? 1u : batch;
         if (passes_left != ~0ull) nb = (uint32_t)std::min<uint64_t>(nb, passes_left);
         if (nb == 0) return fail(FORK_E_NOT_CONVERGED, "max_passes reached with work pending");
         if (o.profile && c->pev.size() < 2 * nb) {
@@ -510,7 +524,32 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
             c->pev.resize(2 * nb, nullptr);
             for (size_t k = old; k < c->pev.size(); ++k) HIPCHK(hipEventCreate(&c->pev[k]));
         }
-        if (o.persistent) {
+        if (trace) {
+            // one pass with the features of every partition and the usefulness of the visits
+            HIPCHK(hipMemsetAsync(c->d_tr, 0, (size_t)c->np * 2 * sizeof(float), s));
+            HIPCHK(fk::launch_mlp_score(g, B, c->d_mlp, c->d_score, c->d_feat, c->d_gstat, 0, s));
+            HIPCHK(fk::launch_select(g, B, pc, s));
+            HIPCHK(fk::launch_worklist(B, Q, pc.kmax, s));
+            HIPCHK(fk::launch_process(g, Q, B, pc, blocks, c->vpmax, s));
+            std::vector<uint32_t> sel(c->np);
+            std::vector<float> feat((size_t)c->np * fk::MLP_IN), tr((size_t)c->np * 2);
+            HIPCHK(hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(fk::Ctl), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(sel.data(), c->d_sel, c->np * 4ull, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(feat.data(), c->d_feat, feat.size() * 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(tr.data(), c->d_tr, tr.size() * 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const uint32_t nsel = std::min<uint32_t>(c->h_ctl->nsel, c->np);
+            for (uint32_t j = 0; j < nsel; ++j) {
+                uint32_t P = sel[j];
+                if (tr[c->np + P] <= 0.f) continue;
+                c->trace.insert(c->trace.end(), feat.begin() + (size_t)P * fk::MLP_IN,
+                                feat.begin() + (size_t)(P + 1) * fk::MLP_IN);
+                c->trace.push_back(tr[P]);
+                c->trace.push_back(tr[c->np + P]);
+                c->trace.push_back((float)c->h_ctl->pass);
+                c->trace.push_back((float)P);
+            }
+        } else if (o.persistent) {
             // one cooperative launch runs up to 64 passes per batch slot on the device
             if (c->pers_blocks_per_cu <= 0) return fail(FORK_E_DEVICE, "persistent kernel does not fit on a CU");
             const uint32_t pblocks = (uint32_t)(c->num_cu * c->pers_blocks_per_cu);
@@ -667,6 +706,8 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     cfg.kmax = o.parts_per_pass ? std::min<uint32_t>(o.parts_per_pass, c->np) : c->np;
     cfg.target_items = o.parts_per_pass ? 0u : (o.items_per_pass ? o.items_per_pass : 16u * slots);
     c->stats = fork_stats_t{};
+    c->trace.clear();
+    if (o.trace && o.persistent) return fail(FORK_E_INVALID, "trace runs use the per-pass kernels (persistent = 0)");
     c->stats.num_partitions = c->np;
     c->stats.weight_bytes = (uint32_t)c->wbytes;
     c->digests.assign(nq_total, fork_digest{});
@@ -683,7 +724,22 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
         }
         uint64_t saved = passes_left;
         fork_stats_t saved_st = c->stats;
-        int rc = run_wave(c, q0, n, o, s, cfg, passes_left);
+        int rc = run_wave(c, q0, n, o, s, cfg, passes_left, false);
+        if (rc == FORK_OK && o.trace) {
+            // traced re-run: the final state of the first run marks useful work
+            size_t words = c->state_words_cap;
+            if (words > c->final_words) {
+                hipFree(c->d_final);
+                c->d_final = nullptr;
+                c->final_words = 0;
+                if ((rc = dalloc(&c->d_final, words))) return rc;
+                c->final_words = words;
+            }
+            HIPCHK(hipMemcpyAsync(c->d_final, c->d_state, words * 4, hipMemcpyDeviceToDevice, s));
+            c->stats = saved_st;
+            uint64_t pl = ~0ull;
+            rc = run_wave(c, q0, n, o, s, cfg, pl, true);
+        }
         if (rc == FORK_E_CAPACITY && n > 1) {
             passes_left = saved;
             c->stats = saved_st;
@@ -725,9 +781,118 @@ extern "C" int fork_fetch(fork_ctx* c, uint32_t qid, int field, void* dst, uint6
     return FORK_OK;
 }
 
+extern "C" int fork_trace(fork_ctx* c, float* dst, uint64_t cap, uint64_t* n) {
+    if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
+    const uint64_t avail = c->trace.size() / FORK_TRACE_WIDTH;
+    if (n) *n = avail;
+    if (dst && cap) memcpy(dst, c->trace.data(), std::min(cap, avail) * FORK_TRACE_WIDTH * sizeof(float));
+    return FORK_OK;
+}
+
 extern "C" int fork_stats(fork_ctx* c, void* dst, uint64_t dst_bytes) {
     if (!c || !dst) return fail(FORK_E_INVALID, "NULL argument");
     if (dst_bytes < sizeof(fork_stats_t)) return fail(FORK_E_INVALID, "dst too small");
     memcpy(dst, &c->stats, sizeof(fork_stats_t));
+    return FORK_OK;
+}
+
+// ------------------------------------------------------------ learned scheduler: MLP entry points
+namespace {
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) hipFree(p); }
+};
+int dev_upload(DevBuf& b, const void* h, size_t bytes) {
+    if (hipMalloc(&b.p, bytes ? bytes : 4) != hipSuccess) return fail(FORK_E_NOMEM, "hipMalloc(%zu) failed", bytes);
+    if (h && bytes && hipMemcpy(b.p, h, bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FORK_E_DEVICE, "hipMemcpy to device failed");
+    return FORK_OK;
+}
+int mlp_check(const float* theta, const float* x, uint64_t n) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(FORK_E_DEVICE, "no HIP device");
+    if (!theta || (n && !x)) return fail(FORK_E_INVALID, "NULL argument");
+    if (n > 0xffffffffull) return fail(FORK_E_INVALID, "too many samples");
+    return FORK_OK;
+}
+}  // namespace
+
+extern "C" int fork_mlp_forward(const float* theta, const float* x, uint64_t n, float* y) {
+    g_err.clear();
+    int rc = mlp_check(theta, x, n);
+    if (rc) return rc;
+    if (!y) return fail(FORK_E_INVALID, "y is NULL");
+    DevBuf dt, dx, dy;
+    if ((rc = dev_upload(dt, theta, fk::MLP_NPARAM * 4))) return rc;
+    if ((rc = dev_upload(dx, x, n * fk::MLP_IN * 4))) return rc;
+    if ((rc = dev_upload(dy, nullptr, n * 4))) return rc;
+    if (n) HIPCHK(fk::launch_mlp_forward((float*)dt.p, (float*)dx.p, (uint32_t)n, (float*)dy.p, 0));
+    HIPCHK(hipMemcpy(y, dy.p, n * 4, hipMemcpyDeviceToHost));
+    return FORK_OK;
+}
+
+extern "C" int fork_mlp_grad(const float* theta, const float* x, const float* t, uint64_t n, float* grad,
+                             float* loss) {
+    g_err.clear();
+    int rc = mlp_check(theta, x, n);
+    if (rc) return rc;
+    if (!t || !grad || !loss || n == 0) return fail(FORK_E_INVALID, "NULL argument or no samples");
+    DevBuf dt, dx, dtg, dg, dl;
+    if ((rc = dev_upload(dt, theta, fk::MLP_NPARAM * 4))) return rc;
+    if ((rc = dev_upload(dx, x, n * fk::MLP_IN * 4))) return rc;
+    if ((rc = dev_upload(dtg, t, n * 4))) return rc;
+    if ((rc = dev_upload(dg, nullptr, fk::MLP_NPARAM * 4))) return rc;
+    if ((rc = dev_upload(dl, nullptr, 4))) return rc;
+    HIPCHK(hipMemset(dg.p, 0, fk::MLP_NPARAM * 4));
+    HIPCHK(hipMemset(dl.p, 0, 4));
+    HIPCHK(fk::launch_mlp_grad((float*)dt.p, (float*)dx.p, (float*)dtg.p, nullptr, (uint32_t)n, (float*)dg.p,
+                               (float*)dl.p, 0));
+    HIPCHK(hipMemcpy(grad, dg.p, fk::MLP_NPARAM * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(loss, dl.p, 4, hipMemcpyDeviceToHost));
+    return FORK_OK;
+}
+
+extern "C" int fork_mlp_train(float* theta, const float* x, const float* t, uint64_t n, uint32_t steps,
+                              uint32_t batch, float lr, uint64_t seed, float* losses) {
+    g_err.clear();
+    int rc = mlp_check(theta, x, n);
+    if (rc) return rc;
+    if (!t || n == 0 || batch == 0 || !(lr > 0.f)) return fail(FORK_E_INVALID, "bad training arguments");
+    batch = (uint32_t)std::min<uint64_t>(batch, n);
+    DevBuf dt, dx, dtg, dg, dl, dm, dv, di;
+    if ((rc = dev_upload(dt, theta, fk::MLP_NPARAM * 4))) return rc;
+    if ((rc = dev_upload(dx, x, n * fk::MLP_IN * 4))) return rc;
+    if ((rc = dev_upload(dtg, t, n * 4))) return rc;
+    if ((rc = dev_upload(dg, nullptr, fk::MLP_NPARAM * 4))) return rc;
+    if ((rc = dev_upload(dl, nullptr, (size_t)std::max(1u, steps) * 4))) return rc;
+    if ((rc = dev_upload(dm, nullptr, fk::MLP_NPARAM * 4))) return rc;
+    if ((rc = dev_upload(dv, nullptr, fk::MLP_NPARAM * 4))) return rc;
+    if ((rc = dev_upload(di, nullptr, n * 4))) return rc;
+    HIPCHK(hipMemset(dm.p, 0, fk::MLP_NPARAM * 4));
+    HIPCHK(hipMemset(dv.p, 0, fk::MLP_NPARAM * 4));
+    HIPCHK(hipMemset(dl.p, 0, (size_t)std::max(1u, steps) * 4));
+    // epochs of a seeded permutation (Fisher-Yates with a SplitMix64 stream)
+    std::vector<uint32_t> perm(n);
+    for (uint64_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
+    unsigned long long st = seed;
+    uint64_t pos = n;
+    for (uint32_t k = 1; k <= steps; ++k) {
+        if (pos + batch > n) {
+            for (uint64_t i = n - 1; i > 0; --i) {
+                st += 0x9E3779B97F4A7C15ull;
+                uint64_t j = fk::mix64(st) % (i + 1);
+                std::swap(perm[i], perm[j]);
+            }
+            HIPCHK(hipMemcpy(di.p, perm.data(), n * 4, hipMemcpyHostToDevice));
+            pos = 0;
+        }
+        HIPCHK(hipMemsetAsync(dg.p, 0, fk::MLP_NPARAM * 4, 0));
+        HIPCHK(fk::launch_mlp_grad((float*)dt.p, (float*)dx.p, (float*)dtg.p, (uint32_t*)di.p + pos, batch,
+                                   (float*)dg.p, (float*)dl.p + (k - 1), 0));
+        HIPCHK(fk::launch_adam((float*)dt.p, (float*)dg.p, (float*)dm.p, (float*)dv.p, k, lr, 0));
+        pos += batch;
+    }
+    HIPCHK(hipMemcpy(theta, dt.p, fk::MLP_NPARAM * 4, hipMemcpyDeviceToHost));
+    if (losses && steps) HIPCHK(hipMemcpy(losses, dl.p, steps * 4ull, hipMemcpyDeviceToHost));
     return FORK_OK;
 }

@@ -1,0 +1,113 @@
+"""Learned partition scheduler: trace collection and GPU training.
+
+The paper schedules partitions with a user priority functor: a partition's
+priority is the best priority among its buffered operations (Section 5.2).
+The learned scheduler replaces that functor by an MLP (16 -> 64 -> 64 -> 1)
+that scores each partition from its buffer statistics.  Training data comes
+from the rule-based scheduler itself: a traced run records, for every
+partition a pass visited, the 16 features it had when it was selected and the
+useful work the visit did (SSSP/BFS: vertex expansions whose distance was
+already final; PPR: vertex pushes).  The network learns to predict
+log(1 + useful work); at run time the partitions with the highest predicted
+useful work are processed first.  Any processing order gives the same exact
+SSSP/BFS answers, so the network changes only speed.
+
+    python -m paper_2103_14915_amd.learn --out paper_2103_14915_amd/sched_mlp.npy
+
+Training runs entirely on the GPU through the library's own forward /
+backward / Adam kernels (fork_mlp_train).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import MLP_NPARAM, ForkGraph, mlp_train
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "sched_mlp.npy")
+
+# Training graphs: R-MAT scales 20 and 21 with seeds distinct from every
+# benchmark and test graph (those use seeds 1..5 and 9..21).
+TRAIN_SPECS = [
+    dict(scale=20, seed=41, wseed=141, sseed=241),
+    dict(scale=21, seed=42, wseed=142, sseed=242),
+    dict(scale=20, seed=43, wseed=143, sseed=243),
+]
+
+
+def init_theta(seed: int) -> np.ndarray:
+    """He-uniform weights, zero biases (same layout as the library)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in ((64, 16), (64, None), (64, 64), (64, None), (1, 64), (1, None)):
+        if fan_in is None:
+            parts.append(np.zeros(fan_out))
+        else:
+            lim = np.sqrt(6.0 / fan_in)
+            parts.append(rng.uniform(-lim, lim, fan_out * fan_in))
+    th = np.concatenate(parts).astype(np.float32)
+    assert th.size == MLP_NPARAM
+    return th
+
+
+def target_of(records: np.ndarray) -> np.ndarray:
+    """Regression target of a trace record: log(1 + useful work of the visit)."""
+    return np.log1p(records[:, 16]).astype(np.float32)
+
+
+def collect(spec: dict, n_sssp: int, n_ppr: int, partition_vertices: int = 0, log=print) -> np.ndarray:
+    import fpp_inputs as fi
+
+    g = fi.rmat(spec["scale"], seed=spec["seed"], weights=(1, 255), weight_seed=spec["wseed"])
+    fg = ForkGraph.from_graph(g, partition_vertices=partition_vertices)
+    if n_sssp:
+        fg.submit("sssp", fi.sources_mixed(g, n_sssp, spec["sseed"]))
+    if n_ppr:
+        fg.submit("ppr", fi.sources_mixed(g, n_ppr, spec["sseed"] + 1), alpha=0.15, epsilon=1e-6, eps_mode=1)
+    t0 = time.time()
+    fg.run(scheduler="priority", trace=1)
+    rec = fg.trace()
+    fg.close()
+    log(f"[learn] traced rmat{spec['scale']} seed {spec['seed']}: {rec.shape[0]} visits in {time.time() - t0:.1f}s")
+    return rec
+
+
+def train(records: np.ndarray, steps: int = 3000, batch: int = 256, lr: float = 1e-3, seed: int = 7):
+    x = records[:, :16]
+    t = target_of(records)
+    theta = init_theta(seed)
+    theta, losses = mlp_train(theta, x, t, steps=steps, batch=batch, lr=lr, seed=seed)
+    return theta, losses
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--sssp", type=int, default=512)
+    ap.add_argument("--ppr", type=int, default=512)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--specs", type=int, default=len(TRAIN_SPECS))
+    args = ap.parse_args(argv)
+    recs = [collect(s, args.sssp, args.ppr) for s in TRAIN_SPECS[:args.specs]]
+    records = np.concatenate(recs)
+    t0 = time.time()
+    theta, losses = train(records, steps=args.steps)
+    print(f"[learn] trained on {records.shape[0]} visits, {args.steps} steps in {time.time() - t0:.1f}s: "
+          f"loss {losses[:50].mean():.4f} -> {losses[-50:].mean():.4f}", flush=True)
+    np.save(args.out, theta)
+    meta = {"records": int(records.shape[0]), "steps": args.steps, "loss_first": float(losses[:50].mean()),
+            "loss_last": float(losses[-50:].mean()), "specs": TRAIN_SPECS[:args.specs],
+            "queries": {"sssp": args.sssp, "ppr": args.ppr}}
+    with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
+        json.dump(meta, f, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,88 @@
+"""GPU tests of the learned scheduler: the MLP's forward and backward kernels
+against the fp64 oracle, training on the GPU, trace capture, and exactness of
+runs scheduled by the network."""
+import sys
+
+import numpy as np
+import pytest
+
+import fpp_inputs as fi
+import oracle
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _fork():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2103_14915_amd as fork
+    return fork
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_mlp_forward_and_gradient_vs_fp64_oracle():
+    fork = _fork()
+    rng = np.random.default_rng(0)
+    theta = (omlp.init(5) + rng.normal(0, 0.02, omlp.N_PARAMS)).astype(np.float32)
+    for n in (1, 63, 64, 200):
+        x = rng.normal(size=(n, 16)).astype(np.float32)
+        t = rng.normal(size=n).astype(np.float32)
+        y = fork.mlp_forward(theta, x)
+        y64, _ = omlp.forward(theta.astype(np.float64), x.astype(np.float64))
+        np.testing.assert_allclose(y, y64, rtol=1e-4, atol=1e-5)
+        loss, g = fork.mlp_grad(theta, x, t)
+        loss64, g64 = omlp.loss_and_grad(theta.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+        assert abs(loss - loss64) <= 1e-4 * max(1.0, abs(loss64))
+        # relative error of the whole gradient vector, and per component where it is not tiny
+        assert np.linalg.norm(g - g64) <= 1e-4 * np.linalg.norm(g64)
+        big = np.abs(g64) > 1e-3 * np.abs(g64).max()
+        np.testing.assert_allclose(g[big], g64[big], rtol=1e-3)
+
+
+def test_mlp_training_on_gpu_reduces_loss():
+    fork = _fork()
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=(4096, 16)).astype(np.float32)
+    t = (np.abs(x[:, 0]) - 0.5 * x[:, 1] + 0.25 * x[:, 2] * x[:, 3]).astype(np.float32)
+    theta0 = omlp.init(3).astype(np.float32)
+    l0 = omlp.loss_and_grad(theta0.astype(np.float64), x, t)[0]
+    theta, losses = fork.mlp_train(theta0, x, t, steps=600, batch=256, lr=3e-3, seed=5)
+    l1 = omlp.loss_and_grad(theta.astype(np.float64), x, t)[0]
+    assert l1 < 0.2 * l0, (l0, l1)
+    assert losses[-20:].mean() < losses[:20].mean()
+
+
+def test_trace_and_learned_schedule_are_exact():
+    """Trace a rule run, train on it, and run with the learned scores: SSSP and
+    BFS stay bit-exact and PPR passes its gates."""
+    fork = _fork()
+    from paper_2103_14915_amd import learn
+    g = fi.rmat(13, seed=31, weights=(1, 255), weight_seed=131)
+    s_sp = fi.sources_mixed(g, 48, 7)
+    s_pr = fi.sources_mixed(g, 16, 8)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=512)
+    fg.submit("sssp", s_sp)
+    fg.submit("ppr", s_pr, alpha=0.15, epsilon=1e-6, eps_mode=1)
+    fg.run(scheduler="priority", trace=1)
+    rec = fg.trace()
+    say("trace records", rec.shape)
+    assert rec.shape[0] > 10 and np.all(rec[:, 17] >= rec[:, 16]) and np.all(rec[:, 16] >= 0)
+    ref = oracle.sssp(g, s_sp)
+    np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(48)]), ref)
+    theta, losses = learn.train(rec, steps=300, batch=64)
+    assert np.isfinite(losses).all()
+    for persistent in (0, 1):
+        fg.run(scheduler="learned", mlp_weights=theta, persistent=persistent, max_passes=200000)
+        np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(48)]), ref)
+        for i, s in enumerate(s_pr):
+            p = fg.fetch(48 + i, fork.FIELD_P).astype(np.float64)
+            r = fg.fetch(48 + i, fork.FIELD_R)
+            assert oracle.push_terminal(g, r, 1e-6, 1, dtype=np.float32)
+            assert oracle.ppr_invariant_l1(g, s, p, r.astype(np.float64), 0.15) <= 1e-4
+    fg.close()
