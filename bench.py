@@ -112,6 +112,10 @@ def main():
     ap.add_argument("--max-queries", type=int, default=0, help="queries resident per wave (0 = auto)")
     ap.add_argument("--persistent", action="store_true", help="one persistent cooperative kernel per batch of passes")
     ap.add_argument("--items-per-pass", type=int, default=0, help="work items queued per pass (0 = auto)")
+    ap.add_argument("--window-mode", type=int, default=0, help="heuristic-2 window: 0 = query-global, 1 = per visit")
+    ap.add_argument("--window", type=int, default=0, help="SSSP batch width inside a visit (0 = auto)")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner on a query sample first (cached)")
+    ap.add_argument("--no-tuned", action="store_true", help="ignore cached autotuner results")
     ap.add_argument("--compare-learned", default="", help="MLP weights (.npy): also time the learned scheduler "
                     "on the same workload and report the speedup over the rule-based one")
     args = ap.parse_args()
@@ -135,8 +139,23 @@ def main():
         queries = [(qt, s[:args.queries]) for qt, s in queries]
     t_gen = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
+    # knobs: defaults <- autotuner (cached, or tuned now with --tune) <- explicit flags
+    from paper_2103_14915_amd import autotune
+    params, source = dict(autotune.DEFAULTS), "defaults"
+    if not args.no_tuned:
+        t_tune = time.perf_counter()
+        tuned = autotune.tune(g, queries, spec, log=lambda *a: print(*a, file=sys.stderr, flush=True)) \
+            if args.tune else autotune.cached(g, queries)
+        if tuned:
+            params, source = dict(tuned), ("tuned" if args.tune else "cache")
+            print(f"[bench] tuned params ({source}, {time.perf_counter() - t_tune:.1f}s): {params}",
+                  file=sys.stderr, flush=True)
+    for k, v in (("partition_vertices", args.partition_vertices), ("items_per_pass", args.items_per_pass),
+                 ("window", args.window), ("delta", args.delta), ("persistent", int(args.persistent))):
+        if v:
+            params[k] = v
     t0 = time.perf_counter()
-    fg = fork.ForkGraph.from_graph(g, partition_vertices=args.partition_vertices, max_queries=args.max_queries)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=params["partition_vertices"], max_queries=args.max_queries)
     t_load = time.perf_counter() - t0
     nq = 0
     for qt, s in queries:
@@ -145,9 +164,9 @@ def main():
         nq += len(s)
     kinds = sorted({qt for qt, _ in queries})
     kind = kinds[0] if len(kinds) == 1 else "mixed"
-    run_kw = dict(scheduler=args.scheduler, parts_per_pass=args.parts_per_pass, delta=args.delta,
-                  edge_budget_mu=args.mu, stream=stream, profile=1, persistent=int(args.persistent),
-                  items_per_pass=args.items_per_pass)
+    run_kw = dict(scheduler=args.scheduler, parts_per_pass=args.parts_per_pass, delta=params["delta"],
+                  edge_budget_mu=args.mu, stream=stream, profile=1, persistent=params["persistent"],
+                  items_per_pass=params["items_per_pass"], window_mode=args.window_mode, window=params["window"])
     for _ in range(args.warmup):
         fg.run(**run_kw)
     torch.cuda.synchronize()
@@ -182,7 +201,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload + (f"@scale{args.scale}" if args.scale else "")
                    + (f"@q{args.queries}" if args.queries else ""), "queries": nq, "types": kinds, "vertices": g.num_vertices,
-                   "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler, "persistent": bool(args.persistent),
+                   "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler, "knobs": params, "knobs_source": source,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_process",
@@ -194,6 +213,7 @@ def main():
                    "passes_per_step": tot["passes"] / args.steps,
                    "edges_per_step": tot["edges"] / args.steps,
                    "ops_emitted_per_step": tot["ops_emitted"] / args.steps,
+                   "ops_pruned_per_step": tot["pruned"] / args.steps,
                    "vertex_pushes_per_step": tot["vertex_pushes"] / args.steps,
                    "work_items_per_step": tot["work_items"] / args.steps},
     }

@@ -77,7 +77,7 @@ typedef struct {
 typedef struct {
     int      scheduler;        /* fork_sched                                     */
     uint32_t parts_per_pass;   /* partitions processed per pass (0 = auto)       */
-    uint32_t delta;            /* SSSP/BFS window width and yield range (0=auto) */
+    uint32_t delta;            /* SSSP/BFS yield range Delta of heuristic 2 (0=auto) */
     float    edge_budget_mu;   /* yield after mu*|E_P|/|Q_P| edges (0 = off)     */
     uint64_t max_passes;       /* 0 = unlimited                                  */
     void    *stream;           /* hipStream_t to run on (NULL = default stream)  */
@@ -88,6 +88,12 @@ typedef struct {
     uint32_t items_per_pass;   /* (partition, query) items queued per pass when
                                   parts_per_pass is 0 (0 = auto)                 */
     int      trace;            /* 1 = record scheduler traces (see fork_trace)   */
+    int      window_mode;      /* heuristic 2 window: 0 = the query's best buffered
+                                  value over all partitions (dist_min), 1 = the
+                                  first value of each visit                     */
+    uint32_t window;           /* SSSP batch width inside a visit: vertices with
+                                  distance in [lo, lo + window) expand together
+                                  (0 = auto)                                     */
 } fork_run_opts;
 
 /* Counters accumulated over the last fork_run (all waves). */
@@ -108,6 +114,7 @@ typedef struct {
     double   process_ms;       /* sum of pass-kernel durations (profile=1)  */
     uint64_t process_launches; /* pass kernels timed                        */
     uint64_t intra_edges;      /* edges whose target is in the same partition */
+    uint64_t pruned;           /* operations not sent: target already as short */
     uint32_t num_partitions;
     uint32_t weight_bytes;     /* bytes per stored edge weight (0 = none)   */
 } fork_stats_t;

@@ -1,0 +1,138 @@
+"""Autotuner for the fork-processing pass.
+
+Picks the knobs that the paper fixes by hand (Section 6.1: partition size =
+LLC size; yield thresholds; one partition processed at a time) for the
+MI355X: partition size (vertices per LDS-staged slice), work items queued per
+pass (how many (partition, query) visits run between two scheduling steps),
+the SSSP batch window and the heuristic-2 range Delta, and whether the pass
+loop runs in one persistent kernel.  It times short runs on a seeded sample
+of the workload's queries and does coordinate descent from the defaults.
+Results are cached in JSON keyed by graph shape, query mix and device.
+
+    from paper_2103_14915_amd import autotune
+    params = autotune.tune(graph, [("sssp", sources), ...], spec)
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+from typing import Optional
+
+import numpy as np
+
+from . import ForkGraph
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.environ.get("FORK_TUNE_CACHE", os.path.join(HERE, "tune_cache.json"))
+
+DEFAULTS = {"partition_vertices": 16384, "items_per_pass": 0, "window": 0, "delta": 0, "persistent": 0}
+
+
+def device_name() -> str:
+    try:
+        import torch
+        return torch.cuda.get_device_name(0)
+    except Exception:  # noqa: BLE001 - the name only keys the cache
+        return "unknown"
+
+
+def signature(g, queries) -> str:
+    h = hashlib.sha1()
+    h.update(np.asarray([g.num_vertices, g.num_edges], np.int64).tobytes())
+    h.update(np.ascontiguousarray(g.row_ptr[:: max(1, g.num_vertices // 4096)]).tobytes())
+    if g.weight is not None:
+        h.update(np.ascontiguousarray(g.weight[:4096]).tobytes())
+    mix = ",".join(f"{qt}:{len(s)}" for qt, s in queries)
+    return f"V{g.num_vertices}-E{g.num_edges}-{mix}-{h.hexdigest()[:12]}"
+
+
+def _load_cache() -> dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def cached(g, queries) -> Optional[dict]:
+    return _load_cache().get(f"{signature(g, queries)}|{device_name()}", {}).get("params")
+
+
+def _sample(queries, n):
+    out = []
+    for qt, s in queries:
+        k = max(1, min(len(s), int(round(n * len(s) / sum(len(x) for _, x in queries)))))
+        idx = np.random.default_rng(12345).choice(len(s), k, replace=False)
+        out.append((qt, np.asarray(s)[np.sort(idx)]))
+    return out
+
+
+def _trial(g, sample, spec, p, stream=None) -> float:
+    fg = ForkGraph.from_graph(g, partition_vertices=p["partition_vertices"])
+    try:
+        n = 0
+        for qt, s in sample:
+            fg.submit(qt, s, alpha=spec.get("alpha", 0.15), epsilon=spec.get("epsilon", 1e-6),
+                      eps_mode=spec.get("eps_mode", 0))
+            n += len(s)
+        kw = dict(items_per_pass=p["items_per_pass"], window=p["window"], delta=p["delta"],
+                  persistent=p["persistent"], stream=stream)
+        fg.run(**kw)
+        t0 = time.perf_counter()
+        fg.run(**kw)
+        return n / (time.perf_counter() - t0)
+    finally:
+        fg.close()
+
+
+def candidates(g, queries) -> dict:
+    kinds = {qt for qt, _ in queries}
+    wmean = float(g.weight.mean()) if g.weight is not None else 1.0
+    c = {
+        "partition_vertices": [4096, 8192, 16384],
+        "items_per_pass": [0, 2048, 16384, 65536],
+        "persistent": [0, 1],
+    }
+    if kinds & {"sssp", "bfs"}:
+        w = max(1, int(round(wmean)))
+        c["window"] = [0, max(1, w // 8), max(1, w // 2), 2 * w]
+        c["delta"] = [0, 4 * w, 16 * w, 256 * w]
+    return c
+
+
+def tune(g, queries, spec, sample=256, rounds=1, budget_s=240.0, log=print, use_cache=True) -> dict:
+    key = f"{signature(g, queries)}|{device_name()}"
+    cache = _load_cache()
+    if use_cache and key in cache:
+        return cache[key]["params"]
+    smp = _sample(queries, sample)
+    best = dict(DEFAULTS)
+    best_v = _trial(g, smp, spec, best)
+    log(f"[tune] default {best} -> {best_v:.1f} q/s")
+    trials = [{"params": dict(best), "qps": best_v}]
+    t_start = time.time()
+    space = candidates(g, queries)
+    for _ in range(rounds):
+        for name, values in space.items():
+            for v in values:
+                if v == best[name] or time.time() - t_start > budget_s:
+                    continue
+                p = dict(best, **{name: v})
+                try:
+                    q = _trial(g, smp, spec, p)
+                except Exception as e:  # noqa: BLE001 - a configuration that fails is just not chosen
+                    log(f"[tune] {p} failed: {e}")
+                    continue
+                trials.append({"params": p, "qps": q})
+                log(f"[tune] {name}={v} -> {q:.1f} q/s")
+                if q > best_v:
+                    best, best_v = p, q
+    cache = _load_cache()
+    cache[key] = {"params": best, "qps_sample": best_v, "sample_queries": int(sum(len(s) for _, s in smp)),
+                  "default_qps_sample": trials[0]["qps"], "trials": trials}
+    with open(CACHE, "w") as f:
+        json.dump(cache, f, indent=1)
+    log(f"[tune] best {best} -> {best_v:.1f} q/s (default {trials[0]['qps']:.1f})")
+    return best

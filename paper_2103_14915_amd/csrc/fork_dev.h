@@ -33,7 +33,7 @@ struct Ctl {
     unsigned int nitems[NXCD];      // per-XCD work list lengths
     unsigned int next[NXCD];        // per-XCD work list cursors
     unsigned long long c_edges, c_improved, c_emitted, c_consumed, c_vpush, c_yields, c_chunks,
-        c_items, c_passes_nonempty, c_intra;
+        c_items, c_passes_nonempty, c_intra, c_pruned;
     unsigned long long pending_ops; // operations buffered at select time
 };
 
@@ -68,6 +68,12 @@ struct QueryDev {
 struct BufDev {
     int32_t* bhead;           // [np*qc] first chunk of the (partition, query) buffer
     int32_t* btail;           // [np*qc] chunk with free slots (-1: none)
+    uint32_t* bval;           // [np*qc] best buffered value: SSSP/BFS min value, PPR ~(max mass bits);
+                              //         0xffffffff when empty (min works for both encodings)
+    uint32_t* bcnt;           // [np*qc] buffered operations
+    uint32_t* bfirst;         // [np*qc] pass in which the buffer became non-empty
+    uint32_t* qmin;           // [qc] SSSP/BFS: best buffered value of the query over all partitions
+    uint32_t* pready;         // [np] buffers ready to run (within the query's window)
     uint2* chunks;            // [nch*CH] (vertex, value) operations
     int32_t* cnext;           // [nch]
     uint32_t* ccount;         // [nch] slots reserved (valid ops = min(ccount, CH))
@@ -102,7 +108,15 @@ struct PassCfg {
     uint32_t seed;
     uint32_t mixed;           // more than one query type in the wave
     uint32_t trace;           // record per-partition usefulness of each visit
+    uint32_t gate;            // process a query's buffer only within its global window (heuristic 2)
 };
+
+// Is the buffered work of bucket b (query type qt) within its query's window?
+__host__ __device__ inline bool bucket_ready(uint32_t bv, uint32_t qt, uint32_t qmin, const PassCfg& cfg) {
+    if (!cfg.gate || qt == Q_PPR) return true;
+    const unsigned long long d = qt == Q_BFS ? cfg.yld_lv : cfg.yld_sp;
+    return d == 0 || (unsigned long long)bv <= (unsigned long long)qmin + d;
+}
 
 __host__ __device__ inline unsigned long long mix64(unsigned long long z) {
     z += 0x9E3779B97F4A7C15ull;

@@ -25,11 +25,17 @@ __global__ __launch_bounds__(SEL_THREADS) void k_select(GraphDev g, BufDev B, Pa
     select_body<SEL_THREADS>(g, B, cfg, s_key, s_qn, SEL_CACHE);
 }
 
-__global__ __launch_bounds__(256) void k_worklist(BufDev B, QueryDev Q) {
+__global__ __launch_bounds__(256) void k_worklist(BufDev B, QueryDev Q, PassCfg cfg) {
     const uint32_t j = blockIdx.x;
     if (B.ctl->err || j >= B.ctl->nsel) return;
-    worklist_one(B, Q, j, blockIdx.y * 256 + threadIdx.x);
+    worklist_one(B, Q, cfg, j, blockIdx.y * 256 + threadIdx.x);
 }
+
+__global__ __launch_bounds__(256) void k_qmin(BufDev B, QueryDev Q, uint32_t np) {
+    qmin_one(B, Q, np, blockIdx.x * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_psum(BufDev B, QueryDev Q, PassCfg cfg) { psum_one(B, Q, cfg, blockIdx.x); }
 
 // ------------------------------------------------------------ wave setup
 __global__ void k_ring_init(uint32_t* ring, unsigned long long nch) {
@@ -52,12 +58,9 @@ __global__ void k_seed(GraphDev g, QueryDev Q, BufDev B, const uint32_t* src) {
     unsigned long long b = (unsigned long long)P * Q.qc + q;
     B.bhead[b] = (int32_t)q;
     B.btail[b] = (int32_t)q;
-    dev_add(&B.pcount[P], 1u);
-    dev_add(&B.pqn[P], 1u);
-    dev_min(&B.pfirst[P], 0u);
-    if (t == Q_PPR) dev_max(&B.pbest_pr[P], __float_as_uint(1.0f));
-    else if (t == Q_BFS) dev_min(&B.pbest_lv[P], 0u);
-    else dev_min(&B.pbest_sp[P], 0u);
+    B.bcnt[b] = 1;
+    B.bval[b] = t == Q_PPR ? ~__float_as_uint(1.0f) : 0u;
+    B.bfirst[b] = 0;
 }
 
 // Per-query digest of the final state (one block per query).
@@ -122,9 +125,14 @@ hipError_t launch_select(const GraphDev& g, const BufDev& B, const PassCfg& cfg,
     hipLaunchKernelGGL(k_select, dim3(1), dim3(SEL_THREADS), 0, s, g, B, cfg);
     return hipGetLastError();
 }
-hipError_t launch_worklist(const BufDev& B, const QueryDev& Q, uint32_t kmax, hipStream_t s) {
-    dim3 grid(kmax, (Q.nq + 255) / 256);
-    hipLaunchKernelGGL(k_worklist, grid, dim3(256), 0, s, B, Q);
+hipError_t launch_worklist(const BufDev& B, const QueryDev& Q, const PassCfg& cfg, hipStream_t s) {
+    dim3 grid(cfg.kmax, (Q.nq + 255) / 256);
+    hipLaunchKernelGGL(k_worklist, grid, dim3(256), 0, s, B, Q, cfg);
+    return hipGetLastError();
+}
+hipError_t launch_summaries(const GraphDev& g, const BufDev& B, const QueryDev& Q, const PassCfg& cfg, hipStream_t s) {
+    hipLaunchKernelGGL(k_qmin, dim3((Q.nq + 255) / 256), dim3(256), 0, s, B, Q, g.np);
+    hipLaunchKernelGGL(k_psum, dim3(g.np), dim3(256), 0, s, B, Q, cfg);
     return hipGetLastError();
 }
 hipError_t launch_ring_init(uint32_t* ring, unsigned long long nch, hipStream_t s) {

@@ -38,7 +38,7 @@ __device__ void gstat_body(const GraphDev& g, const BufDev& B, GStat* out) {
     if (threadIdx.x == 0) *out = s;
 }
 
-// Feature vector of partition P (16 fp32 values): buffer size and share,
+// Feature vector of partition P (16 fp32 values): buffer size, ready share,
 // best SSSP distance / BFS level / PPR mass relative to the global range and
 // their presence flags, recency, visits, partition size, age of the oldest
 // buffered operation, and the fraction of partitions with work.
@@ -52,7 +52,7 @@ __device__ void partition_features(const GraphDev& g, const BufDev& B, const GSt
     uint32_t v0 = g.pstart[P], v1 = g.pstart[P + 1];
     float ep = (float)(g.rowptr[v1] - g.rowptr[v0]);
     x[0] = log1pf((float)cnt) * 0.125f;
-    x[1] = (float)cnt / (float)(s.ops ? s.ops : 1ull);
+    x[1] = (float)B.pready[P] / (float)(B.pqn[P] ? B.pqn[P] : 1u);  // share of its buffers that are ready
     x[2] = sp < INF ? (float)(sp - s.sp_min) / (float)(s.sp_max - s.sp_min + 1u) : 1.f;
     x[3] = sp < INF ? 1.f : 0.f;
     x[4] = lv < INF ? (float)(lv - s.lv_min) / (float)(s.lv_max - s.lv_min + 1u) : 1.f;

@@ -123,13 +123,14 @@ struct ItemCtx {
     QueryDev Q;
     BufDev B;
     uint32_t P, q, qt, v0, nvp, pass, mode;
+    uint32_t qlo;       // query's best buffered value at the start of the pass (INF: unknown)
     float alpha, eps;
     uint32_t* gstate;   // global state of the query (dist, or r for PPR)
     float* gp;          // PPR p
     uint32_t* st;       // LDS slice
     uint32_t* bits;     // LDS in-frontier flags
     // per-thread counters
-    unsigned long long c_edges, c_intra, c_improved, c_emitted, c_consumed, c_vpush, c_chunks;
+    unsigned long long c_edges, c_intra, c_improved, c_emitted, c_consumed, c_vpush, c_chunks, c_pruned;
     // per-item usefulness (trace runs): work units whose value was final / all
     float it_useful, it_work;
     const uint32_t* gfinal;  // final state of the query (trace runs), else NULL
@@ -312,7 +313,7 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
                     if (j + 1 == need) {
                         int32_t old = dev_xchg(&c.B.bhead[b], (int32_t)first);
                         c.B.cnext[ch] = old;
-                        if (old < 0) dev_add(&c.B.pqn[T], 1u);  // the buffer became non-empty
+                        if (old < 0) c.B.bfirst[b] = c.pass;  // the buffer became non-empty
                         // publish the tail only after its slots are reserved
                         if (r0 == 0) dev_xchg(&c.B.btail[b], (int32_t)ch);
                         else dev_or(&c.B.ctl->err, (uint32_t)ERR_CORRUPT);
@@ -320,23 +321,15 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
                     prev = ch;
                 }
             }
-            dev_add(&c.B.pcount[T], len);
-            dev_min(&c.B.pfirst[T], c.pass);
-            if (!is_ppr) {
-                uint32_t mn = INF;
-                for (uint32_t j = rsv; j <= i; ++j) {
-                    uint32_t v = (uint32_t)S.sk[j] & ~RETAIN;
-                    mn = v < mn ? v : mn;
-                }
-                dev_min(c.qt == Q_BFS ? &c.B.pbest_lv[T] : &c.B.pbest_sp[T], mn);
-            } else {
-                float mx = 0.f;
-                for (uint32_t j = rsv; j <= i; ++j) {
-                    float f = __uint_as_float((uint32_t)S.sk[j]);
-                    mx = f > mx ? f : mx;
-                }
-                dev_max(&c.B.pbest_pr[T], __float_as_uint(mx));
+            // bucket summary for the scheduler: operation count and best value
+            dev_add(&c.B.bcnt[b], len);
+            uint32_t best = 0xffffffffu;
+            for (uint32_t j = rsv; j <= i; ++j) {
+                uint32_t v = (uint32_t)S.sk[j];
+                v = is_ppr ? ~v : (v & ~RETAIN);
+                best = v < best ? v : best;
             }
+            dev_min(&c.B.bval[b], best);
             c.c_emitted += len;
         }
     }
@@ -520,7 +513,7 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
         uint32_t lo = INF;
         for (uint32_t i = t; i < nf; i += NT) { uint32_t d = c.st[S.fq[S.cur][i]]; lo = d < lo ? d : lo; }
         lo = block_min(S, lo);
-        if (first_lo == INF) first_lo = lo;
+        if (first_lo == INF) first_lo = c.qlo != INF ? c.qlo : lo;
         if ((yld && (unsigned long long)lo >= (unsigned long long)first_lo + yld) || (budget && edges >= budget)) break;
         uint32_t hi = lo + win;
         if (hi < lo || hi > INF) hi = INF;
@@ -566,7 +559,13 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
                 if (nd < old) { ++c.c_improved; win_ = tas(c.bits, ul); }
             }
             push_frontier(c, S, cur, win_, ul, nd | RETAIN);
-            stage(S, valid && !intra, u, nd);
+            // sender-side pruning (the paper's walk-through of Appendix B.3):
+            // no operation is sent when the target already has a path at
+            // least as short.  The stored distance can only be stale-high
+            // (distances only decrease), so pruning never drops useful work.
+            bool send = valid && !intra;
+            if (send && nd >= c.gstate[u]) { send = false; ++c.c_pruned; }
+            stage(S, send, u, nd);
         }
         __syncthreads();
         if (t == 0 && S.nf > (uint32_t)FCAP) S.nf = FCAP;
@@ -715,6 +714,7 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
         c.gp = (float*)(Q.state + off);
         c.gstate = ppr ? Q.state + off + g.nv : Q.state + off;
         c.gfinal = (cfg.trace && Q.final_state) ? Q.final_state + off : nullptr;
+        c.qlo = (cfg.gate && !ppr) ? B.qmin[c.q] : INF;
         c.it_useful = 0.f;
         c.it_work = 0.f;
         // the slice is staged into LDS on first touch
@@ -759,17 +759,18 @@ __device__ __forceinline__ void init_ctx(ItemCtx& c, const GraphDev& g, const Qu
     c.B = B;
     c.st = dyn;
     c.bits = dyn + slice_words;
-    c.c_edges = c.c_intra = c.c_improved = c.c_emitted = c.c_consumed = c.c_vpush = c.c_chunks = 0;
+    c.c_edges = c.c_intra = c.c_improved = c.c_emitted = c.c_consumed = c.c_vpush = c.c_chunks = c.c_pruned = 0;
 }
 
 __device__ __forceinline__ void publish_counters(const ItemCtx& c, unsigned long long items) {
     const uint32_t t = threadIdx.x;
     const BufDev& B = c.B;
-    unsigned long long v[7] = {c.c_edges, c.c_intra, c.c_improved, c.c_emitted, c.c_consumed, c.c_vpush, c.c_chunks};
-    unsigned long long* dst[7] = {&B.ctl->c_edges, &B.ctl->c_intra, &B.ctl->c_improved, &B.ctl->c_emitted,
-                                  &B.ctl->c_consumed, &B.ctl->c_vpush, &B.ctl->c_chunks};
+    unsigned long long v[8] = {c.c_edges, c.c_intra, c.c_improved, c.c_emitted, c.c_consumed, c.c_vpush, c.c_chunks,
+                               c.c_pruned};
+    unsigned long long* dst[8] = {&B.ctl->c_edges, &B.ctl->c_intra, &B.ctl->c_improved, &B.ctl->c_emitted,
+                                  &B.ctl->c_consumed, &B.ctl->c_vpush, &B.ctl->c_chunks, &B.ctl->c_pruned};
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < 8; ++k) {
         unsigned long long x = v[k];
 #pragma unroll
         for (int o = 32; o; o >>= 1) x += __shfl_xor(x, o);
@@ -791,7 +792,8 @@ __global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B
 }
 
 // Persistent form: one cooperative launch runs up to max_passes passes of
-// Algorithm 2 -- [learned scoring], selection (block 0), detachment into the
+// Algorithm 2 -- buffer summaries (all blocks), [learned scoring], selection
+// (block 0), detachment into the
 // per-XCD work queues (all blocks), processing (all blocks) -- separated by
 // grid-wide barriers, and stops by itself when no buffer holds work.
 template <int WB>
@@ -806,6 +808,11 @@ __global__ __launch_bounds__(NT) void k_persistent(GraphDev g, QueryDev Q, BufDe
     const uint32_t t = threadIdx.x;
     const uint32_t dyn_words = slice_words + (slice_words + 31) / 32;
     for (uint32_t pass = 0; pass < max_passes; ++pass) {
+        // partition summaries from the buffers: per-query windows, then per partition
+        for (uint32_t q = blockIdx.x * NT + t; q < Q.nq; q += gridDim.x * NT) qmin_one(B, Q, g.np, q);
+        grid.sync();
+        for (uint32_t P = blockIdx.x; P < g.np; P += gridDim.x) psum_one(B, Q, cfg, P);
+        grid.sync();
         if (cfg.sched == S_LEARNED) {
             if (blockIdx.x == 0) gstat_body(g, B, gs);
             grid.sync();
@@ -835,7 +842,7 @@ __global__ __launch_bounds__(NT) void k_persistent(GraphDev g, QueryDev Q, BufDe
         const uint32_t nqp = (Q.nq + WAVE - 1) / WAVE * WAVE;
         const unsigned long long total = (unsigned long long)nsel * nqp;
         for (unsigned long long i = (unsigned long long)blockIdx.x * NT + t; i < total; i += (unsigned long long)gridDim.x * NT)
-            worklist_one(B, Q, (uint32_t)(i / nqp), (uint32_t)(i % nqp));
+            worklist_one(B, Q, cfg, (uint32_t)(i / nqp), (uint32_t)(i % nqp));
         grid.sync();
         process_items<WB>(c, S, cfg, items);
         grid.sync();

@@ -18,7 +18,8 @@
 
 namespace fk {
 hipError_t launch_select(const GraphDev&, const BufDev&, const PassCfg&, hipStream_t);
-hipError_t launch_worklist(const BufDev&, const QueryDev&, uint32_t, hipStream_t);
+hipError_t launch_worklist(const BufDev&, const QueryDev&, const PassCfg&, hipStream_t);
+hipError_t launch_summaries(const GraphDev&, const BufDev&, const QueryDev&, const PassCfg&, hipStream_t);
 hipError_t launch_process(const GraphDev&, const QueryDev&, const BufDev&, const PassCfg&, uint32_t, uint32_t, hipStream_t);
 size_t process_dyn_lds(uint32_t vpmax);
 int process_threads();
@@ -86,7 +87,7 @@ struct fork_ctx {
     // partition summaries
     uint32_t *d_pcount = nullptr, *d_pbest_sp = nullptr, *d_pbest_lv = nullptr, *d_pbest_pr = nullptr,
              *d_pfirst = nullptr, *d_plast = nullptr, *d_pvisits = nullptr, *d_pn = nullptr,
-             *d_sel = nullptr, *d_pqn = nullptr;
+             *d_sel = nullptr, *d_pqn = nullptr, *d_pready = nullptr;
     float* d_score = nullptr;
     float* d_mlp = nullptr;
     float* d_feat = nullptr;       // [np*16] features (trace runs)
@@ -106,6 +107,7 @@ struct fork_ctx {
     uint32_t* d_state = nullptr;
     int32_t* d_bhead = nullptr;
     int32_t* d_btail = nullptr;
+    uint32_t *d_bval = nullptr, *d_bcnt = nullptr, *d_bfirst = nullptr, *d_qmin = nullptr;
     fk::Item* d_items = nullptr;
     uint32_t item_cap = 0, kmax_cap = 0;
     uint32_t *d_qtype = nullptr, *d_qsrc = nullptr, *d_qmode = nullptr;
@@ -146,6 +148,10 @@ static void free_wave(fork_ctx* c) {
     hipFree(c->d_state); c->d_state = nullptr;
     hipFree(c->d_bhead); c->d_bhead = nullptr;
     hipFree(c->d_btail); c->d_btail = nullptr;
+    hipFree(c->d_bval); c->d_bval = nullptr;
+    hipFree(c->d_bcnt); c->d_bcnt = nullptr;
+    hipFree(c->d_bfirst); c->d_bfirst = nullptr;
+    hipFree(c->d_qmin); c->d_qmin = nullptr;
     hipFree(c->d_items); c->d_items = nullptr;
     hipFree(c->d_qtype); c->d_qtype = nullptr;
     hipFree(c->d_qsrc); c->d_qsrc = nullptr;
@@ -165,7 +171,7 @@ extern "C" void fork_destroy(fork_ctx* c) {
     free_wave(c);
     void* ptrs[] = {c->d_rowptr, c->d_col, c->d_w, c->d_pstart, c->d_vpart, c->d_chunks, c->d_cnext,
                     c->d_ccount, c->d_ring, c->d_pcount, c->d_pbest_sp, c->d_pbest_lv, c->d_pbest_pr,
-                    c->d_pfirst, c->d_plast, c->d_pvisits, c->d_pn, c->d_sel, c->d_pqn, c->d_score, c->d_mlp,
+                    c->d_pfirst, c->d_plast, c->d_pvisits, c->d_pn, c->d_sel, c->d_pqn, c->d_pready, c->d_score, c->d_mlp,
                     c->d_ctl, c->d_gstat, c->d_feat, c->d_tr, c->d_final};
     for (void* p : ptrs) if (p) hipFree(p);
     if (c->h_ctl) hipHostFree(c->h_ctl);
@@ -309,7 +315,7 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     if ((rc = dalloc(&c->d_ring, c->nch))) return cleanup(rc);
     // partition summaries
     uint32_t** parr[] = {&c->d_pcount, &c->d_pbest_sp, &c->d_pbest_lv, &c->d_pbest_pr, &c->d_pfirst,
-                         &c->d_plast, &c->d_pvisits, &c->d_pn, &c->d_sel, &c->d_pqn};
+                         &c->d_plast, &c->d_pvisits, &c->d_pn, &c->d_sel, &c->d_pqn, &c->d_pready};
     for (auto pp : parr) if ((rc = dalloc(pp, c->np + 1))) return cleanup(rc);
     if ((rc = dalloc(&c->d_score, c->np + 1))) return cleanup(rc);
     if ((rc = dalloc(&c->d_mlp, fk::MLP_NPARAM))) return cleanup(rc);
@@ -394,6 +400,8 @@ static int ensure_wave(fork_ctx* c, uint32_t nq, size_t words, uint32_t kmax) {
     int rc;
     if (nq > c->qcap || kmax > c->kmax_cap) {
         hipFree(c->d_bhead); hipFree(c->d_btail); hipFree(c->d_items);
+        hipFree(c->d_bval); hipFree(c->d_bcnt); hipFree(c->d_bfirst); hipFree(c->d_qmin);
+        c->d_bval = c->d_bcnt = c->d_bfirst = c->d_qmin = nullptr;
         hipFree(c->d_qtype); hipFree(c->d_qsrc); hipFree(c->d_qmode); hipFree(c->d_qoff);
         hipFree(c->d_qalpha); hipFree(c->d_qeps); hipFree(c->d_digest);
         c->d_bhead = nullptr; c->d_btail = nullptr; c->d_items = nullptr;
@@ -402,6 +410,10 @@ static int ensure_wave(fork_ctx* c, uint32_t nq, size_t words, uint32_t kmax) {
         size_t nb = (size_t)c->np * qc;
         if ((rc = dalloc(&c->d_bhead, nb))) return rc;
         if ((rc = dalloc(&c->d_btail, nb))) return rc;
+        if ((rc = dalloc(&c->d_bval, nb))) return rc;
+        if ((rc = dalloc(&c->d_bcnt, nb))) return rc;
+        if ((rc = dalloc(&c->d_bfirst, nb))) return rc;
+        if ((rc = dalloc(&c->d_qmin, qc))) return rc;
         c->item_cap = ((kc + fk::NXCD - 1) / fk::NXCD) * qc;
         if ((rc = dalloc(&c->d_items, (size_t)fk::NXCD * c->item_cap))) return rc;
         if ((rc = dalloc(&c->d_qtype, qc))) return rc;
@@ -432,7 +444,8 @@ static fk::GraphDev graph_dev(const fork_ctx* c) {
 
 static fk::BufDev buf_dev(const fork_ctx* c) {
     fk::BufDev B;
-    B.bhead = c->d_bhead; B.btail = c->d_btail; B.chunks = c->d_chunks; B.cnext = c->d_cnext;
+    B.bhead = c->d_bhead; B.btail = c->d_btail; B.bval = c->d_bval; B.bcnt = c->d_bcnt; B.bfirst = c->d_bfirst;
+    B.qmin = c->d_qmin; B.pready = c->d_pready; B.chunks = c->d_chunks; B.cnext = c->d_cnext;
     B.ccount = c->d_ccount; B.ring = c->d_ring; B.nch = c->nch; B.pcount = c->d_pcount;
     B.pbest_sp = c->d_pbest_sp; B.pbest_lv = c->d_pbest_lv; B.pbest_pr = c->d_pbest_pr;
     B.pfirst = c->d_pfirst; B.plast = c->d_plast; B.pvisits = c->d_pvisits; B.pn = c->d_pn;
@@ -485,6 +498,9 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
     }
     HIPCHK(hipMemsetAsync(c->d_bhead, 0xff, (size_t)c->np * c->qcap * 4, s));
     HIPCHK(hipMemsetAsync(c->d_btail, 0xff, (size_t)c->np * c->qcap * 4, s));
+    HIPCHK(hipMemsetAsync(c->d_bval, 0xff, (size_t)c->np * c->qcap * 4, s));
+    HIPCHK(hipMemsetAsync(c->d_bcnt, 0, (size_t)c->np * c->qcap * 4, s));
+    HIPCHK(hipMemsetAsync(c->d_bfirst, 0xff, (size_t)c->np * c->qcap * 4, s));
     HIPCHK(hipMemsetAsync(c->d_ccount, 0, (size_t)c->nch * 4, s));
     HIPCHK(hipMemsetAsync(c->d_pcount, 0, (c->np + 1) * 4ull, s));
     HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->d_pbest_sp, (int)fk::INF, c->np + 1, s));
@@ -527,9 +543,10 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
         if (trace) {
             // one pass with the features of every partition and the usefulness of the visits
             HIPCHK(hipMemsetAsync(c->d_tr, 0, (size_t)c->np * 2 * sizeof(float), s));
+            HIPCHK(fk::launch_summaries(g, B, Q, pc, s));
             HIPCHK(fk::launch_mlp_score(g, B, c->d_mlp, c->d_score, c->d_feat, c->d_gstat, 0, s));
             HIPCHK(fk::launch_select(g, B, pc, s));
-            HIPCHK(fk::launch_worklist(B, Q, pc.kmax, s));
+            HIPCHK(fk::launch_worklist(B, Q, pc, s));
             HIPCHK(fk::launch_process(g, Q, B, pc, blocks, c->vpmax, s));
             std::vector<uint32_t> sel(c->np);
             std::vector<float> feat((size_t)c->np * fk::MLP_IN), tr((size_t)c->np * 2);
@@ -562,10 +579,11 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
             nb = 1;
         } else {
             for (uint32_t k = 0; k < nb; ++k) {
+                HIPCHK(fk::launch_summaries(g, B, Q, pc, s));
                 if (pc.sched == fk::S_LEARNED)
                     HIPCHK(fk::launch_mlp_score(g, B, c->d_mlp, c->d_score, nullptr, c->d_gstat, 0, s));
                 HIPCHK(fk::launch_select(g, B, pc, s));
-                HIPCHK(fk::launch_worklist(B, Q, pc.kmax, s));
+                HIPCHK(fk::launch_worklist(B, Q, pc, s));
                 if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k], s));
                 HIPCHK(fk::launch_process(g, Q, B, pc, blocks, c->vpmax, s));
                 if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k + 1], s));
@@ -640,6 +658,7 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
     st.yields += h.c_yields;
     st.chunks += h.c_chunks;
     st.intra_edges += h.c_intra;
+    st.pruned += h.c_pruned;
     st.waves += 1;
     c->res_first = q0;
     c->res_n = nq;
@@ -678,9 +697,10 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     // has advanced `delta` past its first value (default: 64 mean weights).
     const double wm = c->wbytes ? c->wmean : 1.0;
     uint32_t delta = o.delta ? o.delta : (uint32_t)std::min(1.0e9, 64.0 * wm);
-    cfg.win_sp = std::max<uint32_t>(1u, (uint32_t)(2.0 * wm));
+    cfg.win_sp = o.window ? o.window : std::max<uint32_t>(1u, (uint32_t)(2.0 * wm));
     cfg.yld_sp = delta;
     cfg.win_lv = 1;
+    cfg.gate = o.window_mode == 0 ? 1u : 0u;
     cfg.yld_lv = o.delta ? std::max<uint32_t>(1u, (uint32_t)(o.delta / wm)) : 64u;
     if (o.scheduler == FORK_SCHED_LEARNED) {
         HIPCHK(hipMemcpyAsync(c->d_mlp, o.mlp_weights, fk::MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));

@@ -61,7 +61,7 @@ __device__ void select_body(const GraphDev& g, const BufDev& B, const PassCfg& c
     // key: (priority << 16 | partition) -- smaller is better, unique
     auto key_of = [&](uint32_t P) -> unsigned long long {
         uint32_t cnt = B.pcount[P];
-        if (!cnt) return ~0ull;
+        if (!cnt || !B.pready[P]) return ~0ull;
         uint32_t k;
         switch (cfg.sched) {
         case S_FIFO: k = B.pfirst[P]; break;
@@ -91,12 +91,12 @@ __device__ void select_body(const GraphDev& g, const BufDev& B, const PassCfg& c
     if (cached) {
         for (uint32_t P = tid; P < np; P += NTH) {
             s_key[P] = key_of(P);
-            s_qn[P] = B.pqn[P];
+            s_qn[P] = B.pready[P];
         }
         __syncthreads();
     }
     auto key_at = [&](uint32_t P) -> unsigned long long { return cached ? s_key[P] : key_of(P); };
-    auto qn_at = [&](uint32_t P) -> uint32_t { return cached ? s_qn[P] : B.pqn[P]; };
+    auto qn_at = [&](uint32_t P) -> uint32_t { return cached ? s_qn[P] : B.pready[P]; };
     const uint32_t kmax = cfg.kmax;
     const uint32_t target = cfg.target_items;
     // Take partitions in priority order until kmax of them, or until their
@@ -106,7 +106,7 @@ __device__ void select_body(const GraphDev& g, const BufDev& B, const PassCfg& c
         if (tid == 0) s_cnt = 0;
         __syncthreads();
         uint32_t it = 0;
-        for (uint32_t P = tid; P < np; P += NTH) it += B.pcount[P] ? B.pqn[P] : 0u;
+        for (uint32_t P = tid; P < np; P += NTH) it += B.pcount[P] ? B.pready[P] : 0u;
         if (it) atomicAdd(&s_cnt, (unsigned long long)it);
         __syncthreads();
         items_all = s_cnt;
@@ -150,15 +150,9 @@ __device__ void select_body(const GraphDev& g, const BufDev& B, const PassCfg& c
     uint32_t nsel = s_nsel < kmax ? s_nsel : kmax;
     for (uint32_t j = tid; j < nsel; j += NTH) {
         uint32_t P = B.sel[j];
-        B.pcount[P] = 0;
-        B.pbest_sp[P] = INF;
-        B.pbest_lv[P] = INF;
-        B.pbest_pr[P] = 0;
-        B.pfirst[P] = INF;
         B.plast[P] = pass;
         B.pvisits[P] += 1;
         B.pn[P] = 0;
-        B.pqn[P] = 0;
     }
     if (tid < NXCD) { ctl->nitems[tid] = 0; ctl->next[tid] = 0; }
     if (tid == 0) {
@@ -173,7 +167,8 @@ __device__ void select_body(const GraphDev& g, const BufDev& B, const PassCfg& c
 
 // Detach the buffer of (selected partition j, query q) into a work item.
 // Lanes of one wave must share j (one reservation per wave).
-__device__ __forceinline__ void worklist_one(const BufDev& B, const QueryDev& Q, uint32_t j, uint32_t q) {
+__device__ __forceinline__ void worklist_one(const BufDev& B, const QueryDev& Q, const PassCfg& cfg, uint32_t j,
+                                             uint32_t q) {
     Ctl* ctl = B.ctl;
     const uint32_t P = B.sel[j];
     const uint32_t x = j % NXCD;
@@ -181,7 +176,10 @@ __device__ __forceinline__ void worklist_one(const BufDev& B, const QueryDev& Q,
     bool has = false;
     int32_t h = -1;
     unsigned long long b = (unsigned long long)P * Q.qc + q;
-    if (q < Q.nq) { h = B.bhead[b]; has = h >= 0; }
+    if (q < Q.nq) {
+        h = B.bhead[b];
+        has = h >= 0 && bucket_ready(B.bval[b], Q.qtype[q], B.qmin[q], cfg);
+    }
     unsigned long long mask = wballot(has);
     uint32_t n = __popcll(mask);
     if (!n) return;
@@ -199,10 +197,70 @@ __device__ __forceinline__ void worklist_one(const BufDev& B, const QueryDev& Q,
             B.items[(unsigned long long)x * B.item_cap + pos] = it;
             B.bhead[b] = -1;
             B.btail[b] = -1;
+            B.bval[b] = 0xffffffffu;
+            B.bcnt[b] = 0;
         } else {
             dev_or(&ctl->err, (uint32_t)ERR_ITEMS);
         }
     }
+}
+
+// Per query: its best buffered SSSP/BFS value over all partitions (the
+// dist_min of heuristic 2, Section 5.1).
+__device__ __forceinline__ void qmin_one(const BufDev& B, const QueryDev& Q, uint32_t np, uint32_t q) {
+    if (q >= Q.nq) return;
+    uint32_t m = 0xffffffffu;
+    if (Q.qtype[q] != Q_PPR)
+        for (uint32_t P = 0; P < np; ++P) {
+            unsigned long long b = (unsigned long long)P * Q.qc + q;
+            if (B.bcnt[b]) { uint32_t v = B.bval[b]; m = v < m ? v : m; }
+        }
+    B.qmin[q] = m;
+}
+
+// Partition summary from its buffers (one block): buffered operations, best
+// SSSP distance / BFS level / PPR mass, non-empty and ready buffers, age of
+// the oldest buffer.  These are what the priority functor and the learned
+// scorer read.
+__device__ void psum_one(const BufDev& B, const QueryDev& Q, const PassCfg& cfg, uint32_t P) {
+    __shared__ unsigned long long s_cnt;
+    __shared__ unsigned int s_sp, s_lv, s_pr, s_ne, s_rd, s_first;
+    if (threadIdx.x == 0) { s_cnt = 0; s_sp = INF; s_lv = INF; s_pr = 0; s_ne = 0; s_rd = 0; s_first = INF; }
+    __syncthreads();
+    unsigned long long cnt = 0;
+    uint32_t sp = INF, lv = INF, pr = 0, ne = 0, rd = 0, first = INF;
+    for (uint32_t q = threadIdx.x; q < Q.nq; q += blockDim.x) {
+        unsigned long long b = (unsigned long long)P * Q.qc + q;
+        uint32_t cb = B.bcnt[b];
+        if (!cb) continue;
+        uint32_t v = B.bval[b], t = Q.qtype[q];
+        cnt += cb;
+        ++ne;
+        if (t == Q_PPR) { uint32_t m = ~v; pr = m > pr ? m : pr; }
+        else if (t == Q_BFS) lv = v < lv ? v : lv;
+        else sp = v < sp ? v : sp;
+        rd += bucket_ready(v, t, B.qmin[q], cfg);
+        uint32_t f = B.bfirst[b];
+        first = f < first ? f : first;
+    }
+    if (cnt) atomicAdd(&s_cnt, cnt);
+    if (sp < INF) atomicMin(&s_sp, sp);
+    if (lv < INF) atomicMin(&s_lv, lv);
+    if (pr) atomicMax(&s_pr, pr);
+    if (ne) atomicAdd(&s_ne, ne);
+    if (rd) atomicAdd(&s_rd, rd);
+    if (first < INF) atomicMin(&s_first, first);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        B.pcount[P] = s_cnt > 0xffffffffull ? 0xffffffffu : (uint32_t)s_cnt;
+        B.pbest_sp[P] = s_sp;
+        B.pbest_lv[P] = s_lv;
+        B.pbest_pr[P] = s_pr;
+        B.pqn[P] = s_ne;
+        B.pready[P] = s_rd;
+        B.pfirst[P] = s_first;
+    }
+    __syncthreads();
 }
 
 }  // namespace fk

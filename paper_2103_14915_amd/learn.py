@@ -61,7 +61,12 @@ def target_of(records: np.ndarray) -> np.ndarray:
     return np.log1p(records[:, 16]).astype(np.float32)
 
 
-def collect(spec: dict, n_sssp: int, n_ppr: int, partition_vertices: int = 0, log=print) -> np.ndarray:
+# run knobs for traces and for learned runs of the SSSP+PPR mix (the autotuned
+# setting of the scale-20 mix: SSSP window 16, Delta 512, 16K items per pass)
+RUN_KW = dict(window=16, delta=512, items_per_pass=16384)
+
+
+def collect(spec: dict, n_sssp: int, n_ppr: int, partition_vertices: int = 0, log=print, **run_kw) -> np.ndarray:
     import fpp_inputs as fi
 
     g = fi.rmat(spec["scale"], seed=spec["seed"], weights=(1, 255), weight_seed=spec["wseed"])
@@ -71,7 +76,7 @@ def collect(spec: dict, n_sssp: int, n_ppr: int, partition_vertices: int = 0, lo
     if n_ppr:
         fg.submit("ppr", fi.sources_mixed(g, n_ppr, spec["sseed"] + 1), alpha=0.15, epsilon=1e-6, eps_mode=1)
     t0 = time.time()
-    fg.run(scheduler="priority", trace=1)
+    fg.run(scheduler="priority", trace=1, **(run_kw or RUN_KW))
     rec = fg.trace()
     fg.close()
     log(f"[learn] traced rmat{spec['scale']} seed {spec['seed']}: {rec.shape[0]} visits in {time.time() - t0:.1f}s")
