@@ -118,7 +118,19 @@ def main():
     ap.add_argument("--no-tuned", action="store_true", help="ignore cached autotuner results")
     ap.add_argument("--compare-learned", default="", help="MLP weights (.npy): also time the learned scheduler "
                     "on the same workload and report the speedup over the rule-based one")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(queries shard across GPUs with no exchange; see DESIGN.md)"}))

@@ -198,7 +198,7 @@ class ForkGraph:
 
     def fetch(self, qid, field=None, out=None):
         """Result vector of query qid (numpy), or written into a device tensor `out`."""
-        t = self.types[qid]
+        t = self.types[qid] if 0 <= qid < len(self.types) else SSSP  # out of range: the C ABI rejects it
         if field is None:
             field = FIELD_VALUE if t != PPR else FIELD_P
         dtype = np.int32 if field == FIELD_VALUE else np.float32

@@ -57,7 +57,13 @@ def _load_cache() -> dict:
 
 
 def cached(g, queries) -> Optional[dict]:
-    return _load_cache().get(f"{signature(g, queries)}|{device_name()}", {}).get("params")
+    """Tuned knobs for this graph and query mix: this device's entry, else any device's."""
+    cache = _load_cache()
+    sig = signature(g, queries)
+    hit = cache.get(f"{sig}|{device_name()}")
+    if hit is None:
+        hit = next((v for k, v in cache.items() if k.split("|")[0] == sig), None)
+    return None if hit is None else hit.get("params")
 
 
 def _sample(queries, n):

@@ -304,7 +304,7 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     if (!pool) {
         size_t fr = 0, tot = 0;
         hipMemGetInfo(&fr, &tot);
-        pool = std::min<uint64_t>((uint64_t)24 << 30, std::max<uint64_t>((uint64_t)64 << 20, fr / 8));
+        pool = std::min<uint64_t>((uint64_t)64 << 30, std::max<uint64_t>((uint64_t)64 << 20, fr / 4));
     }
     const uint64_t per_chunk = sizeof(uint2) * fk::CH + 4 + 4 + 4;
     c->nch = std::max<uint64_t>(1024, pool / per_chunk);

@@ -1,0 +1,202 @@
+"""GPU parity at the workloads' full graph sizes, plus the error paths of the
+C ABI on a real device.
+
+Full-size runs use the autotuned knobs of the workload (as bench.py does)
+and check the outputs the CPU oracle can compute one by one: a seeded sample
+of queries compared element by element (SSSP/BFS bit-exact, PPR push
+invariant within 1e-4 L1 and termination), plus the optimality certificate
+and digests.  The scale-22 and scale-23 graphs run a seeded subset of their
+queries (the full query sets take minutes of GPU time)."""
+import sys
+
+import numpy as np
+import pytest
+
+import fpp_inputs as fi
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _fork():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2103_14915_amd as fork
+    return fork
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# knobs autotuned for the scale-20 R-MAT SSSP+PPR mix; used for R-MAT graphs without a cached tuning
+RMAT_KNOBS = {"partition_vertices": 16384, "items_per_pass": 16384, "window": 16, "delta": 512, "persistent": 0}
+
+
+def knobs(g, queries, fallback=None):
+    from paper_2103_14915_amd import autotune
+    return autotune.cached(g, queries) or dict(fallback or autotune.DEFAULTS)
+
+
+def mix64(z):
+    """SplitMix64 finaliser (Steele, Lea, Flood 2014), vectorised over uint64."""
+    with np.errstate(over="ignore"):
+        z = (z + np.uint64(0x9E3779B97F4A7C15)).astype(np.uint64)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def sp_digest(vec):
+    v = np.flatnonzero(vec != np.int32(0x7FFFFFFF))
+    x = vec[v].astype(np.uint64)
+    with np.errstate(over="ignore"):
+        h = np.sum(mix64((v.astype(np.uint64) << np.uint64(32)) | x), dtype=np.uint64)
+    return int(v.size), int(x.sum()), int(h)
+
+
+def run_workload(fork, g, queries, spec, p):
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=p["partition_vertices"])
+    for qt, s in queries:
+        fg.submit(qt, s, alpha=spec.get("alpha", 0.15), epsilon=spec.get("epsilon", 1e-6),
+                  eps_mode=spec.get("eps_mode", 0))
+    fg.run(items_per_pass=p["items_per_pass"], window=p["window"], delta=p["delta"], persistent=p["persistent"])
+    return fg
+
+
+def check_sp_sample(fork, fg, g, srcs, first_id, kind, n, seed):
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(len(srcs), min(n, len(srcs)), replace=False))
+    ref = oracle.sssp(g, srcs[idx]) if kind == "sssp" else oracle.bfs(g, srcs[idx])
+    resident = 0
+    for k, i in enumerate(idx):
+        d = fg.digest(first_id + int(i))  # digests exist for every wave
+        assert (d["count"], d["sum"], d["hash"]) == sp_digest(ref[k]), f"{kind} query {i} digest"
+        try:
+            got = fg.fetch(first_id + int(i))
+        except fork.ForkError as e:  # vectors stay resident for the last wave only
+            assert e.code == fork.FORK_E_STATE
+            continue
+        resident += 1
+        np.testing.assert_array_equal(got, ref[k], err_msg=f"{kind} query {i}")
+        assert oracle.sp_certificate(g, srcs[i], got, unit_weights=kind == "bfs") == 0
+    return resident
+
+
+def check_ppr_sample(fork, fg, g, srcs, first_id, spec, n, seed):
+    rng = np.random.default_rng(seed)
+    eps, mode, alpha = spec["epsilon"], spec.get("eps_mode", 0), spec["alpha"]
+    idx = np.sort(rng.choice(len(srcs), min(n, len(srcs)), replace=False))
+    keep = []
+    for i in idx:  # vectors of earlier waves are not resident; their digests are checked
+        d = fg.digest(first_id + int(i))
+        assert d["fsum"] > 0.14 and d["fres"] >= 0.0 and d["fsum"] + d["fres"] <= 1.0 + 1e-3
+        try:
+            fg.fetch(first_id + int(i), fork.FIELD_P)
+            keep.append(i)
+        except fork.ForkError as e:
+            assert e.code == fork.FORK_E_STATE
+    idx = np.asarray(keep, np.int64)
+    if idx.size == 0:
+        return
+    P = np.stack([fg.fetch(first_id + int(i), fork.FIELD_P) for i in idx]).astype(np.float64)
+    R32 = np.stack([fg.fetch(first_id + int(i), fork.FIELD_R) for i in idx])
+    R = R32.astype(np.float64)
+    x0 = -R.copy()
+    x0[np.arange(len(idx)), srcs[idx].astype(np.int64)] += 1.0
+    ref = oracle.ppr_power(g, x0, alpha)
+    for k, i in enumerate(idx):
+        assert np.all(P[k] >= 0) and np.all(R[k] >= 0)
+        assert oracle.push_terminal(g, R32[k], eps, mode, dtype=np.float32), f"ppr query {i}"
+        inv = float(np.abs(P[k] - ref[k]).sum())
+        assert inv <= 1e-4, f"ppr query {i}: invariant L1 {inv}"
+
+
+def test_error_paths_on_device():
+    fork = _fork()
+    g = fi.rmat(10, seed=3, weights=(1, 9), weight_seed=4)
+    fg = fork.ForkGraph.from_graph(g)
+    with pytest.raises(fork.ForkError) as e:
+        fg.run()
+    assert e.value.code == fork.FORK_E_STATE            # nothing submitted
+    fg.submit("sssp", [1, 2, 3])
+    with pytest.raises(fork.ForkError) as e:
+        fg.fetch(0)
+    assert e.value.code == fork.FORK_E_STATE            # not run yet
+    with pytest.raises(fork.ForkError) as e:
+        fg.submit("sssp", [5, g.num_vertices])          # one bad source: nothing enqueued
+    assert e.value.code == fork.FORK_E_INVALID
+    with pytest.raises(fork.ForkError) as e:
+        fg.submit("ppr", [5], alpha=1.5)
+    assert e.value.code == fork.FORK_E_INVALID
+    with pytest.raises(fork.ForkError) as e:
+        fg.submit(7, [5])
+    assert e.value.code == fork.FORK_E_INVALID
+    fg.run()
+    assert fg.stats()["waves"] == 1
+    np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(3)]), oracle.sssp(g, [1, 2, 3]))
+    with pytest.raises(fork.ForkError) as e:
+        fg.fetch(0, fork.FIELD_P)                       # SSSP has no p vector
+    assert e.value.code == fork.FORK_E_INVALID
+    with pytest.raises(fork.ForkError) as e:
+        fg.fetch(3)
+    assert e.value.code == fork.FORK_E_INVALID
+    with pytest.raises(fork.ForkError) as e:
+        fg.run(max_passes=1)                            # far fewer passes than needed
+    assert e.value.code == fork.FORK_E_NOT_CONVERGED
+    fg.run()                                            # the context stays usable
+    np.testing.assert_array_equal(fg.fetch(2), oracle.sssp(g, [3])[0])
+    fg.close()
+
+
+def test_rmat20_ppr4096_full():
+    fork = _fork()
+    spec = fi.WORKLOADS["rmat20_ppr4096"]
+    g = fi.make_graph(spec)
+    queries = fi.make_sources(g, spec)
+    p = knobs(g, queries)
+    say("rmat20 ppr4096", p)
+    fg = run_workload(fork, g, queries, spec, p)
+    srcs = queries[0][1]
+    d = [fg.digest(i) for i in range(len(srcs))]
+    assert all(x["fsum"] > 0.14 and x["fres"] >= 0 for x in d)
+    check_ppr_sample(fork, fg, g, srcs, 0, spec, 8, 1)
+    fg.close()
+
+
+def test_grid2048_sssp_bfs_full():
+    fork = _fork()
+    spec = fi.WORKLOADS["grid2048_sssp1024_bfs1024"]
+    g = fi.make_graph(spec)
+    queries = fi.make_sources(g, spec)
+    p = knobs(g, queries)
+    say("grid2048", p)
+    fg = run_workload(fork, g, queries, spec, p)
+    check_sp_sample(fork, fg, g, queries[0][1], 0, "sssp", 12, 2)
+    check_sp_sample(fork, fg, g, queries[1][1], 1024, "bfs", 12, 3)
+    # every query reaches the whole (connected) grid
+    assert all(fg.digest(i)["count"] == g.num_vertices for i in range(0, 2048, 97))
+    fg.close()
+
+
+@pytest.mark.parametrize("name,take", [("rmat22_mixed16384", (256, 128, 128)),
+                                       ("rmat23_sssp_ppr65536", (128, 128))])
+def test_large_rmat_query_subset(name, take):
+    """Full-size scale-22 / scale-23 graphs with a seeded subset of the queries."""
+    fork = _fork()
+    spec = fi.WORKLOADS[name]
+    g = fi.make_graph(spec)
+    queries = [(qt, s[:k]) for (qt, s), k in zip(fi.make_sources(g, spec), take)]
+    p = knobs(g, queries, RMAT_KNOBS)
+    say(name, [len(s) for _, s in queries], p)
+    fg = run_workload(fork, g, queries, spec, p)
+    first = 0
+    for k, (qt, s) in enumerate(queries):
+        if qt == "ppr":
+            check_ppr_sample(fork, fg, g, s, first, spec, 4, 10 + k)
+        else:
+            check_sp_sample(fork, fg, g, s, first, qt, 6, 10 + k)
+        first += len(s)
+    fg.close()
