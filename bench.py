@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--items-per-pass", type=int, default=0, help="work items queued per pass (0 = auto)")
     ap.add_argument("--window-mode", type=int, default=0, help="heuristic-2 window: 0 = query-global, 1 = per visit")
     ap.add_argument("--window", type=int, default=0, help="SSSP batch width inside a visit (0 = auto)")
+    ap.add_argument("--slice-slots", type=int, default=-1,
+                    help="LDS slice: 0 = dense, else hash-table slots (-1 = tuned/default)")
     ap.add_argument("--tune", action="store_true", help="run the autotuner on a query sample first (cached)")
     ap.add_argument("--no-tuned", action="store_true", help="ignore cached autotuner results")
     ap.add_argument("--compare-learned", default="", help="MLP weights (.npy): also time the learned scheduler "
@@ -166,6 +168,8 @@ def main():
                  ("window", args.window), ("delta", args.delta), ("persistent", int(args.persistent))):
         if v:
             params[k] = v
+    if args.slice_slots >= 0:
+        params["slice_slots"] = args.slice_slots
     t0 = time.perf_counter()
     fg = fork.ForkGraph.from_graph(g, partition_vertices=params["partition_vertices"], max_queries=args.max_queries)
     t_load = time.perf_counter() - t0
@@ -178,7 +182,8 @@ def main():
     kind = kinds[0] if len(kinds) == 1 else "mixed"
     run_kw = dict(scheduler=args.scheduler, parts_per_pass=args.parts_per_pass, delta=params["delta"],
                   edge_budget_mu=args.mu, stream=stream, profile=1, persistent=params["persistent"],
-                  items_per_pass=params["items_per_pass"], window_mode=args.window_mode, window=params["window"])
+                  items_per_pass=params["items_per_pass"], window_mode=args.window_mode, window=params["window"],
+                  slice_slots=params.get("slice_slots", 0))
     for _ in range(args.warmup):
         fg.run(**run_kw)
     torch.cuda.synchronize()

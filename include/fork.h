@@ -94,6 +94,13 @@ typedef struct {
     uint32_t window;           /* SSSP batch width inside a visit: vertices with
                                   distance in [lo, lo + window) expand together
                                   (0 = auto)                                     */
+    uint32_t slice_slots;      /* LDS copy of a visited partition's query state:
+                                  0 = dense (one word per partition vertex);
+                                  else a hash table of this many slots (power of
+                                  two, 256..16384) holding only the vertices the
+                                  visit touches, so more workgroups fit per CU;
+                                  vertices that find no free slot are updated in
+                                  place in global memory                          */
 } fork_run_opts;
 
 /* Counters accumulated over the last fork_run (all waves). */

@@ -52,7 +52,8 @@ class fork_run_opts(ctypes.Structure):
                 ("edge_budget_mu", ctypes.c_float), ("max_passes", ctypes.c_uint64),
                 ("stream", ctypes.c_void_p), ("mlp_weights", ctypes.c_void_p), ("persistent", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("profile", ctypes.c_int), ("items_per_pass", ctypes.c_uint32),
-                ("trace", ctypes.c_int), ("window_mode", ctypes.c_int), ("window", ctypes.c_uint32)]
+                ("trace", ctypes.c_int), ("window_mode", ctypes.c_int), ("window", ctypes.c_uint32),
+                ("slice_slots", ctypes.c_uint32)]
 
 
 class fork_stats_t(ctypes.Structure):
@@ -181,7 +182,7 @@ class ForkGraph:
 
     def run(self, scheduler="priority", parts_per_pass=0, delta=0, edge_budget_mu=0.0, max_passes=0,
             stream=None, mlp_weights=None, persistent=0, seed=0, profile=0, items_per_pass=0, trace=0,
-            window_mode=0, window=0):
+            window_mode=0, window=0, slice_slots=0):
         s = SCHEDS[scheduler] if isinstance(scheduler, str) else int(scheduler)
         w = None
         if mlp_weights is not None:
@@ -193,7 +194,7 @@ class ForkGraph:
             sp = stream if isinstance(stream, int) else stream.cuda_stream
         o = fork_run_opts(s, parts_per_pass, delta, edge_budget_mu, max_passes, sp,
                           None if w is None else w.ctypes.data, persistent, seed, profile, items_per_pass, trace,
-                          window_mode, window)
+                          window_mode, window, slice_slots)
         _check(lib.fork_run(self._ctx, ctypes.byref(o)))
 
     def fetch(self, qid, field=None, out=None):

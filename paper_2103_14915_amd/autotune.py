@@ -4,8 +4,9 @@ Picks the knobs that the paper fixes by hand (Section 6.1: partition size =
 LLC size; yield thresholds; one partition processed at a time) for the
 MI355X: partition size (vertices per LDS-staged slice), work items queued per
 pass (how many (partition, query) visits run between two scheduling steps),
-the SSSP batch window and the heuristic-2 range Delta, and whether the pass
-loop runs in one persistent kernel.  It times short runs on a seeded sample
+the SSSP batch window and the heuristic-2 range Delta, whether the pass
+loop runs in one persistent kernel, and the LDS slice shape (dense, or a hash
+table of touched vertices that lets more workgroups share a CU).  It times short runs on a seeded sample
 of the workload's queries and does coordinate descent from the defaults.
 Results are cached in JSON keyed by graph shape, query mix and device.
 
@@ -27,7 +28,8 @@ from . import ForkGraph
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.environ.get("FORK_TUNE_CACHE", os.path.join(HERE, "tune_cache.json"))
 
-DEFAULTS = {"partition_vertices": 16384, "items_per_pass": 0, "window": 0, "delta": 0, "persistent": 0}
+DEFAULTS = {"partition_vertices": 16384, "items_per_pass": 0, "window": 0, "delta": 0, "persistent": 0,
+            "slice_slots": 0}
 
 
 def device_name() -> str:
@@ -63,7 +65,7 @@ def cached(g, queries) -> Optional[dict]:
     hit = cache.get(f"{sig}|{device_name()}")
     if hit is None:
         hit = next((v for k, v in cache.items() if k.split("|")[0] == sig), None)
-    return None if hit is None else hit.get("params")
+    return None if hit is None else dict(DEFAULTS, **hit.get("params", {}))
 
 
 def _sample(queries, n):
@@ -84,7 +86,7 @@ def _trial(g, sample, spec, p, stream=None) -> float:
                       eps_mode=spec.get("eps_mode", 0))
             n += len(s)
         kw = dict(items_per_pass=p["items_per_pass"], window=p["window"], delta=p["delta"],
-                  persistent=p["persistent"], stream=stream)
+                  persistent=p["persistent"], slice_slots=p.get("slice_slots", 0), stream=stream)
         fg.run(**kw)
         t0 = time.perf_counter()
         fg.run(**kw)
@@ -100,6 +102,7 @@ def candidates(g, queries) -> dict:
         "partition_vertices": [4096, 8192, 16384],
         "items_per_pass": [0, 2048, 16384, 65536],
         "persistent": [0, 1],
+        "slice_slots": [0, 1024, 2048, 4096],
     }
     if kinds & {"sssp", "bfs"}:
         w = max(1, int(round(wmean)))

@@ -127,8 +127,10 @@ struct ItemCtx {
     float alpha, eps;
     uint32_t* gstate;   // global state of the query (dist, or r for PPR)
     float* gp;          // PPR p
-    uint32_t* st;       // LDS slice
-    uint32_t* bits;     // LDS in-frontier flags
+    uint32_t* st;       // LDS slice: values by vertex (dense) or by hash slot
+    uint32_t* hkeys;    // hashed slice: vertex of each slot (EMPTY_KEY if free)
+    uint32_t hmask;     // hashed slice: slots - 1 (0: dense slice)
+    uint32_t* bits;     // LDS in-frontier flags (by vertex)
     // per-thread counters
     unsigned long long c_edges, c_intra, c_improved, c_emitted, c_consumed, c_vpush, c_chunks, c_pruned;
     // per-item usefulness (trace runs): work units whose value was final / all
@@ -140,8 +142,57 @@ struct ItemCtx {
 // in proportion to the vertices it touches, not to the partition size.
 constexpr uint32_t UNLOADED = 0xffffffffu;  // no distance or residual has this value
 
-__device__ __forceinline__ void touch(const ItemCtx& c, uint32_t vloc) {
-    if (c.st[vloc] == UNLOADED) atomicCAS(&c.st[vloc], UNLOADED, c.gstate[c.v0 + vloc]);
+constexpr uint32_t EMPTY_KEY = 0xffffffffu;
+constexpr int MAXPROBE = 32;
+
+// Where vertex vloc's value lives during the visit, fetched on first touch.
+// Dense slice: st[vloc].  Hashed slice (for partitions whose visits touch few
+// of their vertices): an LDS open-addressing table; a vertex whose probe path
+// is full stays in global memory for the whole visit (slots are never freed
+// during a visit, so every thread reaches the same decision).
+__device__ __forceinline__ uint32_t* slot(const ItemCtx& c, uint32_t vloc) {
+    if (!c.hmask) {
+        if (c.st[vloc] == UNLOADED) atomicCAS(&c.st[vloc], UNLOADED, c.gstate[c.v0 + vloc]);
+        return &c.st[vloc];
+    }
+    // Fibonacci hashing: the top bits of vloc * 2^32/phi pick the home slot
+    uint32_t h = (uint32_t)(((unsigned long long)(vloc * 0x9E3779B1u) * (c.hmask + 1ull)) >> 32);
+    for (int i = 0; i < MAXPROBE; ++i) {
+        uint32_t k = c.hkeys[h];
+        if (k == EMPTY_KEY) k = atomicCAS(&c.hkeys[h], EMPTY_KEY, vloc);
+        if (k == EMPTY_KEY || k == vloc) {
+            if (c.st[h] == UNLOADED) atomicCAS(&c.st[h], UNLOADED, c.gstate[c.v0 + vloc]);
+            return &c.st[h];
+        }
+        h = (h + 1) & c.hmask;
+    }
+    return c.gstate + c.v0 + vloc;
+}
+
+// Value reads and updates through a slot: LDS instructions for the dense
+// slice, flat (LDS or L2) atomics for the hashed one.
+__device__ __forceinline__ uint32_t sv_get(const ItemCtx& c, uint32_t vloc) {
+    if (!c.hmask) return c.st[vloc];
+    return __hip_atomic_load(slot(c, vloc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t sv_min(const ItemCtx& c, uint32_t vloc, uint32_t x) {
+    uint32_t* p = slot(c, vloc);
+    if (!c.hmask) return atomicMin(p, x);
+    return __hip_atomic_fetch_min(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ float sv_addf(const ItemCtx& c, uint32_t vloc, float x) {
+    float* p = (float*)slot(c, vloc);
+    if (!c.hmask) return atomicAdd(p, x);
+    return __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ float sv_takef(const ItemCtx& c, uint32_t vloc) {
+    uint32_t* p = slot(c, vloc);
+    if (!c.hmask) { uint32_t m = *p; *p = 0u; return __uint_as_float(m); }
+    return __uint_as_float(__hip_atomic_exchange(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+}
+__device__ __forceinline__ void sv_putf(const ItemCtx& c, uint32_t vloc, float x) {
+    // give back residual that was taken but did not qualify for a push
+    if (x != 0.f) sv_addf(c, vloc, x);
 }
 
 __device__ __forceinline__ float thr_of(const ItemCtx& c, uint32_t gv) {
@@ -407,14 +458,13 @@ __device__ __forceinline__ void consume(ItemCtx& c, PassShared& S, int32_t head)
             uint32_t rv = 0;
             if (valid) {
                 ++c.c_consumed;
-                touch(c, vloc);
                 if (c.qt == Q_PPR) {
                     float mass = __uint_as_float(op.y);
-                    float nr = atomicAdd((float*)&c.st[vloc], mass) + mass;
+                    float nr = sv_addf(c, vloc, mass) + mass;
                     act = ppr_active(nr, thr_of(c, op.x));
                 } else {
                     uint32_t val = op.y & ~RETAIN;
-                    uint32_t old = atomicMin(&c.st[vloc], val);
+                    uint32_t old = sv_min(c, vloc, val);
                     bool imp = val < old;
                     c.c_improved += imp;
                     act = imp || (op.y & RETAIN);
@@ -451,7 +501,7 @@ __device__ __forceinline__ uint32_t extract(ItemCtx& c, PassShared& S, uint32_t 
         uint32_t i = i0 + t;
         bool valid = i < nf;
         uint32_t v = valid ? S.fq[cur][i] : 0u;
-        bool take = valid && (!by_value || c.st[v] < hi);
+        bool take = valid && (!by_value || sv_get(c, v) < hi);
         uint32_t p = block_append(take, &S.nb);
         bool tk = take && p < (uint32_t)BCAP;
         if (tk) S.bv[p] = v;
@@ -511,7 +561,7 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
         const uint32_t nf = S.nf;
         if (nf == 0) break;
         uint32_t lo = INF;
-        for (uint32_t i = t; i < nf; i += NT) { uint32_t d = c.st[S.fq[S.cur][i]]; lo = d < lo ? d : lo; }
+        for (uint32_t i = t; i < nf; i += NT) { uint32_t d = sv_get(c, S.fq[S.cur][i]); lo = d < lo ? d : lo; }
         lo = block_min(S, lo);
         if (first_lo == INF) first_lo = c.qlo != INF ? c.qlo : lo;
         if ((yld && (unsigned long long)lo >= (unsigned long long)first_lo + yld) || (budget && edges >= budget)) break;
@@ -523,7 +573,7 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
             atomicAnd(&c.bits[v >> 5], ~(1u << (v & 31)));
             uint32_t gv = c.v0 + v;
             uint32_t r0 = c.g.rowptr[gv], r1 = c.g.rowptr[gv + 1];
-            uint32_t dv = c.st[v];
+            uint32_t dv = sv_get(c, v);
             S.bval[j] = dv;
             S.brow[j] = r0;
             S.bpre[j] = r1 - r0;
@@ -554,8 +604,7 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
             bool win_ = false;
             if (intra) {
                 ++c.c_intra;
-                touch(c, ul);
-                uint32_t old = atomicMin(&c.st[ul], nd);
+                uint32_t old = sv_min(c, ul, nd);
                 if (nd < old) { ++c.c_improved; win_ = tas(c.bits, ul); }
             }
             push_frontier(c, S, cur, win_, ul, nd | RETAIN);
@@ -580,7 +629,7 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
             uint32_t i = i0 + t;
             bool valid = i < nf;
             uint32_t v = valid ? S.fq[cur][i] : 0u;
-            stage(S, valid, c.v0 + v, valid ? (c.st[v] | RETAIN) : 0u);
+            stage(S, valid, c.v0 + v, valid ? (sv_get(c, v) | RETAIN) : 0u);
         }
         __syncthreads();
         if (t == 0) { S.nf = 0; dev_add(&c.B.ctl->c_yields, 1ull); }
@@ -606,11 +655,12 @@ __device__ __forceinline__ void ppr_visit(ItemCtx& c, PassShared& S, uint32_t bu
             uint32_t r0 = c.g.rowptr[gv], r1 = c.g.rowptr[gv + 1];
             uint32_t deg = r1 - r0;
             float thr = c.mode ? c.eps * (float)deg : c.eps;
-            float mass = __uint_as_float(c.st[v]);
+            float mass = sv_takef(c, v);
             uint32_t push_deg = 0;
             float share = 0.f;
-            if (ppr_active(mass, thr)) {
-                c.st[v] = 0u;
+            if (!ppr_active(mass, thr)) {
+                sv_putf(c, v, mass);
+            } else {
                 atomicAdd(&c.gp[gv], a * mass);
                 ++pushed;
                 if (c.gfinal) { c.it_work += 1.f; c.it_useful += 1.f; }  // a push always moves mass to p
@@ -642,8 +692,7 @@ __device__ __forceinline__ void ppr_visit(ItemCtx& c, PassShared& S, uint32_t bu
             bool win_ = false;
             if (intra) {
                 ++c.c_intra;
-                touch(c, ul);
-                float old = atomicAdd((float*)&c.st[ul], share);
+                float old = sv_addf(c, ul, share);
                 float nr = old + share;
                 float thr = thr_of(c, u);
                 if (ppr_active(nr, thr) && !ppr_active(old, thr)) win_ = tas(c.bits, ul);
@@ -718,7 +767,11 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
         c.it_useful = 0.f;
         c.it_work = 0.f;
         // the slice is staged into LDS on first touch
-        for (uint32_t i = t; i < c.nvp; i += NT) c.st[i] = UNLOADED;
+        if (c.hmask) {
+            for (uint32_t i = t; i <= c.hmask; i += NT) { c.st[i] = UNLOADED; c.hkeys[i] = EMPTY_KEY; }
+        } else {
+            for (uint32_t i = t; i < c.nvp; i += NT) c.st[i] = UNLOADED;
+        }
         for (uint32_t i = t; i < (c.nvp + 31) / 32; i += NT) c.bits[i] = 0u;
         if (t == 0) { S.nf = 0; S.ns = 0; S.cur = 0; }
         __syncthreads();
@@ -735,9 +788,16 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
         else sp_visit<WB>(c, S, cfg.win_sp, cfg.yld_sp, budget);
         flush(c, S);
         // write the touched part of the slice back
-        for (uint32_t i = t; i < c.nvp; i += NT) {
-            uint32_t x = c.st[i];
-            if (x != UNLOADED) c.gstate[c.v0 + i] = x;
+        if (c.hmask) {
+            for (uint32_t i = t; i <= c.hmask; i += NT) {
+                uint32_t k = c.hkeys[i], x = c.st[i];
+                if (k != EMPTY_KEY && x != UNLOADED) c.gstate[c.v0 + k] = x;
+            }
+        } else {
+            for (uint32_t i = t; i < c.nvp; i += NT) {
+                uint32_t x = c.st[i];
+                if (x != UNLOADED) c.gstate[c.v0 + i] = x;
+            }
         }
         if (c.gfinal) {
             float u = c.it_useful, w = c.it_work;
@@ -752,13 +812,16 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
     }
 }
 
+// Dynamic LDS: dense slice st[vpmax] | bits, or hashed slice st[slots] | keys[slots] | bits.
 __device__ __forceinline__ void init_ctx(ItemCtx& c, const GraphDev& g, const QueryDev& Q, const BufDev& B,
-                                         uint32_t* dyn, uint32_t slice_words) {
+                                         uint32_t* dyn, uint32_t slice_words, uint32_t hash_slots) {
     c.g = g;
     c.Q = Q;
     c.B = B;
     c.st = dyn;
-    c.bits = dyn + slice_words;
+    c.hmask = hash_slots ? hash_slots - 1 : 0u;
+    c.hkeys = dyn + hash_slots;
+    c.bits = hash_slots ? dyn + 2 * hash_slots : dyn + slice_words;
     c.c_edges = c.c_intra = c.c_improved = c.c_emitted = c.c_consumed = c.c_vpush = c.c_chunks = c.c_pruned = 0;
 }
 
@@ -781,11 +844,12 @@ __device__ __forceinline__ void publish_counters(const ItemCtx& c, unsigned long
 
 // One pass (Algorithm 2's IntraPartProcess over the selected partitions).
 template <int WB>
-__global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B, PassCfg cfg, uint32_t slice_words) {
+__global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B, PassCfg cfg, uint32_t slice_words,
+                                                uint32_t hash_slots) {
     __shared__ PassShared S;
     extern __shared__ uint32_t dyn[];
     ItemCtx c;
-    init_ctx(c, g, Q, B, dyn, slice_words);
+    init_ctx(c, g, Q, B, dyn, slice_words, hash_slots);
     unsigned long long items = 0;
     process_items<WB>(c, S, cfg, items);
     publish_counters(c, items);
@@ -798,15 +862,16 @@ __global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B
 // grid-wide barriers, and stops by itself when no buffer holds work.
 template <int WB>
 __global__ __launch_bounds__(NT) void k_persistent(GraphDev g, QueryDev Q, BufDev B, PassCfg cfg, uint32_t slice_words,
-                                                   uint32_t max_passes, const float* theta, float* score, GStat* gs) {
+                                                   uint32_t hash_slots, uint32_t max_passes, const float* theta,
+                                                   float* score, GStat* gs) {
     __shared__ PassShared S;
     extern __shared__ uint32_t dyn[];
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     ItemCtx c;
-    init_ctx(c, g, Q, B, dyn, slice_words);
+    init_ctx(c, g, Q, B, dyn, slice_words, hash_slots);
     unsigned long long items = 0;
     const uint32_t t = threadIdx.x;
-    const uint32_t dyn_words = slice_words + (slice_words + 31) / 32;
+    const uint32_t dyn_words = (hash_slots ? 2 * hash_slots : slice_words) + (slice_words + 31) / 32;
     for (uint32_t pass = 0; pass < max_passes; ++pass) {
         // partition summaries from the buffers: per-query windows, then per partition
         for (uint32_t q = blockIdx.x * NT + t; q < Q.nq; q += gridDim.x * NT) qmin_one(B, Q, g.np, q);
@@ -850,16 +915,18 @@ __global__ __launch_bounds__(NT) void k_persistent(GraphDev g, QueryDev Q, BufDe
     publish_counters(c, items);
 }
 
-size_t process_dyn_lds(uint32_t vpmax) { return ((size_t)vpmax + (vpmax + 31) / 32) * 4; }
+size_t process_dyn_lds(uint32_t vpmax, uint32_t hash_slots) {
+    return ((size_t)(hash_slots ? 2 * hash_slots : vpmax) + (vpmax + 31) / 32) * 4;
+}
 
 hipError_t launch_process(const GraphDev& g, const QueryDev& Q, const BufDev& B, const PassCfg& cfg,
-                          uint32_t blocks, uint32_t vpmax, hipStream_t s) {
-    size_t dyn = process_dyn_lds(vpmax);
+                          uint32_t blocks, uint32_t vpmax, uint32_t hs, hipStream_t s) {
+    size_t dyn = process_dyn_lds(vpmax, hs);
     switch (g.wbytes) {
-    case 0: hipLaunchKernelGGL((k_process<0>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax); break;
-    case 1: hipLaunchKernelGGL((k_process<1>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax); break;
-    case 2: hipLaunchKernelGGL((k_process<2>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax); break;
-    default: hipLaunchKernelGGL((k_process<4>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax); break;
+    case 0: hipLaunchKernelGGL((k_process<0>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax, hs); break;
+    case 1: hipLaunchKernelGGL((k_process<1>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax, hs); break;
+    case 2: hipLaunchKernelGGL((k_process<2>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax, hs); break;
+    default: hipLaunchKernelGGL((k_process<4>), dim3(blocks), dim3(NT), dyn, s, g, Q, B, cfg, vpmax, hs); break;
     }
     return hipGetLastError();
 }
@@ -882,12 +949,12 @@ const void* persistent_kernel_ptr(int wbytes) {
 }
 
 hipError_t launch_persistent(const GraphDev& g, const QueryDev& Q, const BufDev& B, const PassCfg& cfg,
-                             uint32_t blocks, uint32_t vpmax, uint32_t max_passes, const float* theta, float* score,
-                             void* gstat, hipStream_t s) {
-    size_t dyn = process_dyn_lds(vpmax);
+                             uint32_t blocks, uint32_t vpmax, uint32_t hs, uint32_t max_passes, const float* theta,
+                             float* score, void* gstat, hipStream_t s) {
+    size_t dyn = process_dyn_lds(vpmax, hs);
     uint32_t sw = vpmax;
     GStat* gs = (GStat*)gstat;
-    void* args[] = {(void*)&g, (void*)&Q, (void*)&B, (void*)&cfg, (void*)&sw, (void*)&max_passes,
+    void* args[] = {(void*)&g, (void*)&Q, (void*)&B, (void*)&cfg, (void*)&sw, (void*)&hs, (void*)&max_passes,
                     (void*)&theta, (void*)&score, (void*)&gs};
     return hipLaunchCooperativeKernel(persistent_kernel_ptr(g.wbytes), dim3(blocks), dim3(NT), args, dyn, s);
 }

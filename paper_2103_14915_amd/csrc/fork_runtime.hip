@@ -20,8 +20,9 @@ namespace fk {
 hipError_t launch_select(const GraphDev&, const BufDev&, const PassCfg&, hipStream_t);
 hipError_t launch_worklist(const BufDev&, const QueryDev&, const PassCfg&, hipStream_t);
 hipError_t launch_summaries(const GraphDev&, const BufDev&, const QueryDev&, const PassCfg&, hipStream_t);
-hipError_t launch_process(const GraphDev&, const QueryDev&, const BufDev&, const PassCfg&, uint32_t, uint32_t, hipStream_t);
-size_t process_dyn_lds(uint32_t vpmax);
+hipError_t launch_process(const GraphDev&, const QueryDev&, const BufDev&, const PassCfg&, uint32_t, uint32_t, uint32_t,
+                          hipStream_t);
+size_t process_dyn_lds(uint32_t vpmax, uint32_t hash_slots);
 int process_threads();
 hipError_t launch_ring_init(uint32_t*, unsigned long long, hipStream_t);
 hipError_t launch_seed(const GraphDev&, const QueryDev&, const BufDev&, const uint32_t*, hipStream_t);
@@ -35,7 +36,7 @@ hipError_t launch_mlp_forward(const float*, const float*, uint32_t, float*, hipS
 const void* process_kernel_ptr(int wbytes);
 const void* persistent_kernel_ptr(int wbytes);
 hipError_t launch_persistent(const GraphDev&, const QueryDev&, const BufDev&, const PassCfg&, uint32_t, uint32_t,
-                             uint32_t, const float*, float*, void*, hipStream_t);
+                             uint32_t, uint32_t, const float*, float*, void*, hipStream_t);
 }  // namespace fk
 
 static thread_local std::string g_err;
@@ -123,6 +124,7 @@ struct fork_ctx {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> pev;  // pass-kernel timing events (profile mode)
     int blocks_per_cu = 1, num_cu = 1, pers_blocks_per_cu = 0;
+    uint32_t hslots = 0;  // hashed LDS slice slots of the current run (0 = dense slice)
     uint32_t vpmax = 1;  // largest partition (vertices)
     double wmean = 1.0;  // mean edge weight
 };
@@ -200,6 +202,28 @@ static void plan_partitions(const std::vector<uint32_t>& rp, uint32_t nv, uint32
         s = e;
     }
     starts.push_back(nv);
+}
+
+// Size the process kernels' dynamic LDS for a dense slice (hs = 0) or a
+// hashed slice of hs slots, and record how many workgroups fit per CU.
+static int set_slice(fork_ctx* c, uint32_t hs) {
+    size_t dyn = fk::process_dyn_lds(c->vpmax, hs);
+    const void* kp = fk::process_kernel_ptr(c->wbytes);
+    if (hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess)
+        return fail(FORK_E_DEVICE, "partition slice of %u vertices (%u hash slots) does not fit in LDS", c->vpmax, hs);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, fk::process_threads(), dyn) != hipSuccess || occ <= 0)
+        return fail(FORK_E_DEVICE, "process kernel does not fit on a CU with %zu bytes of LDS", dyn);
+    c->blocks_per_cu = occ;
+    const void* pk = fk::persistent_kernel_ptr(c->wbytes);
+    occ = 0;
+    if (hipFuncSetAttribute(pk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pk, fk::process_threads(), dyn) == hipSuccess)
+        c->pers_blocks_per_cu = occ;
+    else
+        c->pers_blocks_per_cu = 0;
+    c->hslots = hs;
+    return FORK_OK;
 }
 
 extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const uint64_t* row_ptr,
@@ -331,20 +355,7 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
     for (uint32_t P = 0; P < c->np; ++P) c->vpmax = std::max(c->vpmax, c->h_pstart[P + 1] - c->h_pstart[P]);
-    {
-        size_t dyn = fk::process_dyn_lds(c->vpmax);
-        const void* kp = fk::process_kernel_ptr(c->wbytes);
-        if (hipFuncSetAttribute(kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess)
-            return cleanup(fail(FORK_E_DEVICE, "partition slice of %u vertices does not fit in LDS", c->vpmax));
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kp, fk::process_threads(), dyn) == hipSuccess && occ > 0)
-            c->blocks_per_cu = occ;
-        const void* pk = fk::persistent_kernel_ptr(c->wbytes);
-        occ = 0;
-        if (hipFuncSetAttribute(pk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pk, fk::process_threads(), dyn) == hipSuccess)
-            c->pers_blocks_per_cu = occ;
-    }
+    if ((rc = set_slice(c, 0))) return cleanup(rc);
     *out = c;
     return FORK_OK;
 }
@@ -547,7 +558,7 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
             HIPCHK(fk::launch_mlp_score(g, B, c->d_mlp, c->d_score, c->d_feat, c->d_gstat, 0, s));
             HIPCHK(fk::launch_select(g, B, pc, s));
             HIPCHK(fk::launch_worklist(B, Q, pc, s));
-            HIPCHK(fk::launch_process(g, Q, B, pc, blocks, c->vpmax, s));
+            HIPCHK(fk::launch_process(g, Q, B, pc, blocks, c->vpmax, c->hslots, s));
             std::vector<uint32_t> sel(c->np);
             std::vector<float> feat((size_t)c->np * fk::MLP_IN), tr((size_t)c->np * 2);
             HIPCHK(hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(fk::Ctl), hipMemcpyDeviceToHost, s));
@@ -573,7 +584,7 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
             if (o.profile) HIPCHK(hipEventRecord(c->pev[0], s));
             uint64_t lp = 64ull * batch;
             if (passes_left != ~0ull) lp = std::min<uint64_t>(lp, passes_left);
-            HIPCHK(fk::launch_persistent(g, Q, B, pc, pblocks, c->vpmax, (uint32_t)lp, c->d_mlp, c->d_score,
+            HIPCHK(fk::launch_persistent(g, Q, B, pc, pblocks, c->vpmax, c->hslots, (uint32_t)lp, c->d_mlp, c->d_score,
                                          c->d_gstat, s));
             if (o.profile) HIPCHK(hipEventRecord(c->pev[1], s));
             nb = 1;
@@ -585,7 +596,7 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
                 HIPCHK(fk::launch_select(g, B, pc, s));
                 HIPCHK(fk::launch_worklist(B, Q, pc, s));
                 if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k], s));
-                HIPCHK(fk::launch_process(g, Q, B, pc, blocks, c->vpmax, s));
+                HIPCHK(fk::launch_process(g, Q, B, pc, blocks, c->vpmax, c->hslots, s));
                 if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k + 1], s));
             }
         }
@@ -675,7 +686,16 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     if (opts) o = *opts;
     if (o.scheduler < 0 || o.scheduler > FORK_SCHED_MAXOPS) return fail(FORK_E_INVALID, "bad scheduler %d", o.scheduler);
     if (o.scheduler == FORK_SCHED_LEARNED && !o.mlp_weights) return fail(FORK_E_INVALID, "LEARNED needs mlp_weights");
+    if (o.slice_slots && (o.slice_slots < 256 || o.slice_slots > 16384 || (o.slice_slots & (o.slice_slots - 1))))
+        return fail(FORK_E_INVALID, "slice_slots must be 0 or a power of two in [256, 16384], got %u", o.slice_slots);
     if (hipSetDevice(c->device) != hipSuccess) return fail(FORK_E_DEVICE, "hipSetDevice failed");
+    {
+        // a table with at least half as many slots as the largest partition has
+        // vertices saves no LDS: use the dense slice then
+        const uint32_t hs = 2ull * o.slice_slots >= c->vpmax ? 0u : o.slice_slots;
+        int rc = hs == c->hslots ? FORK_OK : set_slice(c, hs);
+        if (rc) return rc;
+    }
     hipStream_t s = (hipStream_t)o.stream;
     const uint32_t nq_total = (uint32_t)c->queries.size();
     // wave capacity from free device memory

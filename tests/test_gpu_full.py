@@ -32,7 +32,8 @@ def say(*a):
 
 
 # knobs autotuned for the scale-20 R-MAT SSSP+PPR mix; used for R-MAT graphs without a cached tuning
-RMAT_KNOBS = {"partition_vertices": 16384, "items_per_pass": 16384, "window": 16, "delta": 512, "persistent": 0}
+RMAT_KNOBS = {"partition_vertices": 16384, "items_per_pass": 16384, "window": 16, "delta": 512, "persistent": 0,
+              "slice_slots": 0}
 
 
 def knobs(g, queries, fallback=None):
@@ -62,7 +63,8 @@ def run_workload(fork, g, queries, spec, p):
     for qt, s in queries:
         fg.submit(qt, s, alpha=spec.get("alpha", 0.15), epsilon=spec.get("epsilon", 1e-6),
                   eps_mode=spec.get("eps_mode", 0))
-    fg.run(items_per_pass=p["items_per_pass"], window=p["window"], delta=p["delta"], persistent=p["persistent"])
+    fg.run(items_per_pass=p["items_per_pass"], window=p["window"], delta=p["delta"], persistent=p["persistent"],
+           slice_slots=p.get("slice_slots", 0))
     return fg
 
 

@@ -263,3 +263,46 @@ def test_persistent_grid():
     d = np.stack([fg.fetch(i) for i in range(32)])
     fg.close()
     np.testing.assert_array_equal(d, oracle.sssp(g, s1))
+
+
+@pytest.mark.parametrize("slots,persistent", [(256, 0), (1024, 0), (256, 1)])
+def test_hashed_slice_parity(slots, persistent):
+    """Hashed LDS slice: the visit keeps only touched vertices in an LDS hash
+    table; with 256 slots and 4096-vertex partitions many vertices find no
+    slot and are updated in global memory, so both paths are exercised."""
+    fork = _fork()
+    g = fi.rmat(13, seed=2, weights=(1, 255), weight_seed=102)
+    s1 = fi.sources_uniform(g, 24, 14)
+    s2 = fi.sources_uniform(g, 16, 15)
+    s3 = fi.sources_uniform(g, 16, 16)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=4096)
+    fg.submit("sssp", s1)
+    fg.submit("bfs", s2)
+    fg.submit("ppr", s3, alpha=ALPHA, epsilon=1e-6, eps_mode=1)
+    say("hashed slice", slots, "persistent", persistent)
+    fg.run(slice_slots=slots, persistent=persistent, max_passes=200000)
+    d = np.stack([fg.fetch(i) for i in range(24)])
+    lv = np.stack([fg.fetch(24 + i) for i in range(16)])
+    np.testing.assert_array_equal(d, oracle.sssp(g, s1))
+    np.testing.assert_array_equal(lv, oracle.bfs(g, s2))
+    P = np.stack([fg.fetch(40 + i, fork.FIELD_P) for i in range(16)])
+    R = np.stack([fg.fetch(40 + i, fork.FIELD_R) for i in range(16)])
+    fg.close()
+    check_ppr(g, s3, P, R, 1e-6, 1)
+
+
+def test_hashed_slice_grid_and_bad_slots():
+    fork = _fork()
+    g = fi.grid(128, 96, weights=(1, 1000), weight_seed=19)
+    s1 = fi.sources_uniform(g, 32, 21)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=4096)
+    fg.submit("sssp", s1)
+    with pytest.raises(fork.ForkError) as e:
+        fg.run(slice_slots=300)                         # not a power of two
+    assert e.value.code == fork.FORK_E_INVALID
+    say("hashed slice grid")
+    fg.run(slice_slots=512, max_passes=1000000)
+    np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(32)]), oracle.sssp(g, s1))
+    fg.run(slice_slots=0, max_passes=1000000)           # back to the dense slice in the same context
+    np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(32)]), oracle.sssp(g, s1))
+    fg.close()
