@@ -35,6 +35,13 @@ constexpr int FCAP = 1024;        // frontier capacity (two buffers)
 constexpr int BCAP = 512;         // vertices expanded per batch
 constexpr int SCAP = 512;         // staged outgoing operations
 constexpr int CCAP = 128;         // chunk ids gathered per consume round
+// Free chunks each workgroup keeps for itself: chunks freed by consume are
+// reused by the same workgroup's next flush without touching the pool's ring
+// counters (two single-address atomics per item otherwise).  A flush needs at
+// most one fresh chunk per run plus SCAP/CH, so STASH >= SCAP + SCAP/CH + 1.
+constexpr int STASH = 640;
+constexpr int REFILL = 32;        // chunks taken from the ring per refill when the pool is not low
+static_assert(STASH >= SCAP + SCAP / 256 + 1, "a flush must fit in the stash");
 constexpr int SE = (SCAP + NT - 1) / NT;
 
 struct PassShared {
@@ -48,6 +55,8 @@ struct PassShared {
     int32_t rt[SCAP];             // per run: tail chunk (-1: none)
     uint32_t rp[SCAP];            // per run: slot | taken << 9 | fresh-chunk base << 18
     int32_t clist[CCAP];          // chunk ids of the consume round
+    uint32_t stash[STASH];        // free chunks owned by this workgroup
+    uint32_t nstash, nrefill;
     uint32_t wred[NW];
     uint32_t nf, nk, nb, ns, ncl, cur;
     int32_t chnext;
@@ -302,25 +311,42 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             if (end) S.rp[rsv] += my_base << 18;
         }
     }
+    const unsigned long long nch = c.B.nch;
     if (t == 0) {
+        // fresh chunks come from the stash; refill it from the pool's ring if short
         unsigned long long base = 0;
-        if (nnew) {
-            base = dev_add(&c.B.ctl->ring_head, (unsigned long long)nnew);
-            if (base + nnew > c.B.ctl->avail_end) {
+        uint32_t k = 0;
+        const uint32_t have = S.nstash;
+        if (nnew > have) {
+            const unsigned long long head = __hip_atomic_load(&c.B.ctl->ring_head, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long avail = c.B.ctl->avail_end > head ? c.B.ctl->avail_end - head : 0ull;
+            k = nnew - have;
+            if (k < (uint32_t)REFILL && avail > 64ull * REFILL) k = REFILL;  // batch while the pool is not low
+            if (k > (uint32_t)STASH - have) k = (uint32_t)STASH - have;
+            base = dev_add(&c.B.ctl->ring_head, (unsigned long long)k);
+            if (base + k > c.B.ctl->avail_end) {
                 dev_or(&c.B.ctl->err, (uint32_t)ERR_CAPACITY);
                 base = ~0ull;
             }
         }
         S.base = base;
+        S.nrefill = k;
     }
     __syncthreads();
-    const unsigned long long base = S.base;
-    if (base == ~0ull) {
+    if (S.base == ~0ull) {
+        __syncthreads();
         if (t == 0) S.ns = 0;
         __syncthreads();
         return;
     }
-    const unsigned long long nch = c.B.nch;
+    {
+        const uint32_t k = S.nrefill, have = S.nstash;
+        for (uint32_t i = t; i < k; i += NT) S.stash[have + i] = c.B.ring[(S.base + i) % nch];
+    }
+    __syncthreads();
+    // this flush takes the top nnew entries of the stash
+    const uint32_t sb = S.nstash + S.nrefill - nnew;
     // every element writes its operation
     {
         uint32_t rsv = rstart_prev;
@@ -335,7 +361,7 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
                 c.B.chunks[(unsigned long long)(uint32_t)S.rt[rsv] * CH + s + off] = op;
             } else {
                 uint32_t j = (off - kk) / CH;
-                uint32_t ch = c.B.ring[(base + cb + j) % nch];
+                uint32_t ch = S.stash[sb + cb + j];
                 c.B.chunks[(unsigned long long)ch * CH + (off - kk) % CH] = op;
             }
         }
@@ -354,10 +380,10 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             uint32_t need = (len - kk + CH - 1) / CH;
             unsigned long long b = (unsigned long long)T * c.Q.qc + c.q;
             if (need) {
-                uint32_t first = c.B.ring[(base + cb) % nch];
+                uint32_t first = S.stash[sb + cb];
                 uint32_t prev = first;
                 for (uint32_t j = 0; j < need; ++j) {
-                    uint32_t ch = j ? c.B.ring[(base + cb + j) % nch] : first;
+                    uint32_t ch = j ? S.stash[sb + cb + j] : first;
                     if (j) c.B.cnext[prev] = (int32_t)ch;
                     uint32_t fill = (j + 1 < need) ? (uint32_t)CH : (len - kk) - j * CH;
                     uint32_t r0 = dev_add(&c.B.ccount[ch], fill);
@@ -384,9 +410,11 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             c.c_emitted += len;
         }
     }
+    __syncthreads();
     if (t == 0) {
         c.c_chunks += nnew;
         S.ns = 0;
+        S.nstash = sb;
     }
     __syncthreads();
 }
@@ -475,14 +503,24 @@ __device__ __forceinline__ void consume(ItemCtx& c, PassShared& S, int32_t head)
             push_frontier(c, S, cur, win, vloc, rv);
         }
         __syncthreads();
-        // free this round's chunks
-        if (t == 0) S.base = dev_add(&c.B.ctl->ring_tail, (unsigned long long)ncl);
-        __syncthreads();
+        // free this round's chunks into the stash; what does not fit goes back to the ring
+        const uint32_t ns0 = S.nstash;
+        const uint32_t keep = ncl < (uint32_t)STASH - ns0 ? ncl : (uint32_t)STASH - ns0;
         for (uint32_t i = t; i < ncl; i += NT) {
             uint32_t ch = (uint32_t)S.clist[i];
-            c.B.ccount[ch] = 0;
-            c.B.ring[(S.base + i) % c.B.nch] = ch;
+            // reset with a device-scope atomic: a flush of this workgroup may
+            // reserve slots in it with device-scope atomics in this same pass
+            dev_xchg(&c.B.ccount[ch], 0u);
+            if (i < keep) S.stash[ns0 + i] = ch;
         }
+        if (ncl > keep) {
+            __syncthreads();
+            if (t == 0) S.base = dev_add(&c.B.ctl->ring_tail, (unsigned long long)(ncl - keep));
+            __syncthreads();
+            for (uint32_t i = keep + t; i < ncl; i += NT) c.B.ring[(S.base + i - keep) % c.B.nch] = (uint32_t)S.clist[i];
+        }
+        __syncthreads();
+        if (t == 0) S.nstash = ns0 + keep;
         __syncthreads();
     }
     if (t == 0 && S.nf > (uint32_t)FCAP) S.nf = FCAP;
@@ -812,6 +850,20 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
     }
 }
 
+// Give the workgroup's stash back to the pool's ring (block-collective).
+__device__ __forceinline__ void return_stash(const BufDev& B, PassShared& S) {
+    const uint32_t t = threadIdx.x;
+    __syncthreads();
+    const uint32_t n = S.nstash;
+    if (n == 0) return;
+    if (t == 0) S.base = dev_add(&B.ctl->ring_tail, (unsigned long long)n);
+    __syncthreads();
+    for (uint32_t i = t; i < n; i += NT) B.ring[(S.base + i) % B.nch] = S.stash[i];
+    __syncthreads();
+    if (t == 0) S.nstash = 0;
+    __syncthreads();
+}
+
 // Dynamic LDS: dense slice st[vpmax] | bits, or hashed slice st[slots] | keys[slots] | bits.
 __device__ __forceinline__ void init_ctx(ItemCtx& c, const GraphDev& g, const QueryDev& Q, const BufDev& B,
                                          uint32_t* dyn, uint32_t slice_words, uint32_t hash_slots) {
@@ -851,7 +903,10 @@ __global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B
     ItemCtx c;
     init_ctx(c, g, Q, B, dyn, slice_words, hash_slots);
     unsigned long long items = 0;
+    if (threadIdx.x == 0) S.nstash = 0;
+    __syncthreads();
     process_items<WB>(c, S, cfg, items);
+    return_stash(B, S);
     publish_counters(c, items);
 }
 
@@ -871,6 +926,8 @@ __global__ __launch_bounds__(NT) void k_persistent(GraphDev g, QueryDev Q, BufDe
     init_ctx(c, g, Q, B, dyn, slice_words, hash_slots);
     unsigned long long items = 0;
     const uint32_t t = threadIdx.x;
+    if (t == 0) S.nstash = 0;
+    __syncthreads();
     const uint32_t dyn_words = (hash_slots ? 2 * hash_slots : slice_words) + (slice_words + 31) / 32;
     for (uint32_t pass = 0; pass < max_passes; ++pass) {
         // partition summaries from the buffers: per-query windows, then per partition
@@ -912,6 +969,7 @@ __global__ __launch_bounds__(NT) void k_persistent(GraphDev g, QueryDev Q, BufDe
         process_items<WB>(c, S, cfg, items);
         grid.sync();
     }
+    return_stash(B, S);
     publish_counters(c, items);
 }
 
