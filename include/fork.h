@@ -100,7 +100,9 @@ typedef struct {
                                   two, 256..16384) holding only the vertices the
                                   visit touches, so more workgroups fit per CU;
                                   vertices that find no free slot are updated in
-                                  place in global memory                          */
+                                  place in global memory.  Partitions too large
+                                  for the dense slice always use a hashed one
+                                  (4096 slots when 0 is given)                    */
 } fork_run_opts;
 
 /* Counters accumulated over the last fork_run (all waves). */

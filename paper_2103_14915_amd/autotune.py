@@ -99,7 +99,7 @@ def candidates(g, queries) -> dict:
     kinds = {qt for qt, _ in queries}
     wmean = float(g.weight.mean()) if g.weight is not None else 1.0
     c = {
-        "partition_vertices": [4096, 8192, 16384],
+        "partition_vertices": [8192, 16384, 32768, 65536],
         "items_per_pass": [0, 2048, 16384, 65536],
         "persistent": [0, 1],
         "slice_slots": [0, 1024, 2048, 4096],

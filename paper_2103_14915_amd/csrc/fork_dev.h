@@ -11,7 +11,9 @@ constexpr int CH = 256;                   // operations per pool chunk
 constexpr uint32_t INF = 0x7fffffffu;     // unreachable distance / level
 constexpr uint32_t RETAIN = 0x80000000u;  // op flag: retained (yielded) work
 constexpr int NXCD = 8;                   // MI355X: 8 XCDs of 32 CUs
-constexpr uint32_t VPMAX = 16384;         // max vertices per partition
+constexpr uint32_t VPMAX = 16384;         // default vertices per partition (the dense LDS slice fits)
+constexpr uint32_t PVMAX = 65536;         // max vertices per partition (hashed LDS slice)
+constexpr uint32_t HS_AUTO = 4096;        // hash slots when the dense slice does not fit
 constexpr int MLP_IN = 16, MLP_H = 64;
 constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;  // 5313
 

@@ -125,6 +125,7 @@ struct fork_ctx {
     std::vector<hipEvent_t> pev;  // pass-kernel timing events (profile mode)
     int blocks_per_cu = 1, num_cu = 1, pers_blocks_per_cu = 0;
     uint32_t hslots = 0;  // hashed LDS slice slots of the current run (0 = dense slice)
+    bool dense_ok = true; // the dense slice of the largest partition fits in LDS
     uint32_t vpmax = 1;  // largest partition (vertices)
     double wmean = 1.0;  // mean edge weight
 };
@@ -286,7 +287,7 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     auto cleanup = [&](int r) { fork_destroy(c); return r; };
     // partition plan
     uint32_t pv = cfg.partition_vertices ? cfg.partition_vertices : fk::VPMAX;
-    if (pv > fk::VPMAX) return cleanup(fail(FORK_E_INVALID, "partition_vertices must be <= %u", fk::VPMAX));
+    if (pv > fk::PVMAX) return cleanup(fail(FORK_E_INVALID, "partition_vertices must be <= %u", fk::PVMAX));
     uint32_t pe = cfg.partition_edges ? cfg.partition_edges : (uint32_t)std::min<uint64_t>(0xffffffffu, std::max<uint64_t>(4096, (uint64_t)pv * 64));
     uint32_t pshift = 0;
     while (pshift < 8 && (2u << pshift) <= pv / 4) ++pshift;
@@ -355,7 +356,13 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
     for (uint32_t P = 0; P < c->np; ++P) c->vpmax = std::max(c->vpmax, c->h_pstart[P + 1] - c->h_pstart[P]);
-    if ((rc = set_slice(c, 0))) return cleanup(rc);
+    // the dense slice (one LDS word per partition vertex) when it fits, else a hashed one
+    if (set_slice(c, 0) != FORK_OK) {
+        (void)hipGetLastError();
+        g_err.clear();
+        c->dense_ok = false;
+        if ((rc = set_slice(c, fk::HS_AUTO))) return cleanup(rc);
+    }
     *out = c;
     return FORK_OK;
 }
@@ -692,7 +699,8 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     {
         // a table with at least half as many slots as the largest partition has
         // vertices saves no LDS: use the dense slice then
-        const uint32_t hs = 2ull * o.slice_slots >= c->vpmax ? 0u : o.slice_slots;
+        uint32_t hs = (c->dense_ok && 2ull * o.slice_slots >= c->vpmax) ? 0u : o.slice_slots;
+        if (!hs && !c->dense_ok) hs = fk::HS_AUTO;
         int rc = hs == c->hslots ? FORK_OK : set_slice(c, hs);
         if (rc) return rc;
     }

@@ -306,3 +306,24 @@ def test_hashed_slice_grid_and_bad_slots():
     fg.run(slice_slots=0, max_passes=1000000)           # back to the dense slice in the same context
     np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(32)]), oracle.sssp(g, s1))
     fg.close()
+
+
+def test_large_partitions_use_hashed_slice():
+    """Partitions of 32K-64K vertices do not fit a dense LDS slice: the library
+    picks a hashed slice by itself, and explicit slot counts work too."""
+    fork = _fork()
+    g = fi.rmat(17, seed=3, weights=(1, 255), weight_seed=103)
+    s1 = fi.sources_uniform(g, 12, 17)
+    s3 = fi.sources_uniform(g, 8, 18)
+    ref = oracle.sssp(g, s1)
+    for pv, slots in ((65536, 0), (32768, 2048), (65536, 8192)):
+        say("large partitions", pv, slots)
+        fg = fork.ForkGraph.from_graph(g, partition_vertices=pv)
+        fg.submit("sssp", s1)
+        fg.submit("ppr", s3, alpha=ALPHA, epsilon=1e-6, eps_mode=1)
+        fg.run(slice_slots=slots, max_passes=200000)
+        np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(12)]), ref)
+        P = np.stack([fg.fetch(12 + i, fork.FIELD_P) for i in range(8)])
+        R = np.stack([fg.fetch(12 + i, fork.FIELD_R) for i in range(8)])
+        fg.close()
+        check_ppr(g, s3, P, R, 1e-6, 1)
