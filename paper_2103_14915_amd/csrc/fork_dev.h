@@ -21,6 +21,7 @@ enum QType : uint32_t { Q_SSSP = 1, Q_BFS = 2, Q_PPR = 3 };
 enum Sched : uint32_t { S_FIFO = 0, S_PRIORITY = 1, S_LEARNED = 2, S_RANDOM = 3, S_MAXOPS = 4 };
 
 // error flags in Ctl::err
+constexpr unsigned long long BTW_EMPTY = 0xffffffff00000000ull | (unsigned long long)CH;
 enum : uint32_t { ERR_CAPACITY = 1u, ERR_ITEMS = 2u, ERR_CORRUPT = 4u };
 
 // One device control block per context.  Counters are 64-bit.
@@ -40,12 +41,18 @@ struct Ctl {
 };
 
 // A (partition, query) work item of one pass.
-struct Item {
+// A detached (partition, query) buffer.  The detach walks the head of the
+// chunk list (in parallel over buffers) so that the visit starts without a
+// serial chain of dependent loads; longer lists continue at `rest`.
+constexpr int ICH = 14;
+struct alignas(16) Item {
     uint32_t part;
     uint32_t q;
-    int32_t head;    // first chunk of the detached buffer list (-1: none)
-    uint32_t count;  // operations in the list
+    int32_t rest;    // next chunk after the inline ones (-1: none)
+    uint32_t nch;    // inline chunks
+    uint2 ch[ICH];   // (chunk id, valid ops)
 };
+static_assert(sizeof(Item) == 128, "work item layout");
 
 struct GraphDev {
     uint32_t nv, np, pshift, wbytes;
@@ -68,8 +75,14 @@ struct QueryDev {
 };
 
 struct BufDev {
-    int32_t* bhead;           // [np*qc] first chunk of the (partition, query) buffer
-    int32_t* btail;           // [np*qc] chunk with free slots (-1: none)
+    // A (partition, query) buffer is a list of chunks bhead -> ... -> tail whose
+    // tail still takes appends, plus an overflow list of chunks added while
+    // the tail was being replaced.  btw packs (tail chunk << 32 | slots
+    // reserved in it); one 64-bit atomic add reserves slots.  An empty buffer
+    // has BTW_EMPTY, i.e. no tail and a full reservation count.
+    int32_t* bhead;           // [np*qc] first chunk of the main list (-1: empty)
+    unsigned long long* btw;  // [np*qc] tail word
+    int32_t* bover;           // [np*qc] overflow list (-1: none)
     uint32_t* bval;           // [np*qc] best buffered value: SSSP/BFS min value, PPR ~(max mass bits);
                               //         0xffffffff when empty (min works for both encodings)
     uint32_t* bcnt;           // [np*qc] buffered operations
@@ -78,7 +91,7 @@ struct BufDev {
     uint32_t* pready;         // [np] buffers ready to run (within the query's window)
     uint2* chunks;            // [nch*CH] (vertex, value) operations
     int32_t* cnext;           // [nch]
-    uint32_t* ccount;         // [nch] slots reserved (valid ops = min(ccount, CH))
+    uint32_t* ccount;         // [nch] valid ops in the chunk (set when it stops being a tail)
     uint32_t* ring;           // [nch] free chunk ids
     unsigned long long nch;
     // partition summaries (maintained at emission, reset when a partition is scheduled)

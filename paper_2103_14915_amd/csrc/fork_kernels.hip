@@ -38,6 +38,11 @@ __global__ __launch_bounds__(256) void k_qmin(BufDev B, QueryDev Q, uint32_t np)
 __global__ __launch_bounds__(256) void k_psum(BufDev B, QueryDev Q, PassCfg cfg) { psum_one(B, Q, cfg, blockIdx.x); }
 
 // ------------------------------------------------------------ wave setup
+__global__ void k_fill64(unsigned long long* p, unsigned long long n, unsigned long long v) {
+    unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (unsigned long long)gridDim.x * blockDim.x) p[i] = v;
+}
+
 __global__ void k_ring_init(uint32_t* ring, unsigned long long nch) {
     unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < nch; i += (unsigned long long)gridDim.x * blockDim.x) ring[i] = (uint32_t)i;
@@ -53,11 +58,9 @@ __global__ void k_seed(GraphDev g, QueryDev Q, BufDev B, const uint32_t* src) {
     uint32_t t = Q.qtype[q];
     uint32_t val = t == Q_PPR ? __float_as_uint(1.0f) : 0u;
     B.chunks[(unsigned long long)q * CH] = make_uint2(s, val);
-    B.ccount[q] = 1;
-    B.cnext[q] = -1;
     unsigned long long b = (unsigned long long)P * Q.qc + q;
     B.bhead[b] = (int32_t)q;
-    B.btail[b] = (int32_t)q;
+    B.btw[b] = ((unsigned long long)q << 32) | 1ull;  // chunk q is the tail, one slot used
     B.bcnt[b] = 1;
     B.bval[b] = t == Q_PPR ? ~__float_as_uint(1.0f) : 0u;
     B.bfirst[b] = 0;
@@ -133,6 +136,10 @@ hipError_t launch_worklist(const BufDev& B, const QueryDev& Q, const PassCfg& cf
 hipError_t launch_summaries(const GraphDev& g, const BufDev& B, const QueryDev& Q, const PassCfg& cfg, hipStream_t s) {
     hipLaunchKernelGGL(k_qmin, dim3((Q.nq + 255) / 256), dim3(256), 0, s, B, Q, g.np);
     hipLaunchKernelGGL(k_psum, dim3(g.np), dim3(256), 0, s, B, Q, cfg);
+    return hipGetLastError();
+}
+hipError_t launch_fill64(unsigned long long* p, unsigned long long n, unsigned long long v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill64, dim3(1024), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 hipError_t launch_ring_init(uint32_t* ring, unsigned long long nch, hipStream_t s) {

@@ -42,6 +42,7 @@ constexpr int CCAP = 128;         // chunk ids gathered per consume round
 constexpr int STASH = 640;
 constexpr int REFILL = 32;        // chunks taken from the ring per refill when the pool is not low
 static_assert(STASH >= SCAP + SCAP / 256 + 1, "a flush must fit in the stash");
+static_assert(CCAP <= NT && ICH <= CCAP, "one thread per chunk of a consume round");
 constexpr int SE = (SCAP + NT - 1) / NT;
 
 struct PassShared {
@@ -55,12 +56,14 @@ struct PassShared {
     int32_t rt[SCAP];             // per run: tail chunk (-1: none)
     uint32_t rp[SCAP];            // per run: slot | taken << 9 | fresh-chunk base << 18
     int32_t clist[CCAP];          // chunk ids of the consume round
+    uint32_t ccnt[CCAP];          // their valid ops
+    uint32_t cpre[CCAP];          // exclusive prefix of ccnt
     uint32_t stash[STASH];        // free chunks owned by this workgroup
     uint32_t nstash, nrefill;
     uint32_t wred[NW];
     uint32_t nf, nk, nb, ns, ncl, cur;
     int32_t chnext;
-    unsigned long long base;
+    unsigned long long base, itpos;
     Item it;
 };
 
@@ -277,7 +280,10 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
         if (i == 0 || S.tp[i] != S.tp[i - 1]) rsmax = i;
     // start of the run still open where my block begins
     const uint32_t rstart_prev = block_max_excl(S, rsmax);
-    // owners: reserve in the tail chunk, count fresh chunks
+    // owners: one 64-bit add on the buffer's tail word reserves slots in the
+    // tail chunk; what does not fit goes to fresh chunks.  The one owner whose
+    // reservation covers slot CH of the tail (f <= CH < f + len) installs the
+    // next tail; owners that arrive while it does (f > CH) use the overflow list.
     uint32_t need_l = 0;
     {
         uint32_t rsv = rstart_prev;
@@ -288,15 +294,12 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             if (!end) continue;
             uint32_t len = i - rsv + 1;
             unsigned long long b = (unsigned long long)T * c.Q.qc + c.q;
-            int32_t tl = __hip_atomic_load(&c.B.btail[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t s = CH, kk = 0;
-            if (tl >= 0) {
-                s = dev_add(&c.B.ccount[tl], len);
-                if (s < (uint32_t)CH) kk = ((uint32_t)CH - s) < len ? ((uint32_t)CH - s) : len;
-                else s = CH;
-            }
-            S.rt[rsv] = tl;
-            S.rp[rsv] = s | (kk << 9) | (need_l << 18);
+            const unsigned long long w = dev_add(&c.B.btw[b], (unsigned long long)len);
+            const uint32_t tl = (uint32_t)(w >> 32), f = (uint32_t)w;
+            uint32_t kk = 0;
+            if (tl != 0xffffffffu && f < (uint32_t)CH) kk = ((uint32_t)CH - f) < len ? ((uint32_t)CH - f) : len;
+            S.rt[rsv] = (int32_t)tl;
+            S.rp[rsv] = (f < 511u ? f : 511u) | (kk << 9) | (need_l << 18);
             need_l += (len - kk + CH - 1) / CH;
         }
     }
@@ -354,7 +357,7 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             if (i == 0 || S.tp[i] != S.tp[i - 1]) rsv = i;
             uint32_t off = i - rsv;
             uint32_t info = S.rp[rsv];
-            uint32_t s = info & 0x1ffu, kk = (info >> 9) & 0x1ffu, cb = info >> 18;
+            uint32_t s = info & 0x1ffu, kk = (info >> 9) & 0x1ffu, cb = info >> 18;  // s: slot in the tail
             unsigned long long sv = S.sk[i];
             uint2 op = make_uint2((uint32_t)(sv >> 32), (uint32_t)sv);
             if (off < kk) {
@@ -366,7 +369,10 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             }
         }
     }
-    // owners link fresh chunks, publish the new tail, update partition summaries
+    // owners link their fresh chunks.  Every plain store below has a single
+    // writer per pass: a chunk's link and count are written by the workgroup
+    // that filled it, except a tail's, which only the owner that replaces the
+    // tail writes (the detach of the next pass closes the last tail).
     {
         uint32_t rsv = rstart_prev;
         for (uint32_t i = lo; i < hi; ++i) {
@@ -376,26 +382,33 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             if (!end) continue;
             uint32_t len = i - rsv + 1;
             uint32_t info = S.rp[rsv];
-            uint32_t kk = (info >> 9) & 0x1ffu, cb = info >> 18;
+            uint32_t f = info & 0x1ffu, kk = (info >> 9) & 0x1ffu, cb = info >> 18;
             uint32_t need = (len - kk + CH - 1) / CH;
             unsigned long long b = (unsigned long long)T * c.Q.qc + c.q;
             if (need) {
-                uint32_t first = S.stash[sb + cb];
-                uint32_t prev = first;
-                for (uint32_t j = 0; j < need; ++j) {
-                    uint32_t ch = j ? S.stash[sb + cb + j] : first;
-                    if (j) c.B.cnext[prev] = (int32_t)ch;
-                    uint32_t fill = (j + 1 < need) ? (uint32_t)CH : (len - kk) - j * CH;
-                    uint32_t r0 = dev_add(&c.B.ccount[ch], fill);
-                    if (j + 1 == need) {
-                        int32_t old = dev_xchg(&c.B.bhead[b], (int32_t)first);
-                        c.B.cnext[ch] = old;
-                        if (old < 0) c.B.bfirst[b] = c.pass;  // the buffer became non-empty
-                        // publish the tail only after its slots are reserved
-                        if (r0 == 0) dev_xchg(&c.B.btail[b], (int32_t)ch);
-                        else dev_or(&c.B.ctl->err, (uint32_t)ERR_CORRUPT);
+                const uint32_t first = S.stash[sb + cb];
+                uint32_t last = first;
+                for (uint32_t j = 1; j < need; ++j) {
+                    uint32_t ch = S.stash[sb + cb + j];
+                    c.B.cnext[last] = (int32_t)ch;
+                    c.B.ccount[last] = CH;
+                    last = ch;
+                }
+                const uint32_t fill = (len - kk) - (need - 1) * CH;
+                const int32_t tl = S.rt[rsv];
+                if (f <= (uint32_t)CH && f + len > (uint32_t)CH) {
+                    // installer: link after the old tail (now full) and make `last` the tail
+                    if (tl != -1) {
+                        c.B.cnext[tl] = (int32_t)first;
+                        c.B.ccount[tl] = CH;
+                    } else {
+                        c.B.bhead[b] = (int32_t)first;
+                        c.B.bfirst[b] = c.pass;  // the buffer became non-empty
                     }
-                    prev = ch;
+                    dev_xchg(&c.B.btw[b], ((unsigned long long)last << 32) | fill);
+                } else {
+                    c.B.ccount[last] = fill;
+                    c.B.cnext[last] = dev_xchg(&c.B.bover[b], (int32_t)first);
                 }
             }
             // bucket summary for the scheduler: operation count and best value
@@ -443,39 +456,57 @@ __device__ __forceinline__ void push_frontier(ItemCtx& c, PassShared& S, uint32_
 // ------------------------------------------------------------ consume
 // Apply the work item's buffered operations to the LDS slice (consolidation
 // of the buffer into the query's state) and free the chunks.
-__device__ __forceinline__ void consume(ItemCtx& c, PassShared& S, int32_t head) {
+__device__ __forceinline__ void consume(ItemCtx& c, PassShared& S) {
     const uint32_t t = threadIdx.x;
-    if (t == 0) { S.chnext = head; }
+    // first round: the chunks the detach listed in the item
+    if (t < S.it.nch) {
+        S.clist[t] = (int32_t)S.it.ch[t].x;
+        S.ccnt[t] = S.it.ch[t].y;
+    }
+    if (t == 0) { S.ncl = S.it.nch; S.chnext = S.it.rest; }
     __syncthreads();
-    while (true) {
-        if (t == 0) {
-            int32_t ch = S.chnext;
-            uint32_t n = 0;
-            while (ch >= 0 && n < (uint32_t)CCAP) {
-                S.clist[n++] = ch;
-                ch = c.B.cnext[ch];
+    for (bool first = true;; first = false) {
+        if (!first) {
+            // longer lists: follow the chain
+            if (t == 0) {
+                int32_t ch = S.chnext;
+                uint32_t n = 0;
+                while (ch >= 0 && n < (uint32_t)CCAP) {
+                    S.clist[n++] = ch;
+                    ch = c.B.cnext[ch];
+                }
+                S.ncl = n;
+                S.chnext = ch;
             }
-            S.ncl = n;
-            S.chnext = ch;
+            __syncthreads();
+            for (uint32_t i = t; i < S.ncl; i += NT) S.ccnt[i] = c.B.ccount[S.clist[i]];
+            __syncthreads();
         }
-        __syncthreads();
         const uint32_t ncl = S.ncl;
         if (ncl == 0) break;
-        const uint32_t slots = ncl * CH;
-        for (uint32_t s0 = 0; s0 < slots; s0 += NT) {
+        // operations of the round, numbered densely: chunk i holds [cpre[i], cpre[i] + ccnt[i])
+        uint32_t total = 0;
+        {
+            uint32_t cnt = t < ncl ? S.ccnt[t] : 0u;
+            cnt = cnt < (uint32_t)CH ? cnt : (uint32_t)CH;
+            uint32_t pre = block_excl(S, cnt, &total);
+            if (t < ncl) S.cpre[t] = pre;
+            __syncthreads();
+        }
+        for (uint32_t s0 = 0; s0 < total; s0 += NT) {
             stage_room(c, S);
             const uint32_t cur = S.cur;
             uint32_t s = s0 + t;
             bool valid = false;
             uint2 op = make_uint2(0, 0);
-            if (s < slots) {
-                uint32_t ch = (uint32_t)S.clist[s / CH];
-                uint32_t cnt = c.B.ccount[ch];
-                cnt = cnt < (uint32_t)CH ? cnt : (uint32_t)CH;
-                if (s % CH < cnt) {
-                    op = c.B.chunks[(unsigned long long)ch * CH + s % CH];
-                    valid = true;
+            if (s < total) {
+                uint32_t lo = 0, hi = ncl;  // last chunk with cpre <= s
+                while (hi - lo > 1) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (S.cpre[mid] <= s) lo = mid; else hi = mid;
                 }
+                op = c.B.chunks[(unsigned long long)(uint32_t)S.clist[lo] * CH + (s - S.cpre[lo])];
+                valid = true;
             }
             uint32_t vloc = op.x - c.v0;
             if (valid && vloc >= c.nvp) {
@@ -506,13 +537,7 @@ __device__ __forceinline__ void consume(ItemCtx& c, PassShared& S, int32_t head)
         // free this round's chunks into the stash; what does not fit goes back to the ring
         const uint32_t ns0 = S.nstash;
         const uint32_t keep = ncl < (uint32_t)STASH - ns0 ? ncl : (uint32_t)STASH - ns0;
-        for (uint32_t i = t; i < ncl; i += NT) {
-            uint32_t ch = (uint32_t)S.clist[i];
-            // reset with a device-scope atomic: a flush of this workgroup may
-            // reserve slots in it with device-scope atomics in this same pass
-            dev_xchg(&c.B.ccount[ch], 0u);
-            if (i < keep) S.stash[ns0 + i] = ch;
-        }
+        for (uint32_t i = t; i < keep; i += NT) S.stash[ns0 + i] = (uint32_t)S.clist[i];
         if (ncl > keep) {
             __syncthreads();
             if (t == 0) S.base = dev_add(&c.B.ctl->ring_tail, (unsigned long long)(ncl - keep));
@@ -770,8 +795,7 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
     c.pass = B.ctl->pass;
     for (;;) {
         if (t == 0) {
-            Item it;
-            it.part = ~0u;
+            unsigned long long pos = ~0ull;
             if (!__hip_atomic_load(&B.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 for (uint32_t k = 0; k < NXCD; ++k) {
                     uint32_t x = (xcd + k) % NXCD;
@@ -779,17 +803,22 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
                     n = n < B.item_cap ? n : B.item_cap;
                     if (__hip_atomic_load(&B.ctl->next[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) continue;
                     uint32_t idx = dev_add(&B.ctl->next[x], 1u);
-                    if (idx < n) { it = B.items[(unsigned long long)x * B.item_cap + idx]; break; }
+                    if (idx < n) { pos = (unsigned long long)x * B.item_cap + idx; break; }
                 }
             }
-            S.it = it;
+            S.itpos = pos;
         }
         __syncthreads();
-        const Item it = S.it;
-        if (it.part == ~0u) break;
+        {
+            const unsigned long long pos = S.itpos;
+            if (pos == ~0ull) break;
+            constexpr uint32_t W16 = sizeof(Item) / 16;
+            if (t < W16) ((uint4*)&S.it)[t] = ((const uint4*)&B.items[pos])[t];
+        }
+        __syncthreads();
         ++items;
-        c.P = it.part;
-        c.q = it.q;
+        c.P = S.it.part;
+        c.q = S.it.q;
         c.v0 = g.pstart[c.P];
         c.nvp = g.pstart[c.P + 1] - c.v0;
         c.qt = Q.qtype[c.q];
@@ -820,7 +849,7 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
             float bgt = cfg.mu * e_p / (float)(np_items ? np_items : 1u);
             budget = bgt < 256.f ? 256u : (bgt > 4.0e9f ? 4000000000u : (uint32_t)bgt);
         }
-        consume(c, S, it.head);
+        consume(c, S);
         if (ppr) ppr_visit(c, S, budget);
         else if (c.qt == Q_BFS) sp_visit<0>(c, S, cfg.win_lv, cfg.yld_lv, budget);
         else sp_visit<WB>(c, S, cfg.win_sp, cfg.yld_sp, budget);

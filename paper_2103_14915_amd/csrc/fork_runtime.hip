@@ -25,6 +25,7 @@ hipError_t launch_process(const GraphDev&, const QueryDev&, const BufDev&, const
 size_t process_dyn_lds(uint32_t vpmax, uint32_t hash_slots);
 int process_threads();
 hipError_t launch_ring_init(uint32_t*, unsigned long long, hipStream_t);
+hipError_t launch_fill64(unsigned long long*, unsigned long long, unsigned long long, hipStream_t);
 hipError_t launch_seed(const GraphDev&, const QueryDev&, const BufDev&, const uint32_t*, hipStream_t);
 hipError_t launch_digest(const QueryDev&, uint32_t, unsigned long long*, hipStream_t);
 hipError_t launch_mlp_score(const GraphDev&, const BufDev&, const float*, float*, float*, void*, uint32_t, hipStream_t);
@@ -107,7 +108,8 @@ struct fork_ctx {
     size_t state_words_cap = 0;
     uint32_t* d_state = nullptr;
     int32_t* d_bhead = nullptr;
-    int32_t* d_btail = nullptr;
+    unsigned long long* d_btw = nullptr;
+    int32_t* d_bover = nullptr;
     uint32_t *d_bval = nullptr, *d_bcnt = nullptr, *d_bfirst = nullptr, *d_qmin = nullptr;
     fk::Item* d_items = nullptr;
     uint32_t item_cap = 0, kmax_cap = 0;
@@ -150,7 +152,8 @@ template <class T> static int dalloc(T** p, size_t n) {
 static void free_wave(fork_ctx* c) {
     hipFree(c->d_state); c->d_state = nullptr;
     hipFree(c->d_bhead); c->d_bhead = nullptr;
-    hipFree(c->d_btail); c->d_btail = nullptr;
+    hipFree(c->d_btw); c->d_btw = nullptr;
+    hipFree(c->d_bover); c->d_bover = nullptr;
     hipFree(c->d_bval); c->d_bval = nullptr;
     hipFree(c->d_bcnt); c->d_bcnt = nullptr;
     hipFree(c->d_bfirst); c->d_bfirst = nullptr;
@@ -417,17 +420,18 @@ static uint64_t qwords(const fork_ctx* c, uint32_t type) { return (type == FORK_
 static int ensure_wave(fork_ctx* c, uint32_t nq, size_t words, uint32_t kmax) {
     int rc;
     if (nq > c->qcap || kmax > c->kmax_cap) {
-        hipFree(c->d_bhead); hipFree(c->d_btail); hipFree(c->d_items);
+        hipFree(c->d_bhead); hipFree(c->d_btw); hipFree(c->d_bover); hipFree(c->d_items);
         hipFree(c->d_bval); hipFree(c->d_bcnt); hipFree(c->d_bfirst); hipFree(c->d_qmin);
         c->d_bval = c->d_bcnt = c->d_bfirst = c->d_qmin = nullptr;
         hipFree(c->d_qtype); hipFree(c->d_qsrc); hipFree(c->d_qmode); hipFree(c->d_qoff);
         hipFree(c->d_qalpha); hipFree(c->d_qeps); hipFree(c->d_digest);
-        c->d_bhead = nullptr; c->d_btail = nullptr; c->d_items = nullptr;
+        c->d_bhead = nullptr; c->d_btw = nullptr; c->d_bover = nullptr; c->d_items = nullptr;
         uint32_t qc = std::max(nq, c->qcap);
         uint32_t kc = std::max(kmax, c->kmax_cap);
         size_t nb = (size_t)c->np * qc;
         if ((rc = dalloc(&c->d_bhead, nb))) return rc;
-        if ((rc = dalloc(&c->d_btail, nb))) return rc;
+        if ((rc = dalloc(&c->d_btw, nb))) return rc;
+        if ((rc = dalloc(&c->d_bover, nb))) return rc;
         if ((rc = dalloc(&c->d_bval, nb))) return rc;
         if ((rc = dalloc(&c->d_bcnt, nb))) return rc;
         if ((rc = dalloc(&c->d_bfirst, nb))) return rc;
@@ -462,7 +466,7 @@ static fk::GraphDev graph_dev(const fork_ctx* c) {
 
 static fk::BufDev buf_dev(const fork_ctx* c) {
     fk::BufDev B;
-    B.bhead = c->d_bhead; B.btail = c->d_btail; B.bval = c->d_bval; B.bcnt = c->d_bcnt; B.bfirst = c->d_bfirst;
+    B.bhead = c->d_bhead; B.btw = c->d_btw; B.bover = c->d_bover; B.bval = c->d_bval; B.bcnt = c->d_bcnt; B.bfirst = c->d_bfirst;
     B.qmin = c->d_qmin; B.pready = c->d_pready; B.chunks = c->d_chunks; B.cnext = c->d_cnext;
     B.ccount = c->d_ccount; B.ring = c->d_ring; B.nch = c->nch; B.pcount = c->d_pcount;
     B.pbest_sp = c->d_pbest_sp; B.pbest_lv = c->d_pbest_lv; B.pbest_pr = c->d_pbest_pr;
@@ -515,7 +519,8 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
         i = j;
     }
     HIPCHK(hipMemsetAsync(c->d_bhead, 0xff, (size_t)c->np * c->qcap * 4, s));
-    HIPCHK(hipMemsetAsync(c->d_btail, 0xff, (size_t)c->np * c->qcap * 4, s));
+    HIPCHK(hipMemsetAsync(c->d_bover, 0xff, (size_t)c->np * c->qcap * 4, s));
+    HIPCHK(fk::launch_fill64(c->d_btw, (unsigned long long)c->np * c->qcap, fk::BTW_EMPTY, s));
     HIPCHK(hipMemsetAsync(c->d_bval, 0xff, (size_t)c->np * c->qcap * 4, s));
     HIPCHK(hipMemsetAsync(c->d_bcnt, 0, (size_t)c->np * c->qcap * 4, s));
     HIPCHK(hipMemsetAsync(c->d_bfirst, 0xff, (size_t)c->np * c->qcap * 4, s));
@@ -713,8 +718,8 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     size_t budget = (fr + reserve) > ((size_t)2 << 30) ? (fr + reserve) - ((size_t)2 << 30) : 0;
     budget = (size_t)(budget * 0.9);
     uint32_t cap_q = c->max_queries ? c->max_queries : nq_total;
-    // per-query bytes beyond state: buckets (8B per partition) + items
-    const size_t per_q_extra = (size_t)c->np * 8 + 64;
+    // per-query bytes beyond state: buckets (28 B per partition) + items
+    const size_t per_q_extra = (size_t)c->np * 28 + 64;
     fk::PassCfg cfg{};
     cfg.sched = (uint32_t)o.scheduler;
     cfg.seed = (uint32_t)o.seed;

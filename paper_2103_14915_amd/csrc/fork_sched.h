@@ -174,11 +174,12 @@ __device__ __forceinline__ void worklist_one(const BufDev& B, const QueryDev& Q,
     const uint32_t x = j % NXCD;
     const uint32_t lane = lane_id();
     bool has = false;
-    int32_t h = -1;
+    int32_t h = -1, o = -1;
     unsigned long long b = (unsigned long long)P * Q.qc + q;
     if (q < Q.nq) {
         h = B.bhead[b];
-        has = h >= 0 && bucket_ready(B.bval[b], Q.qtype[q], B.qmin[q], cfg);
+        o = B.bover[b];
+        has = (h >= 0 || o >= 0) && bucket_ready(B.bval[b], Q.qtype[q], B.qmin[q], cfg);
     }
     unsigned long long mask = wballot(has);
     uint32_t n = __popcll(mask);
@@ -189,14 +190,30 @@ __device__ __forceinline__ void worklist_one(const BufDev& B, const QueryDev& Q,
     if (has) {
         uint32_t pos = base + rank_in(mask);
         if (pos < B.item_cap) {
-            Item it;
-            it.part = P;
-            it.q = q;
-            it.head = h;
-            it.count = 0;
-            B.items[(unsigned long long)x * B.item_cap + pos] = it;
+            // close the tail: record its fill and splice the overflow list after it
+            const unsigned long long w = B.btw[b];
+            uint32_t tl = 0xffffffffu, tf = 0;
+            if (h >= 0) {
+                tl = (uint32_t)(w >> 32);
+                tf = (uint32_t)w < (uint32_t)CH ? (uint32_t)w : (uint32_t)CH;
+                B.ccount[tl] = tf;
+                B.cnext[tl] = o;
+            }
+            Item* it = &B.items[(unsigned long long)x * B.item_cap + pos];
+            int32_t cur = h >= 0 ? h : o;
+            uint32_t n = 0;
+            while (cur >= 0 && n < (uint32_t)ICH) {
+                const bool is_tail = (uint32_t)cur == tl;
+                it->ch[n++] = make_uint2((uint32_t)cur, is_tail ? tf : B.ccount[cur]);
+                cur = is_tail ? o : B.cnext[cur];
+            }
+            it->part = P;
+            it->q = q;
+            it->nch = n;
+            it->rest = cur;
             B.bhead[b] = -1;
-            B.btail[b] = -1;
+            B.bover[b] = -1;
+            B.btw[b] = BTW_EMPTY;
             B.bval[b] = 0xffffffffu;
             B.bcnt[b] = 0;
         } else {
