@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--scale", type=int, default=0, help="experiment: override the R-MAT scale")
     ap.add_argument("--queries", type=int, default=0, help="experiment: use only the first N queries per type")
     ap.add_argument("--max-queries", type=int, default=0, help="queries resident per wave (0 = auto)")
+    ap.add_argument("--pool-mb", type=int, default=0, help="device memory for buffered operations (0 = auto)")
     ap.add_argument("--persistent", action="store_true", help="one persistent cooperative kernel per batch of passes")
     ap.add_argument("--items-per-pass", type=int, default=0, help="work items queued per pass (0 = auto)")
     ap.add_argument("--window-mode", type=int, default=0, help="heuristic-2 window: 0 = query-global, 1 = per visit")
@@ -173,7 +174,8 @@ def main():
     if args.slice_slots >= 0:
         params["slice_slots"] = args.slice_slots
     t0 = time.perf_counter()
-    fg = fork.ForkGraph.from_graph(g, partition_vertices=params["partition_vertices"], max_queries=args.max_queries)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=params["partition_vertices"], max_queries=args.max_queries,
+                                   pool_bytes=args.pool_mb << 20)
     t_load = time.perf_counter() - t0
     nq = 0
     for qt, s in queries:

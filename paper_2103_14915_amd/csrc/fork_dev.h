@@ -85,7 +85,7 @@ struct BufDev {
     int32_t* bover;           // [np*qc] overflow list (-1: none)
     uint32_t* bval;           // [np*qc] best buffered value: SSSP/BFS min value, PPR ~(max mass bits);
                               //         0xffffffff when empty (min works for both encodings)
-    uint32_t* bcnt;           // [np*qc] buffered operations
+    uint32_t* bcnt;           // [np*qc] buffered operations, counted in whole chunks (0 = empty)
     uint32_t* bfirst;         // [np*qc] pass in which the buffer became non-empty
     uint32_t* qmin;           // [qc] SSSP/BFS: best buffered value of the query over all partitions
     uint32_t* pready;         // [np] buffers ready to run (within the query's window)

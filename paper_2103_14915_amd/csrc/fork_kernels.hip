@@ -61,7 +61,7 @@ __global__ void k_seed(GraphDev g, QueryDev Q, BufDev B, const uint32_t* src) {
     unsigned long long b = (unsigned long long)P * Q.qc + q;
     B.bhead[b] = (int32_t)q;
     B.btw[b] = ((unsigned long long)q << 32) | 1ull;  // chunk q is the tail, one slot used
-    B.bcnt[b] = 1;
+    B.bcnt[b] = CH;
     B.bval[b] = t == Q_PPR ? ~__float_as_uint(1.0f) : 0u;
     B.bfirst[b] = 0;
 }

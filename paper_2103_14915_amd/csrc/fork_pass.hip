@@ -411,15 +411,21 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
                     c.B.cnext[last] = dev_xchg(&c.B.bover[b], (int32_t)first);
                 }
             }
-            // bucket summary for the scheduler: operation count and best value
-            dev_add(&c.B.bcnt[b], len);
+            // bucket summary for the scheduler.  The count is kept in whole
+            // chunks (nonzero exactly when the buffer holds operations), so it
+            // changes only when a chunk is added; the best value is updated
+            // only when this run improves it (a stale read can only be high,
+            // since values only decrease between detaches).  Both feed the
+            // schedule only, never the results.
+            if (need) dev_add(&c.B.bcnt[b], need * (uint32_t)CH);
             uint32_t best = 0xffffffffu;
             for (uint32_t j = rsv; j <= i; ++j) {
                 uint32_t v = (uint32_t)S.sk[j];
                 v = is_ppr ? ~v : (v & ~RETAIN);
                 best = v < best ? v : best;
             }
-            dev_min(&c.B.bval[b], best);
+            if (best < __hip_atomic_load(&c.B.bval[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                dev_min(&c.B.bval[b], best);
             c.c_emitted += len;
         }
     }
