@@ -119,6 +119,7 @@ def main():
                     help="LDS slice: 0 = dense, else hash-table slots (-1 = tuned/default)")
     ap.add_argument("--tune", action="store_true", help="run the autotuner on a query sample first (cached)")
     ap.add_argument("--retune", action="store_true", help="with --tune: search again even if a result is cached")
+    ap.add_argument("--tune-sample", type=int, default=1024, help="queries per autotuner trial")
     ap.add_argument("--no-tuned", action="store_true", help="ignore cached autotuner results")
     ap.add_argument("--compare-learned", default="", help="MLP weights (.npy): also time the learned scheduler "
                     "on the same workload and report the speedup over the rule-based one")
@@ -161,7 +162,7 @@ def main():
     if not args.no_tuned:
         t_tune = time.perf_counter()
         tuned = autotune.tune(g, queries, spec, log=lambda *a: print(*a, file=sys.stderr, flush=True),
-                              use_cache=not args.retune) \
+                              use_cache=not args.retune, sample=args.tune_sample) \
             if args.tune else autotune.cached(g, queries)
         if tuned:
             params, source = dict(tuned), ("tuned" if args.tune else "cache")
