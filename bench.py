@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 def algorithmic_bytes(st: dict, kind: str) -> float:
-    """Bytes the buffered pass must move for the work it did (see DESIGN.md).
+    """Bytes the buffered pass must move for the work it did.
 
     per edge scanned: 4 B target id (+ weight bytes for SSSP);
     per edge whose target is in the same partition: 8 B state read+write;
@@ -40,6 +40,21 @@ def algorithmic_bytes(st: dict, kind: str) -> float:
     per_v = 24 if kind == "ppr" else 12
     return (st["edges"] * (4 + wb) + st["intra_edges"] * 8 + st["ops_emitted"] * 8 + st["ops_consumed"] * 16
             + st["vertex_pushes"] * per_v)
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of k_process from the committed rocprofv3 summary of
+    this workload, if that summary was taken from the current kernel source."""
+    from paper_2103_14915_amd import profile_summary as ps
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"k_process_{workload}.md")
+    try:
+        text = open(path).read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_hash") != ps.kernel_source_hash() or "traffic_bytes_per_launch" not in blob:
+        return None
+    return blob
 
 
 def cpu_baseline(g, queries, spec, budget_s=15.0):
@@ -137,8 +152,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(queries shard across GPUs with no exchange; see DESIGN.md)"}))
+        print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1 "
+                                   "(the queries would shard across GPUs with no exchange during a run)"}))
         sys.exit(2)
 
     import torch
@@ -205,6 +220,7 @@ def main():
         tot[k] = st[k]
     value = nq * args.steps / dt
     abytes = algorithmic_bytes(tot, kind if kind != "mixed" else "sssp")
+    prof = measured_traffic(args.workload) if not (args.scale or args.queries) else None
     launches = max(1, tot["process_launches"])
     avg_ms = tot["process_ms"] / launches
     achieved = (abytes / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -226,8 +242,15 @@ def main():
                    "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler, "knobs": params, "knobs_source": source,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_process",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": prof["traffic_bytes_per_launch"] if prof else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_over_algorithmic": (prof["traffic_bytes_per_launch"] / (abytes / launches))
+                     if prof else None,
+                     "profiled_avg_launch_ms": prof.get("avg_launch_ms") if prof else None,
+                     "kernel": "k_process",
                      "avg_launch_ms": avg_ms, "launches_per_step": launches / args.steps,
+                     "algorithmic_bytes_per_launch": abytes / launches,
                      "algorithmic_bytes_per_step": abytes / args.steps},
         "detail": {"graph_gen_s": t_gen, "graph_load_s": t_load,
                    "init_ms_per_step": tot["init_ms"] / args.steps, "run_ms_per_step": tot["run_ms"] / args.steps,

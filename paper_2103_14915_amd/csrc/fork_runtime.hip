@@ -121,6 +121,8 @@ struct fork_ctx {
     std::vector<fork_digest> digests;
     bool ran = false;
     uint32_t res_first = 0, res_n = 0;
+    fk::QueryDev resQ{};        // queries of the resident (last) wave
+    bool dig_pending = false;   // their digests are computed on first request
     std::vector<unsigned long long> res_off;
     fork_stats_t stats{};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -404,6 +406,7 @@ extern "C" int fork_submit(fork_ctx* c, int type, const uint32_t* sources, uint3
         c->digests.clear();
         c->ran = false;
         c->res_n = 0;
+        c->dig_pending = false;
     }
     if (first_id) *first_id = (uint32_t)c->queries.size();
     for (uint32_t i = 0; i < n; ++i) {
@@ -474,6 +477,33 @@ static fk::BufDev buf_dev(const fork_ctx* c) {
     B.sel = c->d_sel; B.pqn = c->d_pqn; B.score = c->d_score;
     B.tr_useful = c->d_tr; B.tr_work = c->d_tr + c->np; B.items = c->d_items; B.item_cap = c->item_cap; B.ctl = c->d_ctl;
     return B;
+}
+
+// Digests of the resident wave's queries (count, sum and hash of the reached
+// values; PPR sums and max), copied to the host.
+static int wave_digest(fork_ctx* c, hipStream_t s) {
+    if (!c->dig_pending) return FORK_OK;
+    const uint32_t q0 = c->res_first, nq = c->res_n;
+    HIPCHK(hipEventRecord(c->ev[2], s));
+    HIPCHK(fk::launch_digest(c->resQ, c->nv, c->d_digest, s));
+    HIPCHK(hipEventRecord(c->ev[3], s));
+    std::vector<unsigned long long> dg((size_t)nq * 6);
+    HIPCHK(hipMemcpyAsync(dg.data(), c->d_digest, dg.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < nq; ++i) {
+        fork_digest& d = c->digests[q0 + i];
+        d.count = dg[i * 6 + 0];
+        d.sum = dg[i * 6 + 1];
+        d.hash = dg[i * 6 + 2];
+        memcpy(&d.fsum, &dg[i * 6 + 3], 8);
+        memcpy(&d.fres, &dg[i * 6 + 4], 8);
+        memcpy(&d.fmax, &dg[i * 6 + 5], 8);
+    }
+    float t_dig = 0;
+    hipEventElapsedTime(&t_dig, c->ev[2], c->ev[3]);
+    c->stats.digest_ms += t_dig;
+    c->dig_pending = false;
+    return FORK_OK;
 }
 
 static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& o, hipStream_t s,
@@ -648,29 +678,19 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
         }
     }
     HIPCHK(hipEventRecord(c->ev[2], s));
-    HIPCHK(fk::launch_digest(Q, c->nv, c->d_digest, s));
-    HIPCHK(hipEventRecord(c->ev[3], s));
-    std::vector<unsigned long long> dg((size_t)nq * 6);
-    HIPCHK(hipMemcpyAsync(dg.data(), c->d_digest, dg.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    for (uint32_t i = 0; i < nq; ++i) {
-        fork_digest& d = c->digests[q0 + i];
-        d.count = dg[i * 6 + 0];
-        d.sum = dg[i * 6 + 1];
-        d.hash = dg[i * 6 + 2];
-        memcpy(&d.fsum, &dg[i * 6 + 3], 8);
-        memcpy(&d.fres, &dg[i * 6 + 4], 8);
-        memcpy(&d.fmax, &dg[i * 6 + 5], 8);
-    }
     float t_init = 0, t_run = 0, t_dig = 0;
     hipEventElapsedTime(&t_init, c->ev[0], c->ev[1]);
     hipEventElapsedTime(&t_run, c->ev[1], c->ev[2]);
-    hipEventElapsedTime(&t_dig, c->ev[2], c->ev[3]);
+    // digests: computed by fork_run before the next wave reuses the state,
+    // or on the first request for the wave that stays resident
+    c->resQ = Q;
+    c->resQ.final_state = nullptr;
+    c->dig_pending = true;
     const fk::Ctl& h = *c->h_ctl;
     fork_stats_t& st = c->stats;
     st.init_ms += t_init;
     st.run_ms += t_run;
-    st.digest_ms += t_dig;
     st.passes += h.pass;
     st.work_items += h.c_items;
     st.edges += h.c_edges;
@@ -765,6 +785,7 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     c->stats.weight_bytes = (uint32_t)c->wbytes;
     c->digests.assign(nq_total, fork_digest{});
     c->res_n = 0;
+    c->dig_pending = false;
     uint64_t passes_left = o.max_passes ? o.max_passes : ~0ull;
     // A wave whose pending operations overflow the pool is split in two and
     // re-run (state is re-initialised per wave, so a retry is exact).
@@ -803,6 +824,7 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
             continue;
         }
         if (rc) return rc;
+        if (wi + 1 < waves.size() && (rc = wave_digest(c, s))) return rc;  // the next wave reuses the state
     }
     c->ran = true;
     return FORK_OK;
@@ -817,6 +839,12 @@ extern "C" int fork_fetch(fork_ctx* c, uint32_t qid, int field, void* dst, uint6
     const uint32_t type = c->queries[qid].type;
     if (field == FORK_FIELD_DIGEST) {
         if (dst_bytes < sizeof(fork_digest)) return fail(FORK_E_INVALID, "dst too small");
+        if (c->dig_pending && qid >= c->res_first && qid < c->res_first + c->res_n) {
+            if (hipSetDevice(c->device) != hipSuccess) return fail(FORK_E_DEVICE, "hipSetDevice failed");
+            HIPCHK(hipDeviceSynchronize());
+            int rc = wave_digest(c, nullptr);
+            if (rc) return rc;
+        }
         if (dst_on_device) HIPCHK(hipMemcpy(dst, &c->digests[qid], sizeof(fork_digest), hipMemcpyHostToDevice));
         else memcpy(dst, &c->digests[qid], sizeof(fork_digest));
         return FORK_OK;
