@@ -55,6 +55,7 @@ struct PassShared {
     uint32_t tp[SCAP];            // target partition of compacted staged op
     int32_t rt[SCAP];             // per run: tail chunk (-1: none)
     uint32_t rp[SCAP];            // per run: slot | taken << 9 | fresh-chunk base << 18
+    uint32_t rbest[SCAP];         // per run: best value (SSSP/BFS min value, PPR ~mass)
     int32_t clist[CCAP];          // chunk ids of the consume round
     uint32_t ccnt[CCAP];          // their valid ops
     uint32_t cpre[CCAP];          // exclusive prefix of ccnt
@@ -212,6 +213,66 @@ __device__ __forceinline__ float thr_of(const ItemCtx& c, uint32_t gv) {
     return c.eps * (float)(c.g.rowptr[gv + 1] - c.g.rowptr[gv]);
 }
 
+// ------------------------------------------------------------ sort
+// Sort the SCAP staged keys of S.sk ascending.  Each wave sorts its 128 keys
+// in registers (two per lane) with a bitonic network whose exchanges are lane
+// shuffles, so it needs no barrier; two merge rounds then combine the four
+// sorted runs, each key moving to (its index in its run) + (the number of
+// keys of the other run that precede it).
+static_assert(SCAP == 2 * NT && NT == 4 * WAVE, "sort layout: four waves, two keys per lane");
+
+__device__ __forceinline__ unsigned long long keep(unsigned long long x, unsigned long long y, bool want_min) {
+    const bool lt = x < y;
+    return want_min == lt ? x : y;
+}
+
+__device__ __forceinline__ uint32_t merged_pos(const PassShared& S, uint32_t i, unsigned long long x, uint32_t run) {
+    const uint32_t base = i & ~(2 * run - 1);
+    const bool left = i - base < run;
+    const uint32_t own = i - base - (left ? 0u : run);
+    const uint32_t other = left ? base + run : base;
+    // ties: keys of the left run go first
+    uint32_t lo = 0, hi = run;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const unsigned long long y = S.sk[other + mid];
+        if (left ? y < x : y <= x) lo = mid + 1;
+        else hi = mid;
+    }
+    return base + own + lo;
+}
+
+__device__ __forceinline__ void sort_staged(PassShared& S) {
+    const uint32_t t = threadIdx.x, l = t & (WAVE - 1), w = t / WAVE;
+    unsigned long long a = S.sk[2 * WAVE * w + l], b = S.sk[2 * WAVE * w + WAVE + l];
+    // a holds element l of the wave's run, b element l + 64
+    for (uint32_t k = 2; k <= 2 * WAVE; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            if (j == WAVE) {  // k = 128: a and b are partners, ascending
+                const unsigned long long lo = a < b ? a : b, hi = a < b ? b : a;
+                a = lo;
+                b = hi;
+            } else {
+                const unsigned long long pa = __shfl_xor(a, (int)j), pb = __shfl_xor(b, (int)j);
+                const uint32_t ia = l, ib = WAVE + l;
+                a = keep(a, pa, ((ia & j) == 0) == ((ia & k) == 0));
+                b = keep(b, pb, ((ib & j) == 0) == ((ib & k) == 0));
+            }
+        }
+    }
+    S.sk[2 * WAVE * w + l] = a;
+    S.sk[2 * WAVE * w + WAVE + l] = b;
+    __syncthreads();
+    for (uint32_t run = 2 * WAVE; run < (uint32_t)SCAP; run <<= 1) {
+        const unsigned long long x0 = S.sk[t], x1 = S.sk[t + NT];
+        const uint32_t p0 = merged_pos(S, t, x0, run), p1 = merged_pos(S, t + NT, x1, run);
+        __syncthreads();
+        S.sk[p0] = x0;
+        S.sk[p1] = x1;
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------ flush
 // Send the staged operations (block-collective; call with uniform control flow).
 __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
@@ -219,22 +280,9 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
     const uint32_t ns = S.ns;
     if (ns == 0) return;
     const uint32_t t = threadIdx.x;
-    uint32_t N = 2;
-    while (N < ns) N <<= 1;
-    for (uint32_t i = ns + t; i < N; i += NT) S.sk[i] = ~0ull;
+    for (uint32_t i = ns + t; i < (uint32_t)SCAP; i += NT) S.sk[i] = ~0ull;  // padding sorts last
     __syncthreads();
-    for (uint32_t k = 2; k <= N; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t x = t; x < N / 2; x += NT) {
-                uint32_t i = ((x & ~(j - 1)) << 1) | (x & (j - 1));
-                uint32_t l = i + j;
-                bool up = (i & k) == 0;
-                unsigned long long a = S.sk[i], b = S.sk[l];
-                if ((a > b) == up) { S.sk[i] = b; S.sk[l] = a; }
-            }
-            __syncthreads();
-        }
-    }
+    sort_staged(S);
     const bool is_ppr = c.qt == Q_PPR;
     // consolidate equal target vertices; thread owns elements [t*SE, t*SE+SE)
     unsigned long long key[SE];
@@ -300,6 +348,7 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             if (tl != 0xffffffffu && f < (uint32_t)CH) kk = ((uint32_t)CH - f) < len ? ((uint32_t)CH - f) : len;
             S.rt[rsv] = (int32_t)tl;
             S.rp[rsv] = (f < 511u ? f : 511u) | (kk << 9) | (need_l << 18);
+            S.rbest[rsv] = 0xffffffffu;
             need_l += (len - kk + CH - 1) / CH;
         }
     }
@@ -360,6 +409,7 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             uint32_t s = info & 0x1ffu, kk = (info >> 9) & 0x1ffu, cb = info >> 18;  // s: slot in the tail
             unsigned long long sv = S.sk[i];
             uint2 op = make_uint2((uint32_t)(sv >> 32), (uint32_t)sv);
+            atomicMin(&S.rbest[rsv], is_ppr ? ~op.y : (op.y & ~RETAIN));  // the run's best value
             if (off < kk) {
                 c.B.chunks[(unsigned long long)(uint32_t)S.rt[rsv] * CH + s + off] = op;
             } else {
@@ -369,6 +419,7 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             }
         }
     }
+    __syncthreads();
     // owners link their fresh chunks.  Every plain store below has a single
     // writer per pass: a chunk's link and count are written by the workgroup
     // that filled it, except a tail's, which only the owner that replaces the
@@ -418,12 +469,7 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             // since values only decrease between detaches).  Both feed the
             // schedule only, never the results.
             if (need) dev_add(&c.B.bcnt[b], need * (uint32_t)CH);
-            uint32_t best = 0xffffffffu;
-            for (uint32_t j = rsv; j <= i; ++j) {
-                uint32_t v = (uint32_t)S.sk[j];
-                v = is_ppr ? ~v : (v & ~RETAIN);
-                best = v < best ? v : best;
-            }
+            const uint32_t best = S.rbest[rsv];
             if (best < __hip_atomic_load(&c.B.bval[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                 dev_min(&c.B.bval[b], best);
             c.c_emitted += len;
@@ -930,8 +976,10 @@ __device__ __forceinline__ void publish_counters(const ItemCtx& c, unsigned long
 }
 
 // One pass (Algorithm 2's IntraPartProcess over the selected partitions).
+// Three workgroups per CU is what the LDS of a typical slice allows; keep the
+// register budget within it (168 VGPRs) so registers never lower occupancy.
 template <int WB>
-__global__ __launch_bounds__(NT) void k_process(GraphDev g, QueryDev Q, BufDev B, PassCfg cfg, uint32_t slice_words,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_process(GraphDev g, QueryDev Q, BufDev B, PassCfg cfg, uint32_t slice_words,
                                                 uint32_t hash_slots) {
     __shared__ PassShared S;
     extern __shared__ uint32_t dyn[];

@@ -56,17 +56,35 @@ def init_theta(seed: int) -> np.ndarray:
     return th
 
 
-def target_of(records: np.ndarray) -> np.ndarray:
-    """Regression target of a trace record: log(1 + useful work of the visit)."""
-    return np.log1p(records[:, 16]).astype(np.float32)
+LABELS = ("useful", "ratio", "net")
+
+
+def target_of(records: np.ndarray, label: str = "useful") -> np.ndarray:
+    """Regression target of a trace record (column 16 = useful work of the
+    partition's visits in the pass, column 17 = all their work):
+    useful: log(1 + useful); ratio: useful / work, the share of the visit that
+    was not redundant; net: log(1 + useful) - log(1 + redundant)."""
+    u, w = records[:, 16].astype(np.float64), records[:, 17].astype(np.float64)
+    if label == "ratio":
+        t = np.where(w > 0, u / np.maximum(w, 1.0), 0.0)
+    elif label == "net":
+        t = np.log1p(u) - np.log1p(np.maximum(w - u, 0.0))
+    elif label == "useful":
+        t = np.log1p(u)
+    else:
+        raise ValueError(label)
+    return t.astype(np.float32)
 
 
 # run knobs for traces and for learned runs of the SSSP+PPR mix (the autotuned
-# setting of the scale-20 mix: SSSP window 16, Delta 512, 16K items per pass)
-RUN_KW = dict(window=16, delta=512, items_per_pass=16384)
+# setting of the scale-20 mix: 8,192-vertex partitions, SSSP window 16,
+# Delta 32768, 64K items per pass, 4,096-slot hashed slices)
+PARTITION_VERTICES = 8192
+RUN_KW = dict(window=16, delta=32768, items_per_pass=65536, slice_slots=4096)
 
 
-def collect(spec: dict, n_sssp: int, n_ppr: int, partition_vertices: int = 0, log=print, **run_kw) -> np.ndarray:
+def collect(spec: dict, n_sssp: int, n_ppr: int, partition_vertices: int = PARTITION_VERTICES, log=print,
+            **run_kw) -> np.ndarray:
     import fpp_inputs as fi
 
     g = fi.rmat(spec["scale"], seed=spec["seed"], weights=(1, 255), weight_seed=spec["wseed"])
@@ -83,9 +101,10 @@ def collect(spec: dict, n_sssp: int, n_ppr: int, partition_vertices: int = 0, lo
     return rec
 
 
-def train(records: np.ndarray, steps: int = 3000, batch: int = 256, lr: float = 1e-3, seed: int = 7):
+def train(records: np.ndarray, steps: int = 3000, batch: int = 256, lr: float = 1e-3, seed: int = 7,
+          label: str = "useful"):
     x = records[:, :16]
-    t = target_of(records)
+    t = target_of(records, label)
     theta = init_theta(seed)
     theta, losses = mlp_train(theta, x, t, steps=steps, batch=batch, lr=lr, seed=seed)
     return theta, losses
@@ -98,16 +117,24 @@ def main(argv=None):
     ap.add_argument("--ppr", type=int, default=512)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--specs", type=int, default=len(TRAIN_SPECS))
+    ap.add_argument("--label", default="useful", choices=LABELS)
+    ap.add_argument("--save-trace", default="", help="also save the trace records (.npy)")
+    ap.add_argument("--load-trace", default="", help="train on saved trace records instead of tracing")
     args = ap.parse_args(argv)
-    recs = [collect(s, args.sssp, args.ppr) for s in TRAIN_SPECS[:args.specs]]
-    records = np.concatenate(recs)
+    if args.load_trace:
+        records = np.load(args.load_trace)
+    else:
+        records = np.concatenate([collect(s, args.sssp, args.ppr) for s in TRAIN_SPECS[:args.specs]])
+    if args.save_trace:
+        np.save(args.save_trace, records)
     t0 = time.time()
-    theta, losses = train(records, steps=args.steps)
+    theta, losses = train(records, steps=args.steps, label=args.label)
     print(f"[learn] trained on {records.shape[0]} visits, {args.steps} steps in {time.time() - t0:.1f}s: "
           f"loss {losses[:50].mean():.4f} -> {losses[-50:].mean():.4f}", flush=True)
     np.save(args.out, theta)
     meta = {"records": int(records.shape[0]), "steps": args.steps, "loss_first": float(losses[:50].mean()),
-            "loss_last": float(losses[-50:].mean()), "specs": TRAIN_SPECS[:args.specs],
+            "loss_last": float(losses[-50:].mean()), "specs": TRAIN_SPECS[:args.specs], "label": args.label,
+            "run_knobs": dict(RUN_KW, partition_vertices=PARTITION_VERTICES),
             "queries": {"sssp": args.sssp, "ppr": args.ppr}}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(meta, f, indent=1)
