@@ -106,8 +106,8 @@ def candidates(g, queries) -> dict:
     }
     if kinds & {"sssp", "bfs"}:
         w = max(1, int(round(wmean)))
-        c["window"] = [0, max(1, w // 8), max(1, w // 2), 2 * w]
-        c["delta"] = [0, 4 * w, 16 * w, 256 * w]
+        c["window"] = [0, max(1, w // 8), max(1, w // 2), 2 * w, 8 * w, 32 * w]
+        c["delta"] = [0, 4 * w, 16 * w, 64 * w, 256 * w]
     return c
 
 
