@@ -104,6 +104,7 @@ struct BufDev {
     uint32_t* pvisits;        // [np] visits
     uint32_t* pn;             // [np] items of the partition in the current pass
     uint32_t* pqn;            // [np] (partition, query) buffers holding operations
+    uint32_t* pqmin;          // [np] SSSP/BFS buffers holding their query's best buffered value (dist_min)
     uint32_t* sel;            // [max parts per pass] selected partitions
     float* score;             // [np] learned score (LEARNED policy)
     float* tr_useful;         // trace runs: [np] useful work of the pass's visits

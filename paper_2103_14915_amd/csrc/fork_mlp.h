@@ -41,7 +41,8 @@ __device__ void gstat_body(const GraphDev& g, const BufDev& B, GStat* out) {
 // Feature vector of partition P (16 fp32 values): buffer size, ready share,
 // best SSSP distance / BFS level / PPR mass relative to the global range and
 // their presence flags, recency, visits, partition size, age of the oldest
-// buffered operation, and the fraction of partitions with work.
+// buffered operation, and the share and count of its buffers that hold their
+// query's dist_min.
 __device__ void partition_features(const GraphDev& g, const BufDev& B, const GStat& s, uint32_t pass, uint32_t P,
                                    float* x) {
     uint32_t cnt = B.pcount[P];
@@ -65,8 +66,10 @@ __device__ void partition_features(const GraphDev& g, const BufDev& B, const GSt
     x[11] = (float)(v1 - v0) / (float)VPMAX;
     uint32_t pf = B.pfirst[P];
     x[12] = pf < INF ? (float)(pass - pf) / fp : 0.f;
-    x[13] = (float)s.nparts / (float)(g.np ? g.np : 1u);
-    x[14] = log1pf((float)s.ops) * 0.05f;
+    // buffers holding their query's dist_min: visiting them is what advances
+    // the queries' heuristic-2 windows
+    x[13] = (float)B.pqmin[P] / (float)(B.pqn[P] ? B.pqn[P] : 1u);
+    x[14] = log1pf((float)B.pqmin[P]) * 0.125f;
     x[15] = pr > 0.f ? fminf(1.f, pr * 1e3f) : 0.f;
 }
 

@@ -89,7 +89,7 @@ struct fork_ctx {
     // partition summaries
     uint32_t *d_pcount = nullptr, *d_pbest_sp = nullptr, *d_pbest_lv = nullptr, *d_pbest_pr = nullptr,
              *d_pfirst = nullptr, *d_plast = nullptr, *d_pvisits = nullptr, *d_pn = nullptr,
-             *d_sel = nullptr, *d_pqn = nullptr, *d_pready = nullptr;
+             *d_sel = nullptr, *d_pqn = nullptr, *d_pready = nullptr, *d_pqmin = nullptr;
     float* d_score = nullptr;
     float* d_mlp = nullptr;
     float* d_feat = nullptr;       // [np*16] features (trace runs)
@@ -179,7 +179,8 @@ extern "C" void fork_destroy(fork_ctx* c) {
     free_wave(c);
     void* ptrs[] = {c->d_rowptr, c->d_col, c->d_w, c->d_pstart, c->d_vpart, c->d_chunks, c->d_cnext,
                     c->d_ccount, c->d_ring, c->d_pcount, c->d_pbest_sp, c->d_pbest_lv, c->d_pbest_pr,
-                    c->d_pfirst, c->d_plast, c->d_pvisits, c->d_pn, c->d_sel, c->d_pqn, c->d_pready, c->d_score, c->d_mlp,
+                    c->d_pfirst, c->d_plast, c->d_pvisits, c->d_pn, c->d_sel, c->d_pqn, c->d_pready, c->d_pqmin,
+                    c->d_score, c->d_mlp,
                     c->d_ctl, c->d_gstat, c->d_feat, c->d_tr, c->d_final};
     for (void* p : ptrs) if (p) hipFree(p);
     if (c->h_ctl) hipHostFree(c->h_ctl);
@@ -345,7 +346,7 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     if ((rc = dalloc(&c->d_ring, c->nch))) return cleanup(rc);
     // partition summaries
     uint32_t** parr[] = {&c->d_pcount, &c->d_pbest_sp, &c->d_pbest_lv, &c->d_pbest_pr, &c->d_pfirst,
-                         &c->d_plast, &c->d_pvisits, &c->d_pn, &c->d_sel, &c->d_pqn, &c->d_pready};
+                         &c->d_plast, &c->d_pvisits, &c->d_pn, &c->d_sel, &c->d_pqn, &c->d_pready, &c->d_pqmin};
     for (auto pp : parr) if ((rc = dalloc(pp, c->np + 1))) return cleanup(rc);
     if ((rc = dalloc(&c->d_score, c->np + 1))) return cleanup(rc);
     if ((rc = dalloc(&c->d_mlp, fk::MLP_NPARAM))) return cleanup(rc);
@@ -474,7 +475,7 @@ static fk::BufDev buf_dev(const fork_ctx* c) {
     B.ccount = c->d_ccount; B.ring = c->d_ring; B.nch = c->nch; B.pcount = c->d_pcount;
     B.pbest_sp = c->d_pbest_sp; B.pbest_lv = c->d_pbest_lv; B.pbest_pr = c->d_pbest_pr;
     B.pfirst = c->d_pfirst; B.plast = c->d_plast; B.pvisits = c->d_pvisits; B.pn = c->d_pn;
-    B.sel = c->d_sel; B.pqn = c->d_pqn; B.score = c->d_score;
+    B.sel = c->d_sel; B.pqn = c->d_pqn; B.pqmin = c->d_pqmin; B.score = c->d_score;
     B.tr_useful = c->d_tr; B.tr_work = c->d_tr + c->np; B.items = c->d_items; B.item_cap = c->item_cap; B.ctl = c->d_ctl;
     return B;
 }
@@ -564,6 +565,7 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
     HIPCHK(hipMemsetAsync(c->d_pvisits, 0, (c->np + 1) * 4ull, s));
     HIPCHK(hipMemsetAsync(c->d_pn, 0, (c->np + 1) * 4ull, s));
     HIPCHK(hipMemsetAsync(c->d_pqn, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetAsync(c->d_pqmin, 0, (c->np + 1) * 4ull, s));
     if (c->nch < nq + 64ull) return fail(FORK_E_CAPACITY, "operation pool too small for %u queries", nq);
     fk::Ctl ctl0{};
     ctl0.ring_head = nq;

@@ -67,7 +67,9 @@ __device__ void select_body(const GraphDev& g, const BufDev& B, const PassCfg& c
         case S_FIFO: k = B.pfirst[P]; break;
         case S_MAXOPS: k = ~cnt; break;
         case S_RANDOM: k = (uint32_t)mix64(((unsigned long long)cfg.seed << 40) ^ ((unsigned long long)pass << 20) ^ P); break;
-        case S_LEARNED: k = ~ordf(B.score[P]); break;
+        // learned: partitions holding some query's dist_min first (they carry
+        // heuristic 2's progress), each class in the network's score order
+        case S_LEARNED: k = ((B.pqmin[P] ? 0u : 1u) << 31) | (~ordf(B.score[P]) >> 1); break;
         default: {
             uint32_t sp = B.pbest_sp[P], lv = B.pbest_lv[P];
             float pr = __uint_as_float(B.pbest_pr[P]);
@@ -241,11 +243,11 @@ __device__ __forceinline__ void qmin_one(const BufDev& B, const QueryDev& Q, uin
 // scorer read.
 __device__ void psum_one(const BufDev& B, const QueryDev& Q, const PassCfg& cfg, uint32_t P) {
     __shared__ unsigned long long s_cnt;
-    __shared__ unsigned int s_sp, s_lv, s_pr, s_ne, s_rd, s_first;
-    if (threadIdx.x == 0) { s_cnt = 0; s_sp = INF; s_lv = INF; s_pr = 0; s_ne = 0; s_rd = 0; s_first = INF; }
+    __shared__ unsigned int s_sp, s_lv, s_pr, s_ne, s_rd, s_first, s_hm;
+    if (threadIdx.x == 0) { s_cnt = 0; s_sp = INF; s_lv = INF; s_pr = 0; s_ne = 0; s_rd = 0; s_first = INF; s_hm = 0; }
     __syncthreads();
     unsigned long long cnt = 0;
-    uint32_t sp = INF, lv = INF, pr = 0, ne = 0, rd = 0, first = INF;
+    uint32_t sp = INF, lv = INF, pr = 0, ne = 0, rd = 0, first = INF, hm = 0;
     for (uint32_t q = threadIdx.x; q < Q.nq; q += blockDim.x) {
         unsigned long long b = (unsigned long long)P * Q.qc + q;
         uint32_t cb = B.bcnt[b];
@@ -257,6 +259,7 @@ __device__ void psum_one(const BufDev& B, const QueryDev& Q, const PassCfg& cfg,
         else if (t == Q_BFS) lv = v < lv ? v : lv;
         else sp = v < sp ? v : sp;
         rd += bucket_ready(v, t, B.qmin[q], cfg);
+        hm += (t != Q_PPR && v == B.qmin[q]) ? 1u : 0u;  // this buffer holds the query's dist_min
         uint32_t f = B.bfirst[b];
         first = f < first ? f : first;
     }
@@ -267,6 +270,7 @@ __device__ void psum_one(const BufDev& B, const QueryDev& Q, const PassCfg& cfg,
     if (ne) atomicAdd(&s_ne, ne);
     if (rd) atomicAdd(&s_rd, rd);
     if (first < INF) atomicMin(&s_first, first);
+    if (hm) atomicAdd(&s_hm, hm);
     __syncthreads();
     if (threadIdx.x == 0) {
         B.pcount[P] = s_cnt > 0xffffffffull ? 0xffffffffu : (uint32_t)s_cnt;
@@ -276,6 +280,7 @@ __device__ void psum_one(const BufDev& B, const QueryDev& Q, const PassCfg& cfg,
         B.pqn[P] = s_ne;
         B.pready[P] = s_rd;
         B.pfirst[P] = s_first;
+        B.pqmin[P] = s_hm;
     }
     __syncthreads();
 }
