@@ -42,11 +42,12 @@ def algorithmic_bytes(st: dict, kind: str) -> float:
             + st["vertex_pushes"] * per_v)
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, root: str = ""):
     """HBM bytes per launch of k_process from the committed rocprofv3 summary of
     this workload, if that summary was taken from the current kernel source."""
     from paper_2103_14915_amd import profile_summary as ps
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"k_process_{workload}.md")
+    root = root or os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", f"k_process_{workload}.md")
     try:
         text = open(path).read()
         blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])

@@ -1,0 +1,126 @@
+"""Host-side logic that needs no GPU: the autotuner's search and cache, the
+rocprofv3 summariser, bench.py's one-GPU guard and traffic lookup."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import fpp_inputs as fi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture()
+def autotune(tmp_path, monkeypatch):
+    from paper_2103_14915_amd import autotune as at
+    monkeypatch.setattr(at, "CACHE", str(tmp_path / "cache.json"))
+    monkeypatch.setattr(at, "device_name", lambda: "test-device")
+    return at
+
+
+def test_autotune_coordinate_descent_and_cache(autotune, monkeypatch):
+    """With a synthetic cost model the search finds the best value of every
+    knob, caches it under (graph, mix, device), and later calls reuse it."""
+    g = fi.rmat(10, seed=1, weights=(1, 9), weight_seed=2)
+    queries = [("sssp", fi.sources_uniform(g, 40, 3)), ("ppr", fi.sources_uniform(g, 20, 4))]
+    best = {"partition_vertices": 32768, "items_per_pass": 16384, "persistent": 1, "slice_slots": 2048,
+            "window": 4, "delta": 80}
+    calls = []
+
+    def trial(g_, sample, spec, p, stream=None):
+        calls.append(dict(p))
+        assert sum(len(s) for _, s in sample) <= 24  # the sample, not the whole batch
+        return 100.0 + 10.0 * sum(k in best and p[k] == best[k] for k in p)  # more matches, more q/s
+
+    monkeypatch.setattr(autotune, "_trial", trial)
+    cand = autotune.candidates(g, queries)
+    w = max(1, int(round(float(g.weight.mean()))))
+    best["window"], best["delta"] = cand["window"][2], cand["delta"][1]
+    p = autotune.tune(g, queries, {}, sample=24, log=lambda *a: None)
+    for k, v in best.items():
+        assert p[k] == v, (k, p[k], v)
+    assert autotune.cached(g, queries) == p
+    n = len(calls)
+    assert autotune.tune(g, queries, {}, sample=24, log=lambda *a: None) == p
+    assert len(calls) == n  # served from the cache
+    cache = json.load(open(autotune.CACHE))
+    (key,) = cache
+    assert key.endswith("|test-device") and cache[key]["trials"][0]["params"] == autotune.DEFAULTS
+    assert w >= 1
+
+
+def test_autotune_cache_falls_back_to_other_device(autotune):
+    g = fi.rmat(9, seed=5)
+    queries = [("ppr", fi.sources_uniform(g, 8, 6))]
+    sig = autotune.signature(g, queries)
+    json.dump({f"{sig}|another-gpu": {"params": {"partition_vertices": 8192}}}, open(autotune.CACHE, "w"))
+    got = autotune.cached(g, queries)
+    assert got["partition_vertices"] == 8192 and got["slice_slots"] == autotune.DEFAULTS["slice_slots"]
+    other = [("ppr", fi.sources_uniform(g, 9, 6))]
+    assert autotune.cached(g, other) is None  # a different query mix is a different key
+
+
+def test_autotune_sample_keeps_the_mix(autotune):
+    g = fi.rmat(9, seed=7)
+    q = [("sssp", np.arange(300)), ("bfs", np.arange(100)), ("ppr", np.arange(100))]
+    s = autotune._sample(q, 100)
+    assert [qt for qt, _ in s] == ["sssp", "bfs", "ppr"]
+    assert [len(x) for _, x in s] == [60, 20, 20]
+    assert all(np.all(np.diff(x) > 0) for _, x in s)  # subsets in submit order, no repeats
+
+
+def _write_csv(path, header, rows):
+    with open(path, "w") as f:
+        f.write(",".join(header) + "\n")
+        for r in rows:
+            f.write(",".join(str(x) for x in r) + "\n")
+
+
+def test_profile_summary_scales_counters_by_copy_calibration(tmp_path):
+    from paper_2103_14915_amd import profile_summary as ps
+    stats = tmp_path / "stats.csv"
+    _write_csv(stats, ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"],
+               [["void fk::k_process<0>(x)", 4, 8e6, 2e6, 90.0], ["fk::k_select(x)", 4, 1e5, 2.5e4, 1.0]])
+    pmc_hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
+    _write_csv(fetch, pmc_hdr, [["fk::k_process<0>(x)", "FETCH_SIZE", 1000.0]] * 4)
+    _write_csv(write, pmc_hdr, [["fk::k_process<0>(x)", "WRITE_SIZE", 500.0]] * 4)
+    cf, cw = tmp_path / "cf.csv", tmp_path / "cw.csv"
+    copy_bytes = 1 << 20  # the copy moved 1 MiB; its counters read half (fetch) and all (write) of it
+    _write_csv(cf, pmc_hdr, [["__amd_rocclr_copyBuffer", "FETCH_SIZE", 512.0]] * 2)
+    _write_csv(cw, pmc_hdr, [["__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024.0]] * 2)
+    out = tmp_path / "k.md"
+    ps.main(["--stats", str(stats), "--fetch", str(fetch), "--write", str(write), "--copy-fetch", str(cf),
+             "--copy-write", str(cw), "--copy-bytes", str(copy_bytes), "--kernel", "k_process",
+             "--command", "cmd", "--out", str(out)])
+    blob = json.loads(out.read_text().split("```json", 1)[1].split("```", 1)[0])
+    assert blob["fetch_scale"] == pytest.approx(2.0) and blob["write_scale"] == pytest.approx(1.0)
+    assert blob["fetch_bytes_per_launch"] == pytest.approx(1000.0 * 1024 * 2.0)
+    assert blob["write_bytes_per_launch"] == pytest.approx(500.0 * 1024)
+    assert blob["avg_launch_ms"] == pytest.approx(2.0) and blob["calls"] == 4
+    assert blob["source_hash"] == ps.kernel_source_hash()
+
+
+def test_bench_traffic_lookup_requires_matching_source(tmp_path):
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2103_14915_amd import profile_summary as ps
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    blob = {"kernel": "k_process", "source_hash": ps.kernel_source_hash(), "traffic_bytes_per_launch": 123.0}
+    (prof / "k_process_w.md").write_text("x\n```json\n" + json.dumps(blob) + "\n```\n")
+    assert bench.measured_traffic("w", str(tmp_path))["traffic_bytes_per_launch"] == 123.0
+    blob["source_hash"] = "0" * 16
+    (prof / "k_process_w.md").write_text("x\n```json\n" + json.dumps(blob) + "\n```\n")
+    assert bench.measured_traffic("w", str(tmp_path)) is None  # profile of another kernel version
+    assert bench.measured_traffic("missing", str(tmp_path)) is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
