@@ -545,21 +545,26 @@ __device__ __forceinline__ void consume(ItemCtx& c, PassShared& S) {
             if (t < ncl) S.cpre[t] = pre;
             __syncthreads();
         }
+        // operation s: chunk = last with cpre <= s.  Each step loads the
+        // next step's operation ahead, so its latency overlaps this step.
+        auto load_op = [&](uint32_t s) -> uint2 {
+            uint32_t lo = 0, hi = ncl;
+            while (hi - lo > 1) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (S.cpre[mid] <= s) lo = mid; else hi = mid;
+            }
+            return c.B.chunks[(unsigned long long)(uint32_t)S.clist[lo] * CH + (s - S.cpre[lo])];
+        };
+        uint2 ahead = t < total ? load_op(t) : make_uint2(0, 0);
         for (uint32_t s0 = 0; s0 < total; s0 += NT) {
             stage_room(c, S);
             const uint32_t cur = S.cur;
-            uint32_t s = s0 + t;
-            bool valid = false;
-            uint2 op = make_uint2(0, 0);
-            if (s < total) {
-                uint32_t lo = 0, hi = ncl;  // last chunk with cpre <= s
-                while (hi - lo > 1) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (S.cpre[mid] <= s) lo = mid; else hi = mid;
-                }
-                op = c.B.chunks[(unsigned long long)(uint32_t)S.clist[lo] * CH + (s - S.cpre[lo])];
-                valid = true;
-            }
+            const uint32_t s = s0 + t;
+            const bool valid0 = s < total;
+            const uint2 op0 = ahead;
+            if (s + NT < total) ahead = load_op(s + NT);
+            bool valid = valid0;
+            uint2 op = valid0 ? op0 : make_uint2(0, 0);
             uint32_t vloc = op.x - c.v0;
             if (valid && vloc >= c.nvp) {
                 dev_or(&c.B.ctl->err, (uint32_t)ERR_CORRUPT);
@@ -701,19 +706,24 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
         if (t == 0) c.c_vpush += nb;
         const uint32_t total = batch_scan(S, nb);
         edges += total;
+        // edge j's target and tentative distance; each step loads the next
+        // step's edge ahead, so its latency overlaps this step
+        auto load_edge = [&](uint32_t j, uint32_t& u, uint32_t& nd) {
+            uint32_t b = find_b(S, nb, j);
+            uint32_t e = S.brow[b] + (j - S.bpre[b]);
+            u = c.g.col[e];
+            unsigned long long sum = (unsigned long long)S.bval[b] + edge_w<WB>(c.g.w, e);
+            nd = sum >= INF ? INF - 1 : (uint32_t)sum;
+        };
+        uint32_t u_ahead = 0, nd_ahead = 0;
+        if (t < total) load_edge(t, u_ahead, nd_ahead);
         for (uint32_t k0 = 0; k0 < total; k0 += NT) {
             stage_room(c, S);
             const uint32_t cur = S.cur;
             uint32_t j = k0 + t;
             bool valid = j < total;
-            uint32_t u = 0, nd = 0;
-            if (valid) {
-                uint32_t b = find_b(S, nb, j);
-                uint32_t e = S.brow[b] + (j - S.bpre[b]);
-                u = c.g.col[e];
-                unsigned long long sum = (unsigned long long)S.bval[b] + edge_w<WB>(c.g.w, e);
-                nd = sum >= INF ? INF - 1 : (uint32_t)sum;
-            }
+            uint32_t u = valid ? u_ahead : 0u, nd = valid ? nd_ahead : 0u;
+            if (j + NT < total) load_edge(j + NT, u_ahead, nd_ahead);
             uint32_t ul = u - c.v0;
             bool intra = valid && ul < c.nvp;
             bool win_ = false;
@@ -789,19 +799,24 @@ __device__ __forceinline__ void ppr_visit(ItemCtx& c, PassShared& S, uint32_t bu
         __syncthreads();
         const uint32_t total = batch_scan(S, nb);
         edges += total;
+        // edge j's target and pushed share, loaded one step ahead
+        auto load_edge = [&](uint32_t j, uint32_t& u, float& share) {
+            uint32_t b = find_b(S, nb, j);
+            uint32_t e = S.brow[b] + (j - S.bpre[b]);
+            u = c.g.col[e];
+            share = __uint_as_float(S.bval[b]);
+        };
+        uint32_t u_ahead = 0;
+        float share_ahead = 0.f;
+        if (t < total) load_edge(t, u_ahead, share_ahead);
         for (uint32_t k0 = 0; k0 < total; k0 += NT) {
             stage_room(c, S);
             const uint32_t cur = S.cur;
             uint32_t j = k0 + t;
             bool valid = j < total;
-            uint32_t u = 0;
-            float share = 0.f;
-            if (valid) {
-                uint32_t b = find_b(S, nb, j);
-                uint32_t e = S.brow[b] + (j - S.bpre[b]);
-                u = c.g.col[e];
-                share = __uint_as_float(S.bval[b]);
-            }
+            uint32_t u = valid ? u_ahead : 0u;
+            float share = valid ? share_ahead : 0.f;
+            if (j + NT < total) load_edge(j + NT, u_ahead, share_ahead);
             uint32_t ul = u - c.v0;
             bool intra = valid && ul < c.nvp;
             bool win_ = false;
