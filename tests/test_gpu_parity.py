@@ -327,3 +327,77 @@ def test_large_partitions_use_hashed_slice():
         R = np.stack([fg.fetch(12 + i, fork.FIELD_R) for i in range(8)])
         fg.close()
         check_ppr(g, s3, P, R, 1e-6, 1)
+
+
+def test_four_byte_weights_and_clamped_tentative_sums():
+    """Weights above 65535 use the 4-byte weight path; a non-shortest path whose
+    length exceeds INT32_MAX is clamped while the true distance is exact."""
+    fork = _fork()
+    rng = np.random.default_rng(40)
+    n, m = 300, 1500
+    src = rng.integers(0, n, m)
+    dst = rng.integers(0, n, m)
+    w = rng.integers(1 << 21, 1 << 22, m)
+    # a separate triangle: n -> n+1 -> n+2 costs 3e9 (beyond int32), n -> n+2 costs 2e9
+    src = np.concatenate([src, [n, n + 1, n]])
+    dst = np.concatenate([dst, [n + 1, n + 2, n + 2]])
+    w = np.concatenate([w, [1_500_000_000, 1_500_000_000, 2_000_000_000]])
+    g = fi.from_edges(n + 3, src, dst, w)
+    srcs = np.asarray([n, 5, 17, 123], np.uint32)
+    ref = oracle.sssp(g, srcs)
+    assert ref[0, n + 2] == 2_000_000_000 and ref[0, n + 1] == 1_500_000_000
+    for pv in (16, 4096):
+        say("4-byte weights pv", pv)
+        out, _ = run_sp(fork, g, srcs, partition_vertices=pv)
+        np.testing.assert_array_equal(out, ref)
+
+
+def test_degenerate_sources_and_repeated_sources():
+    """Sources without out-edges (isolated or dangling), the same source
+    submitted several times, and one source run as SSSP, BFS and PPR."""
+    fork = _fork()
+    g = fi.rmat(12, seed=41, weights=(1, 255), weight_seed=141)
+    deg = g.out_degree()
+    indeg = np.bincount(g.col, minlength=g.num_vertices)
+    isolated = np.flatnonzero((deg == 0) & (indeg == 0))[:3]
+    dangling = np.flatnonzero((deg == 0) & (indeg > 0))[:3]
+    hub = int(np.argmax(deg))
+    srcs = np.concatenate([isolated, dangling, [hub, hub, 7, 7]]).astype(np.uint32)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=256)
+    fg.submit("sssp", srcs)
+    fg.submit("bfs", srcs)
+    fg.submit("ppr", srcs, alpha=ALPHA, epsilon=1e-6, eps_mode=1)
+    say("degenerate sources", srcs.tolist())
+    fg.run(max_passes=200000)
+    n = len(srcs)
+    np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(n)]), oracle.sssp(g, srcs))
+    np.testing.assert_array_equal(np.stack([fg.fetch(n + i) for i in range(n)]), oracle.bfs(g, srcs))
+    P = np.stack([fg.fetch(2 * n + i, fork.FIELD_P) for i in range(n)])
+    R = np.stack([fg.fetch(2 * n + i, fork.FIELD_R) for i in range(n)])
+    fg.close()
+    check_ppr(g, srcs, P, R, 1e-6, 1)
+    for i in range(len(isolated) + len(dangling)):
+        # no out-edges: all mass stops at the source (p = alpha, the rest leaks)
+        assert P[i, srcs[i]] == pytest.approx(ALPHA, rel=1e-6) and P[i].sum() == pytest.approx(ALPHA, rel=1e-6)
+
+
+def test_one_partition_and_one_query_per_wave():
+    """The whole graph in one partition (every edge stays inside it), and waves
+    of a single query each (every wave re-initialises state and buffers)."""
+    fork = _fork()
+    g = fi.rmat(11, seed=42, weights=(1, 99), weight_seed=142)
+    srcs = fi.sources_uniform(g, 6, 43)
+    ref = oracle.sssp(g, srcs)
+    say("one partition")
+    out, st = run_sp(fork, g, srcs, partition_vertices=1 << 12)
+    assert st["num_partitions"] == 1
+    np.testing.assert_array_equal(out, ref)
+    say("one query per wave")
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=128, max_queries=1)
+    fg.submit("sssp", srcs)
+    fg.run(max_passes=200000)
+    assert fg.stats()["waves"] == len(srcs)
+    for i in range(len(srcs)):
+        assert (fg.digest(i)["count"], fg.digest(i)["sum"], fg.digest(i)["hash"]) == sp_digest(ref[i])
+    np.testing.assert_array_equal(fg.fetch(len(srcs) - 1), ref[-1])  # the last wave stays resident
+    fg.close()
