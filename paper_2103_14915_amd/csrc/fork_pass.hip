@@ -163,23 +163,53 @@ constexpr int MAXPROBE = 32;
 // of their vertices): an LDS open-addressing table; a vertex whose probe path
 // is full stays in global memory for the whole visit (slots are never freed
 // during a visit, so every thread reaches the same decision).
-__device__ __forceinline__ uint32_t* slot(const ItemCtx& c, uint32_t vloc) {
-    if (!c.hmask) {
-        if (c.st[vloc] == UNLOADED) atomicCAS(&c.st[vloc], UNLOADED, c.gstate[c.v0 + vloc]);
-        return &c.st[vloc];
-    }
+//
+// In the hashed form a slot's key word also carries the vertex's frontier
+// flag (FRONT), so no per-vertex flag array is needed and the table can use
+// that LDS.  A vertex kept in global memory has no flag: it may enter the
+// frontier more than once, which repeats no update (a second SSSP expansion
+// finds no shorter path, a second PPR push finds its residual already taken).
+constexpr uint32_t FRONT = 0x80000000u;
+
+// LDS index of vertex vloc's value for this visit (claimed on first touch), or
+// -1 when it stays in global memory.
+__device__ __forceinline__ int32_t slot_index(const ItemCtx& c, uint32_t vloc) {
+    if (!c.hmask) return (int32_t)vloc;
     // Fibonacci hashing: the top bits of vloc * 2^32/phi pick the home slot
     uint32_t h = (uint32_t)(((unsigned long long)(vloc * 0x9E3779B1u) * (c.hmask + 1ull)) >> 32);
     for (int i = 0; i < MAXPROBE; ++i) {
         uint32_t k = c.hkeys[h];
         if (k == EMPTY_KEY) k = atomicCAS(&c.hkeys[h], EMPTY_KEY, vloc);
-        if (k == EMPTY_KEY || k == vloc) {
-            if (c.st[h] == UNLOADED) atomicCAS(&c.st[h], UNLOADED, c.gstate[c.v0 + vloc]);
-            return &c.st[h];
-        }
+        if (k == EMPTY_KEY || (k & ~FRONT) == vloc) return (int32_t)h;
         h = (h + 1) & c.hmask;
     }
-    return c.gstate + c.v0 + vloc;
+    return -1;
+}
+
+// Pointer to vertex vloc's value, fetched from global memory on first touch.
+__device__ __forceinline__ uint32_t* slot_at(const ItemCtx& c, int32_t idx, uint32_t vloc) {
+    if (idx < 0) return c.gstate + c.v0 + vloc;
+    if (c.st[idx] == UNLOADED) atomicCAS(&c.st[idx], UNLOADED, c.gstate[c.v0 + vloc]);
+    return &c.st[idx];
+}
+
+__device__ __forceinline__ uint32_t* slot(const ItemCtx& c, uint32_t vloc) {
+    return slot_at(c, slot_index(c, vloc), vloc);
+}
+
+// Frontier flag of vertex vloc (slot idx): set it, returning whether it was clear.
+__device__ __forceinline__ bool front_set(const ItemCtx& c, int32_t idx, uint32_t vloc) {
+    if (!c.hmask) return tas(c.bits, vloc);
+    if (idx < 0) return true;
+    return !(atomicOr(&c.hkeys[idx], FRONT) & FRONT);
+}
+__device__ __forceinline__ void front_clear(const ItemCtx& c, uint32_t vloc) {
+    if (!c.hmask) {
+        atomicAnd(&c.bits[vloc >> 5], ~(1u << (vloc & 31)));
+        return;
+    }
+    const int32_t idx = slot_index(c, vloc);
+    if (idx >= 0) atomicAnd(&c.hkeys[idx], ~FRONT);
 }
 
 // Value reads and updates through a slot: LDS instructions for the dense
@@ -188,15 +218,16 @@ __device__ __forceinline__ uint32_t sv_get(const ItemCtx& c, uint32_t vloc) {
     if (!c.hmask) return c.st[vloc];
     return __hip_atomic_load(slot(c, vloc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ uint32_t sv_min(const ItemCtx& c, uint32_t vloc, uint32_t x) {
-    uint32_t* p = slot(c, vloc);
+__device__ __forceinline__ uint32_t at_min(const ItemCtx& c, uint32_t* p, uint32_t x) {
     if (!c.hmask) return atomicMin(p, x);
     return __hip_atomic_fetch_min(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+__device__ __forceinline__ float at_addf(const ItemCtx& c, uint32_t* p, float x) {
+    if (!c.hmask) return atomicAdd((float*)p, x);
+    return __hip_atomic_fetch_add((float*)p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 __device__ __forceinline__ float sv_addf(const ItemCtx& c, uint32_t vloc, float x) {
-    float* p = (float*)slot(c, vloc);
-    if (!c.hmask) return atomicAdd(p, x);
-    return __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return at_addf(c, slot(c, vloc), x);
 }
 __device__ __forceinline__ float sv_takef(const ItemCtx& c, uint32_t vloc) {
     uint32_t* p = slot(c, vloc);
@@ -572,22 +603,25 @@ __device__ __forceinline__ void consume(ItemCtx& c, PassShared& S) {
             }
             bool act = false;
             uint32_t rv = 0;
+            int32_t idx = -1;
             if (valid) {
                 ++c.c_consumed;
+                idx = slot_index(c, vloc);
+                uint32_t* sp = slot_at(c, idx, vloc);
                 if (c.qt == Q_PPR) {
                     float mass = __uint_as_float(op.y);
-                    float nr = sv_addf(c, vloc, mass) + mass;
+                    float nr = at_addf(c, sp, mass) + mass;
                     act = ppr_active(nr, thr_of(c, op.x));
                 } else {
                     uint32_t val = op.y & ~RETAIN;
-                    uint32_t old = sv_min(c, vloc, val);
+                    uint32_t old = at_min(c, sp, val);
                     bool imp = val < old;
                     c.c_improved += imp;
                     act = imp || (op.y & RETAIN);
                     rv = (imp ? val : old) | RETAIN;
                 }
             }
-            bool win = act && tas(c.bits, vloc);
+            bool win = act && front_set(c, idx, vloc);
             push_frontier(c, S, cur, win, vloc, rv);
         }
         __syncthreads();
@@ -690,7 +724,7 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
         const uint32_t nb = extract(c, S, hi, true);
         for (uint32_t j = t; j < nb; j += NT) {
             uint32_t v = S.bv[j];
-            atomicAnd(&c.bits[v >> 5], ~(1u << (v & 31)));
+            front_clear(c, v);
             uint32_t gv = c.v0 + v;
             uint32_t r0 = c.g.rowptr[gv], r1 = c.g.rowptr[gv + 1];
             uint32_t dv = sv_get(c, v);
@@ -729,8 +763,9 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
             bool win_ = false;
             if (intra) {
                 ++c.c_intra;
-                uint32_t old = sv_min(c, ul, nd);
-                if (nd < old) { ++c.c_improved; win_ = tas(c.bits, ul); }
+                const int32_t idx = slot_index(c, ul);
+                uint32_t old = at_min(c, slot_at(c, idx, ul), nd);
+                if (nd < old) { ++c.c_improved; win_ = front_set(c, idx, ul); }
             }
             push_frontier(c, S, cur, win_, ul, nd | RETAIN);
             // sender-side pruning (the paper's walk-through of Appendix B.3):
@@ -775,7 +810,7 @@ __device__ __forceinline__ void ppr_visit(ItemCtx& c, PassShared& S, uint32_t bu
         uint32_t pushed = 0;
         for (uint32_t j = t; j < nb; j += NT) {
             uint32_t v = S.bv[j];
-            atomicAnd(&c.bits[v >> 5], ~(1u << (v & 31)));
+            front_clear(c, v);
             uint32_t gv = c.v0 + v;
             uint32_t r0 = c.g.rowptr[gv], r1 = c.g.rowptr[gv + 1];
             uint32_t deg = r1 - r0;
@@ -822,10 +857,11 @@ __device__ __forceinline__ void ppr_visit(ItemCtx& c, PassShared& S, uint32_t bu
             bool win_ = false;
             if (intra) {
                 ++c.c_intra;
-                float old = sv_addf(c, ul, share);
+                const int32_t idx = slot_index(c, ul);
+                float old = at_addf(c, slot_at(c, idx, ul), share);
                 float nr = old + share;
                 float thr = thr_of(c, u);
-                if (ppr_active(nr, thr) && !ppr_active(old, thr)) win_ = tas(c.bits, ul);
+                if (ppr_active(nr, thr) && !ppr_active(old, thr)) win_ = front_set(c, idx, ul);
             }
             push_frontier(c, S, cur, win_, ul, 0u);
             stage(S, valid && !intra, u, __float_as_uint(share));
@@ -906,7 +942,8 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
         } else {
             for (uint32_t i = t; i < c.nvp; i += NT) c.st[i] = UNLOADED;
         }
-        for (uint32_t i = t; i < (c.nvp + 31) / 32; i += NT) c.bits[i] = 0u;
+        if (!c.hmask)
+            for (uint32_t i = t; i < (c.nvp + 31) / 32; i += NT) c.bits[i] = 0u;
         if (t == 0) { S.nf = 0; S.ns = 0; S.cur = 0; }
         __syncthreads();
         uint32_t budget = 0;
@@ -925,7 +962,7 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
         if (c.hmask) {
             for (uint32_t i = t; i <= c.hmask; i += NT) {
                 uint32_t k = c.hkeys[i], x = c.st[i];
-                if (k != EMPTY_KEY && x != UNLOADED) c.gstate[c.v0 + k] = x;
+                if (k != EMPTY_KEY && x != UNLOADED) c.gstate[c.v0 + (k & ~FRONT)] = x;
             }
         } else {
             for (uint32_t i = t; i < c.nvp; i += NT) {
@@ -960,7 +997,8 @@ __device__ __forceinline__ void return_stash(const BufDev& B, PassShared& S) {
     __syncthreads();
 }
 
-// Dynamic LDS: dense slice st[vpmax] | bits, or hashed slice st[slots] | keys[slots] | bits.
+// Dynamic LDS: dense slice st[vpmax] | frontier bits, or hashed slice st[slots] | keys[slots]
+// (the frontier flags live in the keys).
 __device__ __forceinline__ void init_ctx(ItemCtx& c, const GraphDev& g, const QueryDev& Q, const BufDev& B,
                                          uint32_t* dyn, uint32_t slice_words, uint32_t hash_slots) {
     c.g = g;
@@ -969,7 +1007,7 @@ __device__ __forceinline__ void init_ctx(ItemCtx& c, const GraphDev& g, const Qu
     c.st = dyn;
     c.hmask = hash_slots ? hash_slots - 1 : 0u;
     c.hkeys = dyn + hash_slots;
-    c.bits = hash_slots ? dyn + 2 * hash_slots : dyn + slice_words;
+    c.bits = hash_slots ? nullptr : dyn + slice_words;
     c.c_edges = c.c_intra = c.c_improved = c.c_emitted = c.c_consumed = c.c_vpush = c.c_chunks = c.c_pruned = 0;
 }
 
@@ -1026,7 +1064,7 @@ __global__ __launch_bounds__(NT) void k_persistent(GraphDev g, QueryDev Q, BufDe
     const uint32_t t = threadIdx.x;
     if (t == 0) S.nstash = 0;
     __syncthreads();
-    const uint32_t dyn_words = (hash_slots ? 2 * hash_slots : slice_words) + (slice_words + 31) / 32;
+    const uint32_t dyn_words = hash_slots ? 2 * hash_slots : slice_words + (slice_words + 31) / 32;
     for (uint32_t pass = 0; pass < max_passes; ++pass) {
         // partition summaries from the buffers: per-query windows, then per partition
         for (uint32_t q = blockIdx.x * NT + t; q < Q.nq; q += gridDim.x * NT) qmin_one(B, Q, g.np, q);
@@ -1072,7 +1110,7 @@ __global__ __launch_bounds__(NT) void k_persistent(GraphDev g, QueryDev Q, BufDe
 }
 
 size_t process_dyn_lds(uint32_t vpmax, uint32_t hash_slots) {
-    return ((size_t)(hash_slots ? 2 * hash_slots : vpmax) + (vpmax + 31) / 32) * 4;
+    return (hash_slots ? 2 * (size_t)hash_slots : (size_t)vpmax + (vpmax + 31) / 32) * 4;
 }
 
 hipError_t launch_process(const GraphDev& g, const QueryDev& Q, const BufDev& B, const PassCfg& cfg,
