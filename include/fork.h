@@ -96,8 +96,8 @@ typedef struct {
                                   (0 = auto)                                     */
     uint32_t slice_slots;      /* LDS copy of a visited partition's query state:
                                   0 = dense (one word per partition vertex);
-                                  else a hash table of this many slots (power of
-                                  two, 256..16384) holding only the vertices the
+                                  else a hash table of this many slots (a
+                                  multiple of 256, 256..16384) holding only the vertices the
                                   visit touches, so more workgroups fit per CU;
                                   vertices that find no free slot are updated in
                                   place in global memory.  Partitions too large

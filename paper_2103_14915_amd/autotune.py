@@ -102,7 +102,7 @@ def candidates(g, queries) -> dict:
         "partition_vertices": [8192, 16384, 32768, 65536],
         "items_per_pass": [0, 2048, 16384, 65536],
         "persistent": [0, 1],
-        "slice_slots": [0, 1024, 2048, 4096],
+        "slice_slots": [0, 1024, 2048, 2560, 4096],
     }
     if kinds & {"sssp", "bfs"}:
         w = max(1, int(round(wmean)))

@@ -142,7 +142,7 @@ struct ItemCtx {
     float* gp;          // PPR p
     uint32_t* st;       // LDS slice: values by vertex (dense) or by hash slot
     uint32_t* hkeys;    // hashed slice: vertex of each slot (EMPTY_KEY if free)
-    uint32_t hmask;     // hashed slice: slots - 1 (0: dense slice)
+    uint32_t hn;        // hashed slice: number of slots (0: dense slice)
     uint32_t* bits;     // LDS in-frontier flags (by vertex)
     // per-thread counters
     unsigned long long c_edges, c_intra, c_improved, c_emitted, c_consumed, c_vpush, c_chunks, c_pruned;
@@ -174,14 +174,14 @@ constexpr uint32_t FRONT = 0x80000000u;
 // LDS index of vertex vloc's value for this visit (claimed on first touch), or
 // -1 when it stays in global memory.
 __device__ __forceinline__ int32_t slot_index(const ItemCtx& c, uint32_t vloc) {
-    if (!c.hmask) return (int32_t)vloc;
+    if (!c.hn) return (int32_t)vloc;
     // Fibonacci hashing: the top bits of vloc * 2^32/phi pick the home slot
-    uint32_t h = (uint32_t)(((unsigned long long)(vloc * 0x9E3779B1u) * (c.hmask + 1ull)) >> 32);
+    uint32_t h = (uint32_t)(((unsigned long long)(vloc * 0x9E3779B1u) * c.hn) >> 32);
     for (int i = 0; i < MAXPROBE; ++i) {
         uint32_t k = c.hkeys[h];
         if (k == EMPTY_KEY) k = atomicCAS(&c.hkeys[h], EMPTY_KEY, vloc);
         if (k == EMPTY_KEY || (k & ~FRONT) == vloc) return (int32_t)h;
-        h = (h + 1) & c.hmask;
+        h = h + 1 == c.hn ? 0u : h + 1;
     }
     return -1;
 }
@@ -199,12 +199,12 @@ __device__ __forceinline__ uint32_t* slot(const ItemCtx& c, uint32_t vloc) {
 
 // Frontier flag of vertex vloc (slot idx): set it, returning whether it was clear.
 __device__ __forceinline__ bool front_set(const ItemCtx& c, int32_t idx, uint32_t vloc) {
-    if (!c.hmask) return tas(c.bits, vloc);
+    if (!c.hn) return tas(c.bits, vloc);
     if (idx < 0) return true;
     return !(atomicOr(&c.hkeys[idx], FRONT) & FRONT);
 }
 __device__ __forceinline__ void front_clear(const ItemCtx& c, uint32_t vloc) {
-    if (!c.hmask) {
+    if (!c.hn) {
         atomicAnd(&c.bits[vloc >> 5], ~(1u << (vloc & 31)));
         return;
     }
@@ -215,15 +215,15 @@ __device__ __forceinline__ void front_clear(const ItemCtx& c, uint32_t vloc) {
 // Value reads and updates through a slot: LDS instructions for the dense
 // slice, flat (LDS or L2) atomics for the hashed one.
 __device__ __forceinline__ uint32_t sv_get(const ItemCtx& c, uint32_t vloc) {
-    if (!c.hmask) return c.st[vloc];
+    if (!c.hn) return c.st[vloc];
     return __hip_atomic_load(slot(c, vloc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ uint32_t at_min(const ItemCtx& c, uint32_t* p, uint32_t x) {
-    if (!c.hmask) return atomicMin(p, x);
+    if (!c.hn) return atomicMin(p, x);
     return __hip_atomic_fetch_min(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ float at_addf(const ItemCtx& c, uint32_t* p, float x) {
-    if (!c.hmask) return atomicAdd((float*)p, x);
+    if (!c.hn) return atomicAdd((float*)p, x);
     return __hip_atomic_fetch_add((float*)p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ float sv_addf(const ItemCtx& c, uint32_t vloc, float x) {
@@ -231,7 +231,7 @@ __device__ __forceinline__ float sv_addf(const ItemCtx& c, uint32_t vloc, float 
 }
 __device__ __forceinline__ float sv_takef(const ItemCtx& c, uint32_t vloc) {
     uint32_t* p = slot(c, vloc);
-    if (!c.hmask) { uint32_t m = *p; *p = 0u; return __uint_as_float(m); }
+    if (!c.hn) { uint32_t m = *p; *p = 0u; return __uint_as_float(m); }
     return __uint_as_float(__hip_atomic_exchange(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
 }
 __device__ __forceinline__ void sv_putf(const ItemCtx& c, uint32_t vloc, float x) {
@@ -937,12 +937,12 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
         c.it_useful = 0.f;
         c.it_work = 0.f;
         // the slice is staged into LDS on first touch
-        if (c.hmask) {
-            for (uint32_t i = t; i <= c.hmask; i += NT) { c.st[i] = UNLOADED; c.hkeys[i] = EMPTY_KEY; }
+        if (c.hn) {
+            for (uint32_t i = t; i < c.hn; i += NT) { c.st[i] = UNLOADED; c.hkeys[i] = EMPTY_KEY; }
         } else {
             for (uint32_t i = t; i < c.nvp; i += NT) c.st[i] = UNLOADED;
         }
-        if (!c.hmask)
+        if (!c.hn)
             for (uint32_t i = t; i < (c.nvp + 31) / 32; i += NT) c.bits[i] = 0u;
         if (t == 0) { S.nf = 0; S.ns = 0; S.cur = 0; }
         __syncthreads();
@@ -959,8 +959,8 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
         else sp_visit<WB>(c, S, cfg.win_sp, cfg.yld_sp, budget);
         flush(c, S);
         // write the touched part of the slice back
-        if (c.hmask) {
-            for (uint32_t i = t; i <= c.hmask; i += NT) {
+        if (c.hn) {
+            for (uint32_t i = t; i < c.hn; i += NT) {
                 uint32_t k = c.hkeys[i], x = c.st[i];
                 if (k != EMPTY_KEY && x != UNLOADED) c.gstate[c.v0 + (k & ~FRONT)] = x;
             }
@@ -1005,7 +1005,7 @@ __device__ __forceinline__ void init_ctx(ItemCtx& c, const GraphDev& g, const Qu
     c.Q = Q;
     c.B = B;
     c.st = dyn;
-    c.hmask = hash_slots ? hash_slots - 1 : 0u;
+    c.hn = hash_slots;
     c.hkeys = dyn + hash_slots;
     c.bits = hash_slots ? nullptr : dyn + slice_words;
     c.c_edges = c.c_intra = c.c_improved = c.c_emitted = c.c_consumed = c.c_vpush = c.c_chunks = c.c_pruned = 0;

@@ -720,8 +720,8 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     if (opts) o = *opts;
     if (o.scheduler < 0 || o.scheduler > FORK_SCHED_MAXOPS) return fail(FORK_E_INVALID, "bad scheduler %d", o.scheduler);
     if (o.scheduler == FORK_SCHED_LEARNED && !o.mlp_weights) return fail(FORK_E_INVALID, "LEARNED needs mlp_weights");
-    if (o.slice_slots && (o.slice_slots < 256 || o.slice_slots > 16384 || (o.slice_slots & (o.slice_slots - 1))))
-        return fail(FORK_E_INVALID, "slice_slots must be 0 or a power of two in [256, 16384], got %u", o.slice_slots);
+    if (o.slice_slots && (o.slice_slots < 256 || o.slice_slots > 16384 || (o.slice_slots % 256)))
+        return fail(FORK_E_INVALID, "slice_slots must be 0 or a multiple of 256 in [256, 16384], got %u", o.slice_slots);
     if (hipSetDevice(c->device) != hipSuccess) return fail(FORK_E_DEVICE, "hipSetDevice failed");
     {
         // a table with at least half as many slots as the largest partition has

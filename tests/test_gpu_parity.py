@@ -298,10 +298,12 @@ def test_hashed_slice_grid_and_bad_slots():
     fg = fork.ForkGraph.from_graph(g, partition_vertices=4096)
     fg.submit("sssp", s1)
     with pytest.raises(fork.ForkError) as e:
-        fg.run(slice_slots=300)                         # not a power of two
+        fg.run(slice_slots=300)                         # not a multiple of 256
     assert e.value.code == fork.FORK_E_INVALID
     say("hashed slice grid")
     fg.run(slice_slots=512, max_passes=1000000)
+    np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(32)]), oracle.sssp(g, s1))
+    fg.run(slice_slots=768, max_passes=1000000)          # a table size that is not a power of two
     np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(32)]), oracle.sssp(g, s1))
     fg.run(slice_slots=0, max_passes=1000000)           # back to the dense slice in the same context
     np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(32)]), oracle.sssp(g, s1))
