@@ -58,7 +58,25 @@ def measured_traffic(workload: str, root: str = ""):
     return blob
 
 
-def cpu_baseline(g, queries, spec, budget_s=15.0):
+def certified_push(oracle, g, batch, alpha, eps, mode, target, threads):
+    """The L1-certified mode on the CPU: the oracle's forward push, restarted
+    with the GPU path's threshold rule until every query's ||r||_1 <= 0.9 * target."""
+    eps = np.full(len(batch), float(eps))
+    todo = np.arange(len(batch))
+    while todo.size:
+        left = []
+        for e in np.unique(eps[todo]):
+            sel = todo[eps[todo] == e]
+            _, r = oracle.forward_push(g, batch[sel], alpha, e, mode, threads)
+            r1 = r.sum(1)
+            for k, q in enumerate(sel):
+                if r1[k] > 0.9 * target:
+                    eps[q] *= min(0.5, max(1e-3, 0.5 * 0.9 * target / r1[k]))
+                    left.append(q)
+        todo = np.asarray(left, np.int64)
+
+
+def cpu_baseline(g, queries, spec, budget_s=15.0, l1_target=0.0):
     """The CPU oracle, untuned, one query per thread over all host cores."""
     import oracle
     threads = os.cpu_count() or 1
@@ -70,7 +88,10 @@ def cpu_baseline(g, queries, spec, budget_s=15.0):
         for qt, s in kinds:
             batch = rng.choice(s, size=min(threads, len(s)), replace=False)
             t0 = time.perf_counter()
-            if qt == "ppr":
+            if qt == "ppr" and l1_target > 0:
+                certified_push(oracle, g, batch, spec.get("alpha", 0.15), spec.get("epsilon", 1e-6),
+                               spec.get("eps_mode", 0), l1_target, threads)
+            elif qt == "ppr":
                 oracle.forward_push(g, batch, spec.get("alpha", 0.15), spec.get("epsilon", 1e-6),
                                     spec.get("eps_mode", 0), threads)
             elif qt == "bfs":
@@ -82,7 +103,9 @@ def cpu_baseline(g, queries, spec, budget_s=15.0):
             samples.append(f"{len(batch)} {qt}")
     return {"value": done / t_total, "unit": "queries/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} queries ({', '.join(sorted(set(samples)))} per batch) of the same workload, "
-                      f"{t_total:.1f} s, fp64 forward push / Dijkstra / BFS, one query per thread"}
+                      f"{t_total:.1f} s, fp64 forward push / Dijkstra / BFS, one query per thread"
+                      + (f"; PPR certified to L1 {l1_target:g} by restarted pushes at lower thresholds"
+                         if l1_target > 0 else "")}
 
 
 def compare_learned(fg, args, run_kw, nq, rule_value):
@@ -126,6 +149,8 @@ def main():
     ap.add_argument("--scale", type=int, default=0, help="experiment: override the R-MAT scale")
     ap.add_argument("--queries", type=int, default=0, help="experiment: use only the first N queries per type")
     ap.add_argument("--max-queries", type=int, default=0, help="queries resident per wave (0 = auto)")
+    ap.add_argument("--l1-target", type=float, default=0.0,
+                    help="PPR queries in the L1-certified mode with this target (0 = plain push at epsilon)")
     ap.add_argument("--pool-mb", type=int, default=0, help="device memory for buffered operations (0 = auto)")
     ap.add_argument("--persistent", action="store_true", help="one persistent cooperative kernel per batch of passes")
     ap.add_argument("--items-per-pass", type=int, default=0, help="work items queued per pass (0 = auto)")
@@ -197,7 +222,7 @@ def main():
     nq = 0
     for qt, s in queries:
         fg.submit(qt, s, alpha=spec.get("alpha", 0.15), epsilon=spec.get("epsilon", 1e-6),
-                  eps_mode=spec.get("eps_mode", 0))
+                  eps_mode=spec.get("eps_mode", 0), l1_target=args.l1_target)
         nq += len(s)
     kinds = sorted({qt for qt, _ in queries})
     kind = kinds[0] if len(kinds) == 1 else "mixed"
@@ -221,7 +246,7 @@ def main():
         tot[k] = st[k]
     value = nq * args.steps / dt
     abytes = algorithmic_bytes(tot, kind if kind != "mixed" else "sssp")
-    prof = measured_traffic(args.workload) if not (args.scale or args.queries) else None
+    prof = measured_traffic(args.workload) if not (args.scale or args.queries or args.l1_target) else None
     launches = max(1, tot["process_launches"])
     avg_ms = tot["process_ms"] / launches
     achieved = (abytes / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -239,7 +264,8 @@ def main():
         "dtype": "f32" if "ppr" in kinds else "int32",
         "data": "synthetic",
         "config": {"workload": args.workload + (f"@scale{args.scale}" if args.scale else "")
-                   + (f"@q{args.queries}" if args.queries else ""), "queries": nq, "types": kinds, "vertices": g.num_vertices,
+                   + (f"@q{args.queries}" if args.queries else "")
+                   + (f"+l1cert{args.l1_target:g}" if args.l1_target > 0 else ""), "queries": nq, "types": kinds, "vertices": g.num_vertices,
                    "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler, "knobs": params, "knobs_source": source,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -261,12 +287,13 @@ def main():
                    "ops_emitted_per_step": tot["ops_emitted"] / args.steps,
                    "ops_pruned_per_step": tot["pruned"] / args.steps,
                    "vertex_pushes_per_step": tot["vertex_pushes"] / args.steps,
-                   "work_items_per_step": tot["work_items"] / args.steps},
+                   "work_items_per_step": tot["work_items"] / args.steps,
+                   "refine_rounds_per_step": tot["refine_rounds"] / args.steps},
     }
     if args.compare_learned:
         line["learned_vs_rule"] = compare_learned(fg, args, run_kw, nq, value)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(g, queries, spec, args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(g, queries, spec, args.cpu_budget, args.l1_target)
     fg.close()
     print(json.dumps(line), flush=True)
 

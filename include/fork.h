@@ -66,11 +66,24 @@ typedef struct {
 
 /* PPR parameters (passed to fork_submit for FORK_PPR).  A vertex is pushed
  * while r[v] > 0 and r[v] >= thr(v), thr(v) = epsilon (eps_mode 0) or
- * epsilon * outdeg(v) (eps_mode 1). */
+ * epsilon * outdeg(v) (eps_mode 1).
+ *
+ * l1_target > 0 asks for a certified result: after the push terminates at
+ * epsilon, the run lowers this query's threshold and pushes again (from every
+ * vertex that then qualifies) until sum_v r[v] <= 0.9 * l1_target.  Forward
+ * push keeps p + PPR(r) = PPR(e_s) (Section 4.1's push; the paper gives no
+ * formula), and ||PPR(r)||_1 <= ||r||_1, so the returned p is then within
+ * l1_target of the exact PPR vector in L1, the last tenth being left for
+ * fp32 rounding.  The cost grows as the threshold falls; after 32 reductions
+ * fork_run gives FORK_E_NOT_CONVERGED.  Certified queries need partitions of
+ * at most 1,024 vertices (fork_config.partition_vertices <= 1024), so that a
+ * refinement's re-activated vertices always fit the visit's frontier;
+ * fork_run gives FORK_E_INVALID, and runs nothing, for larger partitions. */
 typedef struct {
-    float alpha;    /* teleport probability, in (0, 1) */
-    float epsilon;  /* push threshold, > 0             */
-    int   eps_mode; /* 0 = absolute, 1 = degree-scaled */
+    float alpha;     /* teleport probability, in (0, 1)        */
+    float epsilon;   /* push threshold, > 0                    */
+    int   eps_mode;  /* 0 = absolute, 1 = degree-scaled        */
+    float l1_target; /* 0 = off; else the certified L1 bound   */
 } fork_ppr_params;
 
 /* Per-run options.  NULL = defaults (PRIORITY, automatic tuning, stream 0). */
@@ -126,6 +139,8 @@ typedef struct {
     uint64_t pruned;           /* operations not sent: target already as short */
     uint32_t num_partitions;
     uint32_t weight_bytes;     /* bytes per stored edge weight (0 = none)   */
+    uint64_t refine_rounds;    /* certified-PPR threshold reductions, summed
+                                  over waves                                */
 } fork_stats_t;
 
 /* Per-query digest (fork_fetch field FORK_FIELD_DIGEST).  For SSSP/BFS:

@@ -44,7 +44,8 @@ class fork_config(ctypes.Structure):
 
 
 class fork_ppr_params(ctypes.Structure):
-    _fields_ = [("alpha", ctypes.c_float), ("epsilon", ctypes.c_float), ("eps_mode", ctypes.c_int)]
+    _fields_ = [("alpha", ctypes.c_float), ("epsilon", ctypes.c_float), ("eps_mode", ctypes.c_int),
+                ("l1_target", ctypes.c_float)]
 
 
 class fork_run_opts(ctypes.Structure):
@@ -62,7 +63,7 @@ class fork_stats_t(ctypes.Structure):
                [("init_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("digest_ms", ctypes.c_double),
                 ("process_ms", ctypes.c_double), ("process_launches", ctypes.c_uint64),
                 ("intra_edges", ctypes.c_uint64), ("pruned", ctypes.c_uint64), ("num_partitions", ctypes.c_uint32),
-                ("weight_bytes", ctypes.c_uint32)]
+                ("weight_bytes", ctypes.c_uint32), ("refine_rounds", ctypes.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -166,12 +167,12 @@ class ForkGraph:
         _check(lib.fork_partitions(self._ctx, ctypes.c_void_p(out.ctypes.data), n.value, ctypes.byref(n)))
         return out
 
-    def submit(self, qtype, sources, alpha=0.15, epsilon=1e-6, eps_mode=0) -> int:
+    def submit(self, qtype, sources, alpha=0.15, epsilon=1e-6, eps_mode=0, l1_target=0.0) -> int:
         t = QTYPES[qtype] if isinstance(qtype, str) else int(qtype)
         src = np.ascontiguousarray(np.asarray(sources), np.uint32)
         params = None
         if t == PPR:
-            params = ctypes.byref(fork_ppr_params(alpha, epsilon, eps_mode))
+            params = ctypes.byref(fork_ppr_params(alpha, epsilon, eps_mode, l1_target))
         first = ctypes.c_uint32()
         _check(lib.fork_submit(self._ctx, t, ctypes.c_void_p(src.ctypes.data), src.size, params,
                                ctypes.byref(first)))

@@ -14,6 +14,10 @@ constexpr int NXCD = 8;                   // MI355X: 8 XCDs of 32 CUs
 constexpr uint32_t VPMAX = 16384;         // default vertices per partition (the dense LDS slice fits)
 constexpr uint32_t PVMAX = 65536;         // max vertices per partition (hashed LDS slice)
 constexpr uint32_t HS_AUTO = 4096;        // hash slots when the dense slice does not fit
+// Largest partition (vertices) for L1-certified PPR queries: at most the
+// visit's frontier capacity, so a refinement's re-activations always fit the
+// frontier and are never spilled back into the buffers.
+constexpr uint32_t CERT_MAX_PART = 1024;
 constexpr int MLP_IN = 16, MLP_H = 64;
 constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;  // 5313
 
@@ -53,6 +57,10 @@ struct alignas(16) Item {
     uint2 ch[ICH];   // (chunk id, valid ops)
 };
 static_assert(sizeof(Item) == 128, "work item layout");
+// Item::rest of a refinement item (certified PPR): no buffered operations;
+// the visit starts from every vertex of the partition whose residual
+// reaches the query's current threshold.
+constexpr int32_t RESCAN = -2;
 
 struct GraphDev {
     uint32_t nv, np, pshift, wbytes;

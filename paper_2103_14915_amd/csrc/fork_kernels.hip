@@ -120,6 +120,57 @@ __global__ __launch_bounds__(256) void k_digest(QueryDev Q, uint32_t nv, unsigne
     }
 }
 
+// ------------------------------------------------------------ certified PPR
+// Residual mass ||r||_1 of each listed PPR query, in fp64 (one block per
+// query).  It bounds the L1 distance of p from the PPR vector, since that
+// distance is ||PPR(r)||_1 <= ||r||_1 by the push invariant.
+__global__ __launch_bounds__(256) void k_rnorm(QueryDev Q, uint32_t nv, const uint32_t* qs, uint32_t n, double* out) {
+    const uint32_t i = blockIdx.x;
+    if (i >= n) return;
+    const uint32_t q = qs[i];
+    __shared__ double s_f;
+    if (threadIdx.x == 0) s_f = 0;
+    __syncthreads();
+    double f = 0;
+    if (q < Q.nq && Q.qtype[q] == Q_PPR) {
+        const float* r = (const float*)(Q.state + Q.qoff[q]) + nv;
+        for (uint32_t v = threadIdx.x; v < nv; v += blockDim.x) f += r[v];
+    }
+#pragma unroll
+    for (int o = 32; o; o >>= 1) f += __shfl_xor(f, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&s_f, f);
+    __syncthreads();
+    if (threadIdx.x == 0) out[i] = s_f;
+}
+
+// Opens a refinement pass: work items for the (partition, query) pairs
+// lo .. lo+n-1 of the np x |qs| grid (pair i = j*np + P, query qs[j]), each
+// marked RESCAN, dealt round-robin over the per-XCD lists.  Also does what
+// k_select does for a pass: the pass number, the pool bound, the list heads
+// and the items per partition (approximate here; it only sizes yield
+// heuristic 1's edge budget).
+__global__ __launch_bounds__(256) void k_rescan_items(BufDev B, uint32_t np, const uint32_t* qs,
+                                                      unsigned long long lo, uint32_t n) {
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k < n) {
+        const unsigned long long i = lo + k;
+        Item* it = &B.items[(unsigned long long)(k % NXCD) * B.item_cap + k / NXCD];
+        it->part = (uint32_t)(i % np);
+        it->q = qs[i / np];
+        it->rest = RESCAN;
+        it->nch = 0;
+    }
+    if (k < np) B.pn[k] = (n + np - 1) / np;
+    if (blockIdx.x == 0 && threadIdx.x < NXCD) {
+        B.ctl->nitems[threadIdx.x] = (n + NXCD - 1 - threadIdx.x) / NXCD;
+        B.ctl->next[threadIdx.x] = 0;
+    }
+    if (k == 0) {
+        B.ctl->pass += 1;
+        B.ctl->avail_end = B.ctl->ring_tail;
+    }
+}
+
 }  // namespace fk
 
 // ------------------------------------------------------------ launchers
@@ -148,6 +199,20 @@ hipError_t launch_ring_init(uint32_t* ring, unsigned long long nch, hipStream_t 
 }
 hipError_t launch_seed(const GraphDev& g, const QueryDev& Q, const BufDev& B, const uint32_t* src, hipStream_t s) {
     hipLaunchKernelGGL(k_seed, dim3((Q.nq + 255) / 256), dim3(256), 0, s, g, Q, B, src);
+    return hipGetLastError();
+}
+hipError_t launch_rnorm(const QueryDev& Q, uint32_t nv, const uint32_t* qs, uint32_t n, double* out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rnorm, dim3(n), dim3(256), 0, s, Q, nv, qs, n, out);
+    return hipGetLastError();
+}
+// n pairs starting at lo; the caller keeps n <= NXCD * item_cap and
+// lo + n <= np * |qs|.
+hipError_t launch_rescan_items(const BufDev& B, uint32_t np, const uint32_t* qs, unsigned long long lo, uint32_t n,
+                               hipStream_t s) {
+    if (n == 0 || n > (unsigned long long)NXCD * B.item_cap) return hipErrorInvalidValue;
+    const uint32_t m = n > np ? n : np;
+    hipLaunchKernelGGL(k_rescan_items, dim3((m + 255) / 256), dim3(256), 0, s, B, np, qs, lo, n);
     return hipGetLastError();
 }
 hipError_t launch_digest(const QueryDev& Q, uint32_t nv, unsigned long long* out, hipStream_t s) {

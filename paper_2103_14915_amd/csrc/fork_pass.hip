@@ -32,6 +32,7 @@ namespace fk {
 constexpr int NT = 256;           // threads per workgroup
 constexpr int NW = NT / WAVE;     // waves per workgroup
 constexpr int FCAP = 1024;        // frontier capacity (two buffers)
+static_assert((uint32_t)FCAP >= CERT_MAX_PART, "a certified refinement fits the frontier");
 constexpr int BCAP = 512;         // vertices expanded per batch
 constexpr int SCAP = 512;         // staged outgoing operations
 constexpr int CCAP = 128;         // chunk ids gathered per consume round
@@ -643,6 +644,31 @@ __device__ __forceinline__ void consume(ItemCtx& c, PassShared& S) {
     __syncthreads();
 }
 
+// Refinement item of a certified PPR query (the threshold was lowered after
+// the query terminated): re-activate every vertex of the partition whose
+// residual reaches the new threshold, exactly as a zero-mass operation to it
+// would, so the visit that follows pushes them (Section 4.1's push).
+__device__ __forceinline__ void rescan(ItemCtx& c, PassShared& S) {
+    const uint32_t t = threadIdx.x;
+    for (uint32_t i0 = 0; i0 < c.nvp; i0 += NT) {
+        stage_room(c, S);
+        const uint32_t cur = S.cur;
+        const uint32_t vloc = i0 + t;
+        bool act = false;
+        int32_t idx = -1;
+        if (vloc < c.nvp && ppr_active(__uint_as_float(c.gstate[c.v0 + vloc]), thr_of(c, c.v0 + vloc))) {
+            idx = slot_index(c, vloc);
+            slot_at(c, idx, vloc);  // stage the residual into the slice
+            act = true;
+        }
+        bool win = act && front_set(c, idx, vloc);
+        push_frontier(c, S, cur, win, vloc, 0u);
+    }
+    __syncthreads();
+    if (t == 0 && S.nf > (uint32_t)FCAP) S.nf = FCAP;
+    __syncthreads();
+}
+
 // Split the frontier: vertices with value < hi (all for PPR) go to the
 // batch (up to BCAP), the rest stay in the other frontier buffer.
 __device__ __forceinline__ uint32_t extract(ItemCtx& c, PassShared& S, uint32_t hi, bool by_value) {
@@ -740,24 +766,27 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
         if (t == 0) c.c_vpush += nb;
         const uint32_t total = batch_scan(S, nb);
         edges += total;
-        // edge j's target and tentative distance; each step loads the next
-        // step's edge ahead, so its latency overlaps this step
-        auto load_edge = [&](uint32_t j, uint32_t& u, uint32_t& nd) {
+        // edge j's target, tentative distance and, for a target outside the
+        // partition, its stored distance (for pruning).  Each step loads the
+        // next step's edge ahead, so its latency overlaps this step.
+        auto load_edge = [&](uint32_t j, uint32_t& u, uint32_t& nd, uint32_t& du) {
             uint32_t b = find_b(S, nb, j);
             uint32_t e = S.brow[b] + (j - S.bpre[b]);
             u = c.g.col[e];
             unsigned long long sum = (unsigned long long)S.bval[b] + edge_w<WB>(c.g.w, e);
             nd = sum >= INF ? INF - 1 : (uint32_t)sum;
+            du = u - c.v0 >= c.nvp ? c.gstate[u] : 0xffffffffu;
         };
-        uint32_t u_ahead = 0, nd_ahead = 0;
-        if (t < total) load_edge(t, u_ahead, nd_ahead);
+        uint32_t u_ahead = 0, nd_ahead = 0, du_ahead = 0xffffffffu;
+        if (t < total) load_edge(t, u_ahead, nd_ahead, du_ahead);
         for (uint32_t k0 = 0; k0 < total; k0 += NT) {
             stage_room(c, S);
             const uint32_t cur = S.cur;
             uint32_t j = k0 + t;
             bool valid = j < total;
             uint32_t u = valid ? u_ahead : 0u, nd = valid ? nd_ahead : 0u;
-            if (j + NT < total) load_edge(j + NT, u_ahead, nd_ahead);
+            const uint32_t du = du_ahead;
+            if (j + NT < total) load_edge(j + NT, u_ahead, nd_ahead, du_ahead);
             uint32_t ul = u - c.v0;
             bool intra = valid && ul < c.nvp;
             bool win_ = false;
@@ -770,10 +799,11 @@ __device__ __forceinline__ void sp_visit(ItemCtx& c, PassShared& S, uint32_t win
             push_frontier(c, S, cur, win_, ul, nd | RETAIN);
             // sender-side pruning (the paper's walk-through of Appendix B.3):
             // no operation is sent when the target already has a path at
-            // least as short.  The stored distance can only be stale-high
-            // (distances only decrease), so pruning never drops useful work.
+            // least as short.  The stored distance, read one step early, can
+            // only be stale-high (distances only decrease), so pruning never
+            // drops useful work.
             bool send = valid && !intra;
-            if (send && nd >= c.gstate[u]) { send = false; ++c.c_pruned; }
+            if (send && nd >= du) { send = false; ++c.c_pruned; }
             stage(S, send, u, nd);
         }
         __syncthreads();
@@ -953,7 +983,8 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
             float bgt = cfg.mu * e_p / (float)(np_items ? np_items : 1u);
             budget = bgt < 256.f ? 256u : (bgt > 4.0e9f ? 4000000000u : (uint32_t)bgt);
         }
-        consume(c, S);
+        if (S.it.rest != RESCAN) consume(c, S);
+        else if (ppr) rescan(c, S);
         if (ppr) ppr_visit(c, S, budget);
         else if (c.qt == Q_BFS) sp_visit<0>(c, S, cfg.win_lv, cfg.yld_lv, budget);
         else sp_visit<WB>(c, S, cfg.win_sp, cfg.yld_sp, budget);

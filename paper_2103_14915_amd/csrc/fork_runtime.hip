@@ -28,6 +28,8 @@ hipError_t launch_ring_init(uint32_t*, unsigned long long, hipStream_t);
 hipError_t launch_fill64(unsigned long long*, unsigned long long, unsigned long long, hipStream_t);
 hipError_t launch_seed(const GraphDev&, const QueryDev&, const BufDev&, const uint32_t*, hipStream_t);
 hipError_t launch_digest(const QueryDev&, uint32_t, unsigned long long*, hipStream_t);
+hipError_t launch_rnorm(const QueryDev&, uint32_t, const uint32_t*, uint32_t, double*, hipStream_t);
+hipError_t launch_rescan_items(const BufDev&, uint32_t, const uint32_t*, unsigned long long, uint32_t, hipStream_t);
 hipError_t launch_mlp_score(const GraphDev&, const BufDev&, const float*, float*, float*, void*, uint32_t, hipStream_t);
 size_t gstat_bytes();
 hipError_t launch_mlp_grad(const float*, const float*, const float*, const uint32_t*, uint32_t, float*, float*,
@@ -64,6 +66,7 @@ static int fail(int code, const char* fmt, ...) {
 struct QueryRec {
     uint32_t type, src, mode;
     float alpha, eps;
+    float l1 = 0.f;  // PPR: certified L1 target (0 = off)
 };
 
 struct fork_ctx {
@@ -117,6 +120,8 @@ struct fork_ctx {
     unsigned long long* d_qoff = nullptr;
     float *d_qalpha = nullptr, *d_qeps = nullptr;
     unsigned long long* d_digest = nullptr;
+    uint32_t* d_certq = nullptr;   // [qcap] certified PPR queries still above their target
+    double* d_rnorm = nullptr;     // [qcap] their residual mass
     // results
     std::vector<fork_digest> digests;
     bool ran = false;
@@ -168,6 +173,8 @@ static void free_wave(fork_ctx* c) {
     hipFree(c->d_qalpha); c->d_qalpha = nullptr;
     hipFree(c->d_qeps); c->d_qeps = nullptr;
     hipFree(c->d_digest); c->d_digest = nullptr;
+    hipFree(c->d_certq); c->d_certq = nullptr;
+    hipFree(c->d_rnorm); c->d_rnorm = nullptr;
     c->qcap = 0;
     c->state_words_cap = 0;
     c->kmax_cap = 0;
@@ -396,9 +403,12 @@ extern "C" int fork_submit(fork_ctx* c, int type, const uint32_t* sources, uint3
         if (!(pp->alpha > 0.f && pp->alpha < 1.f)) return fail(FORK_E_INVALID, "alpha must be in (0,1)");
         if (!(pp->epsilon > 0.f)) return fail(FORK_E_INVALID, "epsilon must be > 0");
         if (pp->eps_mode != 0 && pp->eps_mode != 1) return fail(FORK_E_INVALID, "eps_mode must be 0 or 1");
+        if (!(pp->l1_target >= 0.f && pp->l1_target <= 1e30f))
+            return fail(FORK_E_INVALID, "l1_target must be finite and >= 0");
         base.alpha = pp->alpha;
         base.eps = pp->epsilon;
         base.mode = (uint32_t)pp->eps_mode;
+        base.l1 = pp->l1_target;
     }
     for (uint32_t i = 0; i < n; ++i)
         if (sources[i] >= c->nv) return fail(FORK_E_INVALID, "source %u out of range (V=%u)", sources[i], c->nv);
@@ -429,6 +439,8 @@ static int ensure_wave(fork_ctx* c, uint32_t nq, size_t words, uint32_t kmax) {
         c->d_bval = c->d_bcnt = c->d_bfirst = c->d_qmin = nullptr;
         hipFree(c->d_qtype); hipFree(c->d_qsrc); hipFree(c->d_qmode); hipFree(c->d_qoff);
         hipFree(c->d_qalpha); hipFree(c->d_qeps); hipFree(c->d_digest);
+        hipFree(c->d_certq); hipFree(c->d_rnorm);
+        c->d_certq = nullptr; c->d_rnorm = nullptr;
         c->d_bhead = nullptr; c->d_btw = nullptr; c->d_bover = nullptr; c->d_items = nullptr;
         uint32_t qc = std::max(nq, c->qcap);
         uint32_t kc = std::max(kmax, c->kmax_cap);
@@ -449,6 +461,8 @@ static int ensure_wave(fork_ctx* c, uint32_t nq, size_t words, uint32_t kmax) {
         if ((rc = dalloc(&c->d_qalpha, qc))) return rc;
         if ((rc = dalloc(&c->d_qeps, qc))) return rc;
         if ((rc = dalloc(&c->d_digest, (size_t)qc * 6))) return rc;
+        if ((rc = dalloc(&c->d_certq, qc))) return rc;
+        if ((rc = dalloc(&c->d_rnorm, qc))) return rc;
         c->qcap = qc;
         c->kmax_cap = kc;
     }
@@ -586,7 +600,79 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
     const double prog_every = prog ? atof(prog) : 0.0;  // seconds between progress lines (0 = off)
     auto t_start = std::chrono::steady_clock::now();
     auto t_last = t_start;
-    while (!done) {
+    // L1-certified PPR queries (wave-local ids).  Once the wave has drained,
+    // a query whose residual mass ||r||_1 is above 0.9 of its target gets a
+    // lower threshold and is pushed again from every vertex that now
+    // qualifies.  By the push invariant ||pi_s - p||_1 = ||PPR(r)||_1 <=
+    // ||r||_1, so the target holds with a tenth of it left for fp32 rounding.
+    std::vector<uint32_t> cert;
+    for (uint32_t i = 0; i < nq; ++i)
+        if (qt[i] == FORK_PPR && c->queries[q0 + i].l1 > 0.f) cert.push_back(i);
+    constexpr uint32_t MAX_REFINE = 32;
+    uint32_t refine_rounds = 0;
+    // returns < 0 on error, 0 when every certified query meets its target,
+    // 1 after launching the refinement passes
+    auto refine = [&]() -> int {
+        if (cert.empty()) return 0;
+        HIPCHK(hipMemcpyAsync(c->d_certq, cert.data(), cert.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(fk::launch_rnorm(Q, c->nv, c->d_certq, (uint32_t)cert.size(), c->d_rnorm, s));
+        std::vector<double> rn(cert.size());
+        HIPCHK(hipMemcpyAsync(rn.data(), c->d_rnorm, rn.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<uint32_t> above;
+        for (size_t k = 0; k < cert.size(); ++k) {
+            const uint32_t i = cert[k];
+            const double tgt = 0.9 * (double)c->queries[q0 + i].l1;
+            if (rn[k] <= tgt) continue;
+            // ||r||_1 shrinks roughly in proportion to the threshold
+            const double f = std::min(0.5, std::max(1e-3, 0.5 * tgt / rn[k]));
+            qe[i] = (float)((double)qe[i] * f);
+            if (!(qe[i] > 0.f))
+                return fail(FORK_E_NOT_CONVERGED, "query %u: threshold underflow with ||r||_1 = %g", q0 + i, rn[k]);
+            above.push_back(i);
+        }
+        cert.swap(above);
+        if (cert.empty()) return 0;
+        if (++refine_rounds > MAX_REFINE)
+            return fail(FORK_E_NOT_CONVERGED, "L1 target not met after %u threshold reductions", MAX_REFINE);
+        const unsigned long long pairs = (unsigned long long)c->np * cert.size();
+        const unsigned long long per = (unsigned long long)fk::NXCD * c->item_cap;
+        const uint64_t npass = (pairs + per - 1) / per;
+        if (passes_left != ~0ull) {
+            if (npass > passes_left) return fail(FORK_E_NOT_CONVERGED, "max_passes reached with work pending");
+            passes_left -= npass;
+        }
+        HIPCHK(hipMemcpyAsync(c->d_qeps, qe.data(), nq * 4ull, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->d_certq, cert.data(), cert.size() * 4, hipMemcpyHostToDevice, s));
+        if (o.profile && c->pev.size() < 2) {
+            c->pev.resize(2, nullptr);
+            for (auto& e : c->pev) if (!e) HIPCHK(hipEventCreate(&e));
+        }
+        for (unsigned long long lo = 0; lo < pairs; lo += per) {
+            const uint32_t n = (uint32_t)std::min(per, pairs - lo);
+            HIPCHK(fk::launch_rescan_items(B, c->np, c->d_certq, lo, n, s));
+            if (o.profile) HIPCHK(hipEventRecord(c->pev[0], s));
+            HIPCHK(fk::launch_process(g, Q, B, pc, blocks, c->vpmax, c->hslots, s));
+            if (o.profile) {
+                HIPCHK(hipEventRecord(c->pev[1], s));
+                HIPCHK(hipEventSynchronize(c->pev[1]));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, c->pev[0], c->pev[1]));
+                c->stats.process_ms += ms;
+                c->stats.process_launches += 1;
+            }
+        }
+        HIPCHK(hipStreamSynchronize(s));  // the host lists stay alive until the copies ran
+        c->stats.refine_rounds += 1;
+        return 1;
+    };
+    while (true) {
+        if (done) {
+            const int r = refine();
+            if (r < 0) return r;
+            if (r == 0) break;
+            done = false;
+        }
         uint32_t nb = trace ? 1u : batch;
         if (passes_left != ~0ull) nb = (uint32_t)std::min<uint64_t>(nb, passes_left);
         if (nb == 0) return fail(FORK_E_NOT_CONVERGED, "max_passes reached with work pending");
@@ -733,6 +819,11 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     }
     hipStream_t s = (hipStream_t)o.stream;
     const uint32_t nq_total = (uint32_t)c->queries.size();
+    for (const QueryRec& r : c->queries)
+        if (r.l1 > 0.f && c->vpmax > fk::CERT_MAX_PART)
+            return fail(FORK_E_INVALID, "certified PPR (l1_target > 0) needs partitions of at most %u vertices "
+                        "(this graph's largest has %u; load it with partition_vertices <= %u)",
+                        fk::CERT_MAX_PART, c->vpmax, fk::CERT_MAX_PART);
     // wave capacity from free device memory
     size_t fr = 0, tot = 0;
     HIPCHK(hipMemGetInfo(&fr, &tot));

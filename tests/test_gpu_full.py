@@ -168,6 +168,40 @@ def test_rmat20_ppr4096_full():
     fg.close()
 
 
+@pytest.mark.skip(reason="one run of this case (65,536-vertex partitions, before certified queries were limited "
+                  "to partitions of at most 1,024 vertices) ended in a GPU memory fault whose cause is not found; "
+                  "it stays off the GPU until that cause is found")
+def test_rmat20_ppr_certified_sample():
+    """The scale-20 PPR workload's graph and sources (the first 64), run in
+    the L1-certified mode: every query ends with ||r||_1 <= 0.9e-4, and a
+    seeded sample is within 1e-4 of fp64 power iteration in L1."""
+    fork = _fork()
+    spec = fi.WORKLOADS["rmat20_ppr4096"]
+    g = fi.make_graph(spec)
+    queries = fi.make_sources(g, spec)
+    p = knobs(g, queries)
+    srcs = queries[0][1][:64]
+    say("rmat20 certified ppr64", p)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=p["partition_vertices"])
+    fg.submit("ppr", srcs, alpha=spec["alpha"], epsilon=spec["epsilon"], eps_mode=spec["eps_mode"], l1_target=1e-4)
+    fg.run(items_per_pass=p["items_per_pass"], window=p["window"], delta=p["delta"],
+           slice_slots=p.get("slice_slots", 0))
+    st = fg.stats()
+    say("refine rounds", st["refine_rounds"], "edges", st["edges"], "run_ms", round(st["run_ms"], 1))
+    assert st["refine_rounds"] >= 1
+    for i in range(len(srcs)):
+        d = fg.digest(i)
+        assert 0.0 <= d["fres"] <= 0.9e-4 * (1 + 1e-6), (i, d["fres"])
+    idx = np.sort(np.random.default_rng(7).choice(len(srcs), 4, replace=False))
+    P = np.stack([fg.fetch(int(i), fork.FIELD_P) for i in idx]).astype(np.float64)
+    fg.close()
+    pi = oracle.ppr_exact(g, srcs[idx], spec["alpha"])
+    for k, i in enumerate(idx):
+        err = float(np.abs(P[k] - pi[k]).sum())
+        say("query", int(i), "L1 to power iteration", err)
+        assert np.all(P[k] >= 0) and err <= 1e-4, (int(i), err)
+
+
 def test_grid2048_sssp_bfs_full():
     fork = _fork()
     spec = fi.WORKLOADS["grid2048_sssp1024_bfs1024"]
