@@ -82,6 +82,10 @@ TRACE_WIDTH = 20
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2103_14915_amd.build`")
+    # torch (device memory and streams for callers) ships its own HIP runtime;
+    # load it first so that the library binds to the same runtime and both
+    # share one device context and stream namespace.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
     lib.fork_graph_load.argtypes = [ctypes.POINTER(ctypes.c_void_p), U32, U64, P, P, P,

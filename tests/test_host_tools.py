@@ -124,3 +124,36 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_ablation_configs_cover_the_study():
+    """The study's tables: four schedules; heuristic 1 at 0.25-4 mu with
+    heuristic 2 off; heuristic 2 at 0.25-4 Delta with heuristic 1 off; a run
+    without yielding; the cumulative ladder.  The priority run comes first."""
+    from paper_2103_14915_amd import ablation as ab
+    c = ab.configs({"sssp", "bfs"}, 1000)
+    assert c[0] == ("A", "Shortest (priority functor)", {"scheduler": "priority"})
+    assert [o["scheduler"] for g, _, o in c if g == "A"] == ["priority", "fifo", "random", "maxops"]
+    b = [o for g, _, o in c if g == "B"]
+    assert [o["edge_budget_mu"] for o in b] == [0.25, 0.5, 1.0, 2.0, 4.0, 0.0]
+    assert all(o["window_mode"] == 1 and o["delta"] >= 2 ** 30 for o in b)  # heuristic 2 off
+    cc = [o for g, _, o in c if g == "C"]
+    assert [o["delta"] for o in cc[:5]] == [250, 500, 1000, 2000, 4000]
+    assert "edge_budget_mu" not in cc[0] and cc[5] == b[5]  # heuristic 1 off; the same no-yield run
+    acc = [o for g, _, o in c if g == "acc"]
+    assert acc[0]["scheduler"] == "fifo" and acc[1]["scheduler"] == "priority" and acc[0]["edge_budget_mu"] == 0
+    assert acc[2] == {"scheduler": "priority"}
+    p = ab.configs({"ppr"}, 1)
+    assert not [1 for g, _, _ in p if g == "C"]
+    assert [o.get("edge_budget_mu") for g, _, o in p if g == "acc"] == [0.0, 0.0, 2.0]
+
+
+def test_ablation_markdown_marks_differences():
+    from paper_2103_14915_amd import ablation as ab
+    rows = [{"group": "A", "config": "x", "queries_per_s": 10.0, "ms_per_run": 1.0, "passes": 3, "edges": 5,
+             "sssp_bfs_identical": True, "ppr_mean_residual": None},
+            {"group": "B", "config": "y", "queries_per_s": 5.0, "ms_per_run": 2.0, "passes": 4, "edges": 6,
+             "sssp_bfs_identical": False, "ppr_mean_residual": 0.25}]
+    md = ab.markdown(rows).splitlines()
+    assert "| 1.00× |" in md[2] and "identical" in md[2]
+    assert "0.50×" in md[3] and "DIFFERENT" in md[3] and "0.25" in md[3]
