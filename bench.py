@@ -172,10 +172,16 @@ def main():
         n = args.copy_calibration // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
+        y.copy_(x)  # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(5):
             y.copy_(x)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 5}), flush=True)
+        ms = e0.elapsed_time(e1) / 5
+        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 6,
+                          "copy_gbs": 2.0 * n * 4 / (ms * 1e-3) / 1e9}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1 "
@@ -275,6 +281,9 @@ def main():
                      "traffic_over_algorithmic": (prof["traffic_bytes_per_launch"] / (abytes / launches))
                      if prof else None,
                      "profiled_avg_launch_ms": prof.get("avg_launch_ms") if prof else None,
+                     "l2_hit_rate": prof.get("l2_hit_rate") if prof else None,
+                     "wave_wait_share": prof.get("wave_wait_share") if prof else None,
+                     "achievable_copy_gbs": prof.get("copy_gbs") if prof else None,
                      "kernel": "k_process",
                      "avg_launch_ms": avg_ms, "launches_per_step": launches / args.steps,
                      "algorithmic_bytes_per_launch": abytes / launches,

@@ -7,9 +7,12 @@
 
 HBM traffic of a kernel = its FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
 each scaled by the factor that makes the same counter read the true byte count
-of a plain device-to-device copy of known size.  The summary records the hash
-of the kernel's source so that bench.py reports the traffic only while the
-kernel is unchanged.
+of a plain device-to-device copy of known size.  Optional passes add the L2
+hit rate (TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)), the share of wave
+cycles spent waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES), and the copy's own
+achieved bandwidth (the calibration run's JSON line).  The summary records
+the hash of the kernel's source so that bench.py reports these figures only
+while the kernel is unchanged.
 """
 from __future__ import annotations
 
@@ -60,6 +63,9 @@ def main(argv=None):
     ap.add_argument("--copy-write")
     ap.add_argument("--copy-bytes", type=int, default=0)
     ap.add_argument("--copy-kernel", default="copyBuffer")
+    ap.add_argument("--copy-log", help="stdout of the copy calibration run (its JSON line has copy_gbs)")
+    ap.add_argument("--tcc", help="counter CSV with TCC_HIT_sum and TCC_MISS_sum")
+    ap.add_argument("--sq", help="counter CSV with SQ_WAIT_ANY and SQ_WAVE_CYCLES")
     ap.add_argument("--kernel", default="k_process")
     ap.add_argument("--command", default="")
     ap.add_argument("--title", default="")
@@ -91,6 +97,26 @@ def main(argv=None):
                       f"{w_scale:.3f}; scales from a {a.copy_bytes} B device copy): "
                       f"fetch {fetch_b / 1e6:.1f} MB, write {write_b / 1e6:.1f} MB, "
                       f"total {(fetch_b + write_b) / 1e6:.1f} MB over {n1} launches."]
+    if a.tcc:
+        _, (_, hit) = pick(per_kernel(a.tcc, "TCC_HIT_sum"), a.kernel)
+        _, (_, miss) = pick(per_kernel(a.tcc, "TCC_MISS_sum"), a.kernel)
+        out["l2_hit_rate"] = hit / (hit + miss) if hit + miss else None
+        lines += ["", f"L2 hit rate of `{a.kernel}` (TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)): "
+                      f"{100.0 * out['l2_hit_rate']:.1f}%."]
+    if a.sq:
+        _, (_, wait) = pick(per_kernel(a.sq, "SQ_WAIT_ANY"), a.kernel)
+        _, (_, cyc) = pick(per_kernel(a.sq, "SQ_WAVE_CYCLES"), a.kernel)
+        out["wave_wait_share"] = wait / cyc if cyc else None
+        lines += ["", f"Wave cycles of `{a.kernel}` spent waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES): "
+                      f"{100.0 * out['wave_wait_share']:.1f}%."]
+    if a.copy_log:
+        for ln in open(a.copy_log):
+            ln = ln.strip()
+            if ln.startswith("{") and "copy_gbs" in ln:
+                out["copy_gbs"] = json.loads(ln)["copy_gbs"]
+        if "copy_gbs" in out:
+            lines += ["", f"Achieved bandwidth of the plain device copy (read + write bytes / time): "
+                          f"{out['copy_gbs']:.0f} GB/s."]
     lines += ["", "```json", json.dumps(out, indent=1), "```", ""]
     with open(a.out, "w") as f:
         f.write("\n".join(lines))

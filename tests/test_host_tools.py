@@ -92,11 +92,19 @@ def test_profile_summary_scales_counters_by_copy_calibration(tmp_path):
     copy_bytes = 1 << 20  # the copy moved 1 MiB; its counters read half (fetch) and all (write) of it
     _write_csv(cf, pmc_hdr, [["__amd_rocclr_copyBuffer", "FETCH_SIZE", 512.0]] * 2)
     _write_csv(cw, pmc_hdr, [["__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024.0]] * 2)
+    tcc, sq, clog = tmp_path / "tcc.csv", tmp_path / "sq.csv", tmp_path / "copy.log"
+    _write_csv(tcc, pmc_hdr, [["fk::k_process<0>(x)", "TCC_HIT_sum", 300.0], ["fk::k_process<0>(x)", "TCC_MISS_sum", 100.0],
+                              ["fk::k_select(x)", "TCC_HIT_sum", 1.0], ["fk::k_select(x)", "TCC_MISS_sum", 99.0]] * 2)
+    _write_csv(sq, pmc_hdr, [["fk::k_process<0>(x)", "SQ_WAIT_ANY", 60.0], ["fk::k_process<0>(x)", "SQ_WAVE_CYCLES", 80.0]])
+    clog.write_text("noise\n" + json.dumps({"copy_calibration_bytes": 1, "copy_gbs": 4321.0}) + "\n")
     out = tmp_path / "k.md"
     ps.main(["--stats", str(stats), "--fetch", str(fetch), "--write", str(write), "--copy-fetch", str(cf),
              "--copy-write", str(cw), "--copy-bytes", str(copy_bytes), "--kernel", "k_process",
+             "--tcc", str(tcc), "--sq", str(sq), "--copy-log", str(clog),
              "--command", "cmd", "--out", str(out)])
     blob = json.loads(out.read_text().split("```json", 1)[1].split("```", 1)[0])
+    assert blob["l2_hit_rate"] == pytest.approx(0.75)  # the kernel's own counters, not k_select's
+    assert blob["wave_wait_share"] == pytest.approx(0.75) and blob["copy_gbs"] == 4321.0
     assert blob["fetch_scale"] == pytest.approx(2.0) and blob["write_scale"] == pytest.approx(1.0)
     assert blob["fetch_bytes_per_launch"] == pytest.approx(1000.0 * 1024 * 2.0)
     assert blob["write_bytes_per_launch"] == pytest.approx(500.0 * 1024)
