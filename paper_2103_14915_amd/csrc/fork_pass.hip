@@ -375,7 +375,13 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
             uint32_t len = i - rsv + 1;
             unsigned long long b = (unsigned long long)T * c.Q.qc + c.q;
             const unsigned long long w = dev_add(&c.B.btw[b], (unsigned long long)len);
-            const uint32_t tl = (uint32_t)(w >> 32), f = (uint32_t)w;
+            uint32_t tl = (uint32_t)(w >> 32), f = (uint32_t)w;
+            if (tl != 0xffffffffu && tl >= c.B.nch) {
+                // a damaged tail word: flag it (the run ends) and keep every write in range
+                dev_or(&c.B.ctl->err, (uint32_t)ERR_CORRUPT);
+                tl = 0xffffffffu;
+                f = CH + 1;
+            }
             uint32_t kk = 0;
             if (tl != 0xffffffffu && f < (uint32_t)CH) kk = ((uint32_t)CH - f) < len ? ((uint32_t)CH - f) : len;
             S.rt[rsv] = (int32_t)tl;
@@ -426,7 +432,14 @@ __device__ __forceinline__ void flush(ItemCtx& c, PassShared& S) {
     }
     {
         const uint32_t k = S.nrefill, have = S.nstash;
-        for (uint32_t i = t; i < k; i += NT) S.stash[have + i] = c.B.ring[(S.base + i) % nch];
+        for (uint32_t i = t; i < k; i += NT) {
+            uint32_t id = c.B.ring[(S.base + i) % nch];
+            if (id >= nch) {  // a damaged free ring: flag it (the run ends), keep writes in range
+                dev_or(&c.B.ctl->err, (uint32_t)ERR_CORRUPT);
+                id = 0;
+            }
+            S.stash[have + i] = id;
+        }
     }
     __syncthreads();
     // this flush takes the top nnew entries of the stash
@@ -542,12 +555,21 @@ __device__ __forceinline__ void push_frontier(ItemCtx& c, PassShared& S, uint32_
 // of the buffer into the query's state) and free the chunks.
 __device__ __forceinline__ void consume(ItemCtx& c, PassShared& S) {
     const uint32_t t = threadIdx.x;
-    // first round: the chunks the detach listed in the item
-    if (t < S.it.nch) {
-        S.clist[t] = (int32_t)S.it.ch[t].x;
-        S.ccnt[t] = S.it.ch[t].y;
+    // first round: the chunks the detach listed in the item.  A chunk id out
+    // of range means a damaged buffer: it is flagged (the run ends with the
+    // consistency error) and read as an empty chunk, so no access leaves the pool.
+    const uint32_t nch0 = S.it.nch < (uint32_t)ICH ? S.it.nch : (uint32_t)ICH;
+    if (t < nch0) {
+        uint32_t id = S.it.ch[t].x, cnt = S.it.ch[t].y;
+        if (id >= c.B.nch) {
+            dev_or(&c.B.ctl->err, (uint32_t)ERR_CORRUPT);
+            id = 0;
+            cnt = 0;
+        }
+        S.clist[t] = (int32_t)id;
+        S.ccnt[t] = cnt;
     }
-    if (t == 0) { S.ncl = S.it.nch; S.chnext = S.it.rest; }
+    if (t == 0) { S.ncl = nch0; S.chnext = S.it.rest; }
     __syncthreads();
     for (bool first = true;; first = false) {
         if (!first) {
@@ -556,6 +578,11 @@ __device__ __forceinline__ void consume(ItemCtx& c, PassShared& S) {
                 int32_t ch = S.chnext;
                 uint32_t n = 0;
                 while (ch >= 0 && n < (uint32_t)CCAP) {
+                    if ((unsigned long long)ch >= c.B.nch) {  // a damaged link: flag it, end the list
+                        dev_or(&c.B.ctl->err, (uint32_t)ERR_CORRUPT);
+                        ch = -1;
+                        break;
+                    }
                     S.clist[n++] = ch;
                     ch = c.B.cnext[ch];
                 }

@@ -346,7 +346,7 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     }
     const uint64_t per_chunk = sizeof(uint2) * fk::CH + 4 + 4 + 4;
     c->nch = std::max<uint64_t>(1024, pool / per_chunk);
-    if (c->nch > 0xfffffff0ull) c->nch = 0xfffffff0ull;
+    if (c->nch > 0x7fffffffull) c->nch = 0x7fffffffull;  // chunk links are int32
     if ((rc = dalloc(&c->d_chunks, c->nch * fk::CH))) return cleanup(rc);
     if ((rc = dalloc(&c->d_cnext, c->nch))) return cleanup(rc);
     if ((rc = dalloc(&c->d_ccount, c->nch))) return cleanup(rc);

@@ -195,19 +195,33 @@ __device__ __forceinline__ void worklist_one(const BufDev& B, const QueryDev& Q,
             // close the tail: record its fill and splice the overflow list after it
             const unsigned long long w = B.btw[b];
             uint32_t tl = 0xffffffffu, tf = 0;
-            if (h >= 0) {
+            // chunk ids out of range mean a damaged buffer: the item is left
+            // empty and the run stops with the consistency error
+            bool bad = (unsigned long long)h >= B.nch && h >= 0;
+            bad |= (unsigned long long)o >= B.nch && o >= 0;
+            if (h >= 0 && !bad) {
                 tl = (uint32_t)(w >> 32);
                 tf = (uint32_t)w < (uint32_t)CH ? (uint32_t)w : (uint32_t)CH;
-                B.ccount[tl] = tf;
-                B.cnext[tl] = o;
+                if (tl < B.nch) {
+                    B.ccount[tl] = tf;
+                    B.cnext[tl] = o;
+                } else {
+                    bad = true;
+                }
             }
             Item* it = &B.items[(unsigned long long)x * B.item_cap + pos];
-            int32_t cur = h >= 0 ? h : o;
+            int32_t cur = (h >= 0 ? h : o);
             uint32_t n = 0;
-            while (cur >= 0 && n < (uint32_t)ICH) {
+            while (!bad && cur >= 0 && n < (uint32_t)ICH) {
+                if ((unsigned long long)cur >= B.nch) { bad = true; break; }
                 const bool is_tail = (uint32_t)cur == tl;
                 it->ch[n++] = make_uint2((uint32_t)cur, is_tail ? tf : B.ccount[cur]);
                 cur = is_tail ? o : B.cnext[cur];
+            }
+            if (bad) {
+                dev_or(&ctl->err, (uint32_t)ERR_CORRUPT);
+                n = 0;
+                cur = -1;
             }
             it->part = P;
             it->q = q;
