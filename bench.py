@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--scale", type=int, default=0, help="experiment: override the R-MAT scale")
     ap.add_argument("--queries", type=int, default=0, help="experiment: use only the first N queries per type")
     ap.add_argument("--max-queries", type=int, default=0, help="queries resident per wave (0 = auto)")
+    ap.add_argument("--order", default="auto", choices=["auto", "none", "tiles", "rcm"],
+                    help="internal vertex order: auto = square tiles for grids, the generator's order otherwise")
     ap.add_argument("--l1-target", type=float, default=0.0,
                     help="PPR queries in the L1-certified mode with this target (0 = plain push at epsilon)")
     ap.add_argument("--pool-mb", type=int, default=0, help="device memory for buffered operations (0 = auto)")
@@ -221,9 +223,22 @@ def main():
             params[k] = v
     if args.slice_slots >= 0:
         params["slice_slots"] = args.slice_slots
+    from paper_2103_14915_amd import order as vorder
+    t0 = time.perf_counter()
+    if args.order == "auto":
+        pos = vorder.auto(spec, g, params["partition_vertices"])
+    elif args.order == "tiles":
+        pos = vorder.grid_tiles(spec["rows"], spec["cols"], vorder.square_tile(params["partition_vertices"]))
+    elif args.order == "rcm":
+        pos = vorder.rcm(g)
+    else:
+        pos = None
+    params["vertex_order"] = "none" if pos is None else (
+        "rcm" if args.order == "rcm" else f"tiles{vorder.square_tile(params['partition_vertices'])}")
+    t_order = time.perf_counter() - t0
     t0 = time.perf_counter()
     fg = fork.ForkGraph.from_graph(g, partition_vertices=params["partition_vertices"], max_queries=args.max_queries,
-                                   pool_bytes=args.pool_mb << 20)
+                                   pool_bytes=args.pool_mb << 20, vertex_order=pos)
     t_load = time.perf_counter() - t0
     nq = 0
     for qt, s in queries:
@@ -288,7 +303,7 @@ def main():
                      "avg_launch_ms": avg_ms, "launches_per_step": launches / args.steps,
                      "algorithmic_bytes_per_launch": abytes / launches,
                      "algorithmic_bytes_per_step": abytes / args.steps},
-        "detail": {"graph_gen_s": t_gen, "graph_load_s": t_load,
+        "detail": {"graph_gen_s": t_gen, "vertex_order_s": t_order, "graph_load_s": t_load,
                    "init_ms_per_step": tot["init_ms"] / args.steps, "run_ms_per_step": tot["run_ms"] / args.steps,
                    "process_ms_per_step": tot["process_ms"] / args.steps,
                    "passes_per_step": tot["passes"] / args.steps,

@@ -62,6 +62,21 @@ typedef struct {
     uint64_t pool_bytes;         /* device bytes for the operation pool        */
     int      inputs_on_device;   /* row_ptr/col/weight are device pointers     */
     int      device;             /* HIP device ordinal                          */
+    const uint32_t *vertex_order;/* NULL, or uint32[num_vertices]: a permutation
+                                    giving each vertex's position in the
+                                    library's internal numbering.  Partitions
+                                    are contiguous ranges of that numbering, so
+                                    an order that keeps neighbours close (2D
+                                    tiles of a grid, a space-filling curve of a
+                                    road network) cuts fewer edges; the paper's
+                                    partitioner study credits locality-aware
+                                    partitions with large gains over random
+                                    ones (Section 7.3).  Sources, results and
+                                    digests always use the caller's ids; only
+                                    fork_partitions reports internal positions.
+                                    Host memory, or device memory when
+                                    inputs_on_device.  Not a permutation:
+                                    FORK_E_INVALID.                            */
 } fork_config;
 
 /* PPR parameters (passed to fork_submit for FORK_PPR).  A vertex is pushed

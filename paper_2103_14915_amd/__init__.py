@@ -40,7 +40,8 @@ class ForkError(RuntimeError):
 class fork_config(ctypes.Structure):
     _fields_ = [("partition_vertices", ctypes.c_uint32), ("partition_edges", ctypes.c_uint32),
                 ("max_queries", ctypes.c_uint32), ("pool_bytes", ctypes.c_uint64),
-                ("inputs_on_device", ctypes.c_int), ("device", ctypes.c_int)]
+                ("inputs_on_device", ctypes.c_int), ("device", ctypes.c_int),
+                ("vertex_order", ctypes.c_void_p)]
 
 
 class fork_ppr_params(ctypes.Structure):
@@ -133,7 +134,10 @@ class ForkGraph:
     """A graph loaded on the GPU plus the queries submitted against it."""
 
     def __init__(self, num_vertices, row_ptr, col, weight=None, partition_vertices=0, partition_edges=0,
-                 max_queries=0, pool_bytes=0, device=0):
+                 max_queries=0, pool_bytes=0, device=0, vertex_order=None):
+        """vertex_order: None, or each vertex's position in the library's internal
+        numbering (a permutation; see ``paper_2103_14915_amd.order``).  Sources,
+        results and digests stay in the caller's ids."""
         rp, dev_rp, k1 = _ptr(row_ptr if not isinstance(row_ptr, np.ndarray) else row_ptr.astype(np.uint64))
         cp, dev_c, k2 = _ptr(col if not isinstance(col, np.ndarray) else col.astype(np.uint32))
         wp, dev_w, k3 = _ptr(weight if (weight is None or not isinstance(weight, np.ndarray))
@@ -141,7 +145,12 @@ class ForkGraph:
         on_dev = dev_rp or dev_c or dev_w
         if on_dev and not (dev_rp and dev_c and (weight is None or dev_w)):
             raise ValueError("row_ptr, col and weight must all be on the host or all on the device")
-        cfg = fork_config(partition_vertices, partition_edges, max_queries, pool_bytes, int(on_dev), device)
+        if vertex_order is not None and not hasattr(vertex_order, "data_ptr"):
+            vertex_order = np.ascontiguousarray(vertex_order, np.uint32)
+        op, dev_o, k4 = _ptr(vertex_order)
+        if vertex_order is not None and bool(dev_o) != bool(on_dev):
+            raise ValueError("vertex_order must be where row_ptr and col are (host or device)")
+        cfg = fork_config(partition_vertices, partition_edges, max_queries, pool_bytes, int(on_dev), device, op)
         ne = int(k2.shape[0]) if k2 is not None else 0
         self._ctx = ctypes.c_void_p()
         self.num_vertices = int(num_vertices)

@@ -66,8 +66,11 @@ __global__ void k_seed(GraphDev g, QueryDev Q, BufDev B, const uint32_t* src) {
     B.bfirst[b] = 0;
 }
 
-// Per-query digest of the final state (one block per query).
-__global__ __launch_bounds__(256) void k_digest(QueryDev Q, uint32_t nv, unsigned long long* out /*[nq*6]*/) {
+// Per-query digest of the final state (one block per query).  orig (NULL
+// for the identity) maps the internal vertex numbering to the caller's ids,
+// which the hash is defined on.
+__global__ __launch_bounds__(256) void k_digest(QueryDev Q, uint32_t nv, unsigned long long* out /*[nq*6]*/,
+                                                const uint32_t* orig) {
     const uint32_t q = blockIdx.x;
     if (q >= Q.nq) return;
     const uint32_t t = Q.qtype[q];
@@ -97,7 +100,7 @@ __global__ __launch_bounds__(256) void k_digest(QueryDev Q, uint32_t nv, unsigne
             if (x != INF) {
                 ++cnt;
                 sum += x;
-                hash += mix64(((unsigned long long)v << 32) | x);
+                hash += mix64(((unsigned long long)(orig ? orig[v] : v) << 32) | x);
             }
         }
     }
@@ -118,6 +121,13 @@ __global__ __launch_bounds__(256) void k_digest(QueryDev Q, uint32_t nv, unsigne
         o[4] = __double_as_longlong(s_f1);
         o[5] = __double_as_longlong(fm);
     }
+}
+
+// A result vector in the caller's numbering: dst[v] = src[pos[v]], with pos
+// the internal position of vertex v.
+__global__ void k_gather(const uint32_t* src, const uint32_t* pos, uint32_t* dst, uint32_t nv) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x)
+        dst[v] = src[pos[v]];
 }
 
 // ------------------------------------------------------------ certified PPR
@@ -215,8 +225,14 @@ hipError_t launch_rescan_items(const BufDev& B, uint32_t np, const uint32_t* qs,
     hipLaunchKernelGGL(k_rescan_items, dim3((m + 255) / 256), dim3(256), 0, s, B, np, qs, lo, n);
     return hipGetLastError();
 }
-hipError_t launch_digest(const QueryDev& Q, uint32_t nv, unsigned long long* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_digest, dim3(Q.nq), dim3(256), 0, s, Q, nv, out);
+hipError_t launch_digest(const QueryDev& Q, uint32_t nv, unsigned long long* out, const uint32_t* orig,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_digest, dim3(Q.nq), dim3(256), 0, s, Q, nv, out, orig);
+    return hipGetLastError();
+}
+hipError_t launch_gather(const uint32_t* src, const uint32_t* pos, uint32_t* dst, uint32_t nv, hipStream_t s) {
+    const uint32_t blocks = (nv + 255) / 256 < 4096u ? (nv + 255) / 256 : 4096u;
+    hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(256), 0, s, src, pos, dst, nv);
     return hipGetLastError();
 }
 }  // namespace fk

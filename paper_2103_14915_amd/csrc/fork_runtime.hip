@@ -27,7 +27,8 @@ int process_threads();
 hipError_t launch_ring_init(uint32_t*, unsigned long long, hipStream_t);
 hipError_t launch_fill64(unsigned long long*, unsigned long long, unsigned long long, hipStream_t);
 hipError_t launch_seed(const GraphDev&, const QueryDev&, const BufDev&, const uint32_t*, hipStream_t);
-hipError_t launch_digest(const QueryDev&, uint32_t, unsigned long long*, hipStream_t);
+hipError_t launch_digest(const QueryDev&, uint32_t, unsigned long long*, const uint32_t*, hipStream_t);
+hipError_t launch_gather(const uint32_t*, const uint32_t*, uint32_t*, uint32_t, hipStream_t);
 hipError_t launch_rnorm(const QueryDev&, uint32_t, const uint32_t*, uint32_t, double*, hipStream_t);
 hipError_t launch_rescan_items(const BufDev&, uint32_t, const uint32_t*, unsigned long long, uint32_t, hipStream_t);
 hipError_t launch_mlp_score(const GraphDev&, const BufDev&, const float*, float*, float*, void*, uint32_t, hipStream_t);
@@ -77,6 +78,11 @@ struct fork_ctx {
     uint32_t np = 0, pshift = 0;
     std::vector<uint32_t> h_pstart;
     std::vector<uint32_t> h_rowptr;  // host copy (partition planning, statistics)
+    // caller's vertex order (empty: identity): internal position of each vertex
+    std::vector<uint32_t> h_pos;
+    uint32_t* d_pos = nullptr;     // [nv] internal position of caller vertex v
+    uint32_t* d_orig = nullptr;    // [nv] caller id of internal vertex u
+    uint32_t* d_gather = nullptr;  // [nv] staging for fetches to host memory
     // graph
     uint32_t* d_rowptr = nullptr;
     uint32_t* d_col = nullptr;
@@ -188,7 +194,7 @@ extern "C" void fork_destroy(fork_ctx* c) {
                     c->d_ccount, c->d_ring, c->d_pcount, c->d_pbest_sp, c->d_pbest_lv, c->d_pbest_pr,
                     c->d_pfirst, c->d_plast, c->d_pvisits, c->d_pn, c->d_sel, c->d_pqn, c->d_pready, c->d_pqmin,
                     c->d_score, c->d_mlp,
-                    c->d_ctl, c->d_gstat, c->d_feat, c->d_tr, c->d_final};
+                    c->d_ctl, c->d_gstat, c->d_feat, c->d_tr, c->d_final, c->d_pos, c->d_orig, c->d_gather};
     for (void* p : ptrs) if (p) hipFree(p);
     if (c->h_ctl) hipHostFree(c->h_ctl);
     for (auto& e : c->ev) if (e) hipEventDestroy(e);
@@ -286,6 +292,37 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     if (ws && wmax > 0x7fffffffu) return fail(FORK_E_INVALID, "weights must be < 2^31");
     double wsum = 0;
     if (ws) for (uint64_t e = 0; e < ne; ++e) wsum += ws[e];
+    // the caller's vertex order: relabel to internal positions (vertex v ->
+    // pos[v]), keeping each adjacency list's order
+    std::vector<uint32_t> pos, orig, pcol, pw;
+    std::vector<uint64_t> prp;
+    if (cfg.vertex_order) {
+        pos.resize(nv);
+        if (cfg.inputs_on_device)
+            HIPCHK(hipMemcpy(pos.data(), cfg.vertex_order, nv * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        else
+            memcpy(pos.data(), cfg.vertex_order, nv * sizeof(uint32_t));
+        orig.assign(nv, 0xffffffffu);
+        for (uint32_t v = 0; v < nv; ++v) {
+            if (pos[v] >= nv || orig[pos[v]] != 0xffffffffu)
+                return fail(FORK_E_INVALID, "vertex_order is not a permutation (entry %u = %u)", v, pos[v]);
+            orig[pos[v]] = v;
+        }
+        prp.assign(nv + 1, 0);
+        for (uint32_t u = 0; u < nv; ++u) prp[u + 1] = prp[u] + (rps[orig[u] + 1] - rps[orig[u]]);
+        pcol.resize(ne);
+        if (ws) pw.resize(ne);
+        for (uint32_t u = 0; u < nv; ++u) {
+            const uint64_t b = rps[orig[u]], d = rps[orig[u] + 1] - b;
+            for (uint64_t k = 0; k < d; ++k) {
+                pcol[prp[u] + k] = pos[cols[b + k]];
+                if (ws) pw[prp[u] + k] = ws[b + k];
+            }
+        }
+        rps = prp.data();
+        cols = pcol.data();
+        if (ws) ws = pw.data();
+    }
 
     fork_ctx* c = new fork_ctx();
     c->device = cfg.device;
@@ -298,6 +335,14 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     for (uint32_t v = 0; v <= nv; ++v) c->h_rowptr[v] = (uint32_t)rps[v];
     int rc = FORK_OK;
     auto cleanup = [&](int r) { fork_destroy(c); return r; };
+    if (!pos.empty()) {
+        if ((rc = dalloc(&c->d_pos, nv))) return cleanup(rc);
+        if ((rc = dalloc(&c->d_orig, nv))) return cleanup(rc);
+        if (hipMemcpy(c->d_pos, pos.data(), nv * 4ull, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->d_orig, orig.data(), nv * 4ull, hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(FORK_E_DEVICE, "hipMemcpy of the vertex order failed"));
+        c->h_pos.swap(pos);
+    }
     // partition plan
     uint32_t pv = cfg.partition_vertices ? cfg.partition_vertices : fk::VPMAX;
     if (pv > fk::PVMAX) return cleanup(fail(FORK_E_INVALID, "partition_vertices must be <= %u", fk::PVMAX));
@@ -422,7 +467,7 @@ extern "C" int fork_submit(fork_ctx* c, int type, const uint32_t* sources, uint3
     if (first_id) *first_id = (uint32_t)c->queries.size();
     for (uint32_t i = 0; i < n; ++i) {
         QueryRec r = base;
-        r.src = sources[i];
+        r.src = c->h_pos.empty() ? sources[i] : c->h_pos[sources[i]];
         c->queries.push_back(r);
     }
     return FORK_OK;
@@ -500,7 +545,7 @@ static int wave_digest(fork_ctx* c, hipStream_t s) {
     if (!c->dig_pending) return FORK_OK;
     const uint32_t q0 = c->res_first, nq = c->res_n;
     HIPCHK(hipEventRecord(c->ev[2], s));
-    HIPCHK(fk::launch_digest(c->resQ, c->nv, c->d_digest, s));
+    HIPCHK(fk::launch_digest(c->resQ, c->nv, c->d_digest, c->d_orig, s));
     HIPCHK(hipEventRecord(c->ev[3], s));
     std::vector<unsigned long long> dg((size_t)nq * 6);
     HIPCHK(hipMemcpyAsync(dg.data(), c->d_digest, dg.size() * 8, hipMemcpyDeviceToHost, s));
@@ -951,6 +996,21 @@ extern "C" int fork_fetch(fork_ctx* c, uint32_t qid, int field, void* dst, uint6
     if (dst_bytes < (uint64_t)c->nv * 4) return fail(FORK_E_INVALID, "dst too small");
     if (hipSetDevice(c->device) != hipSuccess) return fail(FORK_E_DEVICE, "hipSetDevice failed");
     const uint32_t* src = c->d_state + c->res_off[qid - c->res_first] + (field == FORK_FIELD_R ? c->nv : 0);
+    if (c->d_pos) {
+        // back to the caller's numbering
+        uint32_t* g = (uint32_t*)dst;
+        if (!dst_on_device) {
+            if (!c->d_gather) {
+                int rc = dalloc(&c->d_gather, c->nv);
+                if (rc) return rc;
+            }
+            g = c->d_gather;
+        }
+        HIPCHK(fk::launch_gather(src, c->d_pos, g, c->nv, nullptr));
+        if (dst_on_device) HIPCHK(hipDeviceSynchronize());
+        else HIPCHK(hipMemcpy(dst, g, (size_t)c->nv * 4, hipMemcpyDeviceToHost));
+        return FORK_OK;
+    }
     HIPCHK(hipMemcpy(dst, src, (size_t)c->nv * 4, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
     return FORK_OK;
 }

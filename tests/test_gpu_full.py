@@ -59,7 +59,10 @@ def sp_digest(vec):
 
 
 def run_workload(fork, g, queries, spec, p):
-    fg = fork.ForkGraph.from_graph(g, partition_vertices=p["partition_vertices"])
+    """The workload as bench.py runs it: tuned knobs and the workload's vertex order."""
+    from paper_2103_14915_amd import order
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=p["partition_vertices"],
+                                   vertex_order=order.auto(spec, g, p["partition_vertices"]))
     for qt, s in queries:
         fg.submit(qt, s, alpha=spec.get("alpha", 0.15), epsilon=spec.get("epsilon", 1e-6),
                   eps_mode=spec.get("eps_mode", 0))
