@@ -228,13 +228,13 @@ def main():
     if args.order == "auto":
         pos = vorder.auto(spec, g, params["partition_vertices"])
     elif args.order == "tiles":
-        pos = vorder.grid_tiles(spec["rows"], spec["cols"], vorder.square_tile(params["partition_vertices"]))
+        pos = vorder.grid_tiles(spec["rows"], spec["cols"], *vorder.tile_shape(params["partition_vertices"]))
     elif args.order == "rcm":
         pos = vorder.rcm(g)
     else:
         pos = None
-    params["vertex_order"] = "none" if pos is None else (
-        "rcm" if args.order == "rcm" else f"tiles{vorder.square_tile(params['partition_vertices'])}")
+    tr, tc = vorder.tile_shape(params["partition_vertices"])
+    params["vertex_order"] = "none" if pos is None else ("rcm" if args.order == "rcm" else f"tiles{tr}x{tc}")
     t_order = time.perf_counter() - t0
     t0 = time.perf_counter()
     fg = fork.ForkGraph.from_graph(g, partition_vertices=params["partition_vertices"], max_queries=args.max_queries,

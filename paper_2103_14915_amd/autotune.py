@@ -78,7 +78,10 @@ def _sample(queries, n):
 
 
 def _trial(g, sample, spec, p, stream=None) -> float:
-    fg = ForkGraph.from_graph(g, partition_vertices=p["partition_vertices"])
+    from . import order
+    # the workload's vertex order follows the partition size (one tile per partition on grids)
+    fg = ForkGraph.from_graph(g, partition_vertices=p["partition_vertices"],
+                              vertex_order=order.auto(spec, g, p["partition_vertices"]))
     try:
         n = 0
         for qt, s in sample:

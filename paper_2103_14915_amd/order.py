@@ -46,6 +46,19 @@ def square_tile(partition_vertices: int) -> int:
     return max(1, int(math.isqrt(int(partition_vertices))))
 
 
+def tile_shape(partition_vertices: int) -> tuple:
+    """(rows, cols) of a tile that fills one partition: a power-of-two
+    rectangle (square, or twice as wide as tall) when partition_vertices is a
+    power of two, so tiles and partitions stay aligned; else the largest
+    square."""
+    pv = int(partition_vertices)
+    if pv > 0 and pv & (pv - 1) == 0:
+        k = pv.bit_length() - 1
+        return 1 << (k // 2), 1 << (k - k // 2)
+    s = square_tile(pv)
+    return s, s
+
+
 def rcm(g) -> np.ndarray:
     """Position of each vertex in the reverse Cuthill-McKee order of the
     symmetrised graph."""
@@ -61,10 +74,10 @@ def rcm(g) -> np.ndarray:
 
 
 def auto(spec: dict, g, partition_vertices: int):
-    """The order the benchmark workloads use: square tiles of one partition
-    each for grids (their row-major numbering cuts a band of rows into each
+    """The order the benchmark workloads use: tiles of one partition each
+    for grids (their row-major numbering cuts a band of rows into each
     partition); None (the generator's numbering) for R-MAT graphs, whose
     vertices have no geometry."""
     if spec.get("kind") == "grid":
-        return grid_tiles(spec["rows"], spec["cols"], square_tile(partition_vertices))
+        return grid_tiles(spec["rows"], spec["cols"], *tile_shape(partition_vertices))
     return None

@@ -47,3 +47,10 @@ def test_rcm_and_auto():
     a = order.auto({"kind": "grid", "rows": 32, "cols": 32}, gg, 256)
     assert np.array_equal(a, order.grid_tiles(32, 32, 16))
     assert order.square_tile(65536) == 256 and order.square_tile(1000) == 31
+    assert order.tile_shape(65536) == (256, 256) and order.tile_shape(8192) == (64, 128)
+    assert order.tile_shape(32768) == (128, 256) and order.tile_shape(1000) == (31, 31)
+    # a tile is exactly one partition's range of positions
+    pv = 8192
+    p = order.auto({"kind": "grid", "rows": 256, "cols": 256}, fi.grid(256, 256, weights=None), pv)
+    r, c = np.divmod(np.arange(256 * 256), 256)
+    assert np.all(p // pv == (r // 64) * 2 + c // 128)
