@@ -101,6 +101,37 @@ def collect(spec: dict, n_sssp: int, n_ppr: int, partition_vertices: int = PARTI
     return rec
 
 
+# Grid family (the road-network stand-in): grids whose weight and source
+# seeds differ from every test and benchmark grid, traced with the knobs tuned
+# for the 2048 x 2048 workload in its tile order.
+GRID_SPECS = [
+    dict(rows=1024, cols=1024, wseed=161, sseed=261),
+    dict(rows=1536, cols=1536, wseed=162, sseed=262),
+    dict(rows=1024, cols=2048, wseed=163, sseed=263),
+]
+GRID_PARTITION_VERTICES = 8192
+GRID_RUN_KW = dict(window=0, delta=128256, items_per_pass=65536, slice_slots=0)
+
+
+def collect_grid(spec: dict, n_sssp: int, n_bfs: int, log=print) -> np.ndarray:
+    import fpp_inputs as fi
+    from . import order
+
+    g = fi.grid(spec["rows"], spec["cols"], weights=(1, 1000), weight_seed=spec["wseed"])
+    pos = order.grid_tiles(spec["rows"], spec["cols"], *order.tile_shape(GRID_PARTITION_VERTICES))
+    fg = ForkGraph.from_graph(g, partition_vertices=GRID_PARTITION_VERTICES, vertex_order=pos)
+    if n_sssp:
+        fg.submit("sssp", fi.sources_uniform(g, n_sssp, spec["sseed"]))
+    if n_bfs:
+        fg.submit("bfs", fi.sources_uniform(g, n_bfs, spec["sseed"] + 1))
+    t0 = time.time()
+    fg.run(scheduler="priority", trace=1, **GRID_RUN_KW)
+    rec = fg.trace()
+    fg.close()
+    log(f"[learn] traced grid {spec['rows']}x{spec['cols']}: {rec.shape[0]} visits in {time.time() - t0:.1f}s")
+    return rec
+
+
 def train(records: np.ndarray, steps: int = 3000, batch: int = 256, lr: float = 1e-3, seed: int = 7,
           label: str = "useful"):
     x = records[:, :16]
@@ -113,18 +144,25 @@ def train(records: np.ndarray, steps: int = 3000, batch: int = 256, lr: float = 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--family", default="rmat", choices=["rmat", "grid"],
+                    help="training graphs: R-MAT SSSP+PPR mixes, or grids with SSSP+BFS")
     ap.add_argument("--sssp", type=int, default=512)
     ap.add_argument("--ppr", type=int, default=512)
+    ap.add_argument("--bfs", type=int, default=256, help="BFS queries per grid (grid family)")
     ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--specs", type=int, default=len(TRAIN_SPECS))
+    ap.add_argument("--specs", type=int, default=0, help="training graphs to use (0 = all of the family)")
     ap.add_argument("--label", default="useful", choices=LABELS)
     ap.add_argument("--save-trace", default="", help="also save the trace records (.npy)")
     ap.add_argument("--load-trace", default="", help="train on saved trace records instead of tracing")
     args = ap.parse_args(argv)
+    specs = (GRID_SPECS if args.family == "grid" else TRAIN_SPECS)
+    specs = specs[:args.specs] if args.specs else specs
     if args.load_trace:
         records = np.load(args.load_trace)
+    elif args.family == "grid":
+        records = np.concatenate([collect_grid(s, args.sssp, args.bfs) for s in specs])
     else:
-        records = np.concatenate([collect(s, args.sssp, args.ppr) for s in TRAIN_SPECS[:args.specs]])
+        records = np.concatenate([collect(s, args.sssp, args.ppr) for s in specs])
     if args.save_trace:
         np.save(args.save_trace, records)
     t0 = time.time()
@@ -132,10 +170,12 @@ def main(argv=None):
     print(f"[learn] trained on {records.shape[0]} visits, {args.steps} steps in {time.time() - t0:.1f}s: "
           f"loss {losses[:50].mean():.4f} -> {losses[-50:].mean():.4f}", flush=True)
     np.save(args.out, theta)
+    grid = args.family == "grid"
     meta = {"records": int(records.shape[0]), "steps": args.steps, "loss_first": float(losses[:50].mean()),
-            "loss_last": float(losses[-50:].mean()), "specs": TRAIN_SPECS[:args.specs], "label": args.label,
-            "run_knobs": dict(RUN_KW, partition_vertices=PARTITION_VERTICES),
-            "queries": {"sssp": args.sssp, "ppr": args.ppr}}
+            "loss_last": float(losses[-50:].mean()), "family": args.family, "specs": specs, "label": args.label,
+            "run_knobs": dict(GRID_RUN_KW, partition_vertices=GRID_PARTITION_VERTICES) if grid
+            else dict(RUN_KW, partition_vertices=PARTITION_VERTICES),
+            "queries": {"sssp": args.sssp, "bfs": args.bfs} if grid else {"sssp": args.sssp, "ppr": args.ppr}}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(meta, f, indent=1)
     return 0
