@@ -84,24 +84,31 @@ def cpu_baseline(g, queries, spec, budget_s=15.0, l1_target=0.0):
     done, t_total = 0, 0.0
     rng = np.random.default_rng(0)
     samples = []
+    work = {}  # query type -> [queries, edges the sequential algorithm scanned or pushed]
     while t_total < budget_s and done < sum(len(s) for _, s in kinds):
         for qt, s in kinds:
             batch = rng.choice(s, size=min(threads, len(s)), replace=False)
             t0 = time.perf_counter()
+            w = None
             if qt == "ppr" and l1_target > 0:
                 certified_push(oracle, g, batch, spec.get("alpha", 0.15), spec.get("epsilon", 1e-6),
                                spec.get("eps_mode", 0), l1_target, threads)
             elif qt == "ppr":
-                oracle.forward_push(g, batch, spec.get("alpha", 0.15), spec.get("epsilon", 1e-6),
-                                    spec.get("eps_mode", 0), threads)
+                _, _, w = oracle.forward_push(g, batch, spec.get("alpha", 0.15), spec.get("epsilon", 1e-6),
+                                              spec.get("eps_mode", 0), threads, return_work=True)
             elif qt == "bfs":
-                oracle.bfs(g, batch, threads)
+                _, w = oracle.bfs(g, batch, threads, return_work=True)
             else:
-                oracle.sssp(g, batch, threads)
+                _, w = oracle.sssp(g, batch, threads, return_work=True)
             t_total += time.perf_counter() - t0
             done += len(batch)
             samples.append(f"{len(batch)} {qt}")
+            if w is not None:
+                acc = work.setdefault(qt, [0, 0])
+                acc[0] += len(batch)
+                acc[1] += int(np.sum(w))
     return {"value": done / t_total, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sequential_edges_per_query": {qt: e / n for qt, (n, e) in work.items()},
             "sample": f"{done} queries ({', '.join(sorted(set(samples)))} per batch) of the same workload, "
                       f"{t_total:.1f} s, fp64 forward push / Dijkstra / BFS, one query per thread"
                       + (f"; PPR certified to L1 {l1_target:g} by restarted pushes at lower thresholds"
@@ -317,7 +324,15 @@ def main():
     if args.compare_learned:
         line["learned_vs_rule"] = compare_learned(fg, args, run_kw, nq, value)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(g, queries, spec, args.cpu_budget, args.l1_target)
+        cb = cpu_baseline(g, queries, spec, args.cpu_budget, args.l1_target)
+        per_q = cb.pop("sequential_edges_per_query")
+        line["cpu_baseline"] = cb
+        # work efficiency: edges the GPU run scanned or pushed over the edges the
+        # sequential algorithms (Dijkstra, BFS, sequential push) need for the same queries
+        if per_q and all(qt in per_q for qt, _ in queries):
+            seq = sum(len(s) * per_q[qt] for qt, s in queries)
+            line["detail"]["sequential_edges_per_query"] = per_q
+            line["detail"]["edges_vs_sequential"] = (tot["edges"] / args.steps) / seq if seq else None
     fg.close()
     print(json.dumps(line), flush=True)
 
