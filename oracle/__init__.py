@@ -18,6 +18,8 @@ sequential algorithm, with no blocking or reordering):
                      vector that forward push approximates.
 * ``sp_certificate`` -- optimality certificate for shortest distances.
 * ``mlp``         -- fp64 forward/backward of the partition-scoring MLP.
+* ``ncp``         -- sweep-cut conductance profiles of PPR vectors and the
+                     network community profile (numpy).
 
 Readings where the paper is silent (no PPR formula, alpha, epsilon or
 dangling-vertex rule is printed): the walk is substochastic (a vertex without
