@@ -177,6 +177,22 @@ enum {
     FORK_FIELD_DIGEST = 3  /* fork_digest                                    */
 };
 
+/* Sweep cut of one PPR result (fork_sweep).  Sizes count swept vertices. */
+#define FORK_SWEEP_MAX 1024
+#define FORK_SWEEP_BUCKETS 11
+typedef struct {
+    uint32_t support;          /* vertices with p > 0 and d > 0                   */
+    uint32_t swept;            /* prefixes evaluated: min(support, max_size)      */
+    uint32_t best_size;        /* least-conductance prefix (0: none defined)      */
+    uint32_t flags;            /* 1 = more than FORK_SWEEP_MAX vertices share the
+                                  cut-off key: no result for this query           */
+    double   best_conductance; /* +inf when no prefix has one                     */
+    uint64_t best_cut;         /* edges leaving the best prefix                   */
+    uint64_t best_volume;      /* its volume                                      */
+    double   size_min[FORK_SWEEP_BUCKETS]; /* least conductance of prefix sizes in
+                                  [2^j, 2^(j+1)); +inf when none                  */
+} fork_sweep_t;
+
 /*
  * Load a graph (Definition 2.1 fixes what a partition owns: the out-edges of
  * its vertices).  row_ptr: uint64[num_vertices+1], col: uint32[num_edges],
@@ -209,6 +225,25 @@ int fork_submit(fork_ctx *ctx, int query_type, const uint32_t *sources,
  * operations are retained, so correctness holds).
  */
 int fork_run(fork_ctx *ctx, const fork_run_opts *opts);
+
+/*
+ * Sweep cuts of resident PPR queries: the NCP application built on the PPR
+ * queries (Sections 2 and 7.1; the paper computes the network community
+ * profile from one PPR per seed and does not print the sweep).  Reading:
+ * the graph is taken as undirected, each directed edge one undirected edge,
+ * d(v) = out-degree + in-degree, total volume 2|E|; the vertices with
+ * p[v] > 0 and d(v) > 0 are swept in decreasing fp32 p[v]/d(v), equal keys
+ * in increasing internal position (the caller's id when no vertex_order was
+ * given); prefix S_k has conductance cut(S_k) / min(vol(S_k), 2|E| - vol(S_k)).
+ * For queries first_query_id .. first_query_id + n - 1 (all PPR and in the
+ * resident wave), evaluates the first min(support, max_size) prefixes,
+ * 1 <= max_size <= FORK_SWEEP_MAX, and writes one fork_sweep_t per query to
+ * out (host memory, n entries).  The first call builds the graph's reverse
+ * adjacency on the device (4|E| + 8|V| bytes, kept until fork_destroy).
+ * Errors: FORK_E_INVALID (bad range, type or max_size), FORK_E_STATE (a
+ * query that is not resident).
+ */
+int fork_sweep(fork_ctx *ctx, uint32_t first_query_id, uint32_t n, uint32_t max_size, fork_sweep_t *out);
 
 /*
  * Copy one query's result: field FORK_FIELD_VALUE (int32[V]), _P or _R

@@ -70,13 +70,21 @@ class fork_stats_t(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class fork_sweep_t(ctypes.Structure):
+    _fields_ = [("support", ctypes.c_uint32), ("swept", ctypes.c_uint32), ("best_size", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("best_conductance", ctypes.c_double), ("best_cut", ctypes.c_uint64),
+                ("best_volume", ctypes.c_uint64), ("size_min", ctypes.c_double * 11)]
+
+
 class fork_digest(ctypes.Structure):
     _fields_ = [("count", ctypes.c_uint64), ("sum", ctypes.c_uint64), ("hash", ctypes.c_uint64),
                 ("fsum", ctypes.c_double), ("fres", ctypes.c_double), ("fmax", ctypes.c_double)]
 
 
 EXPORTS = ["fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions",
-           "fork_trace", "fork_destroy", "fork_last_error", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train"]
+           "fork_trace", "fork_destroy", "fork_last_error", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train",
+           "fork_sweep"]
+SWEEP_MAX, SWEEP_BUCKETS = 1024, 11
 TRACE_WIDTH = 20
 
 
@@ -100,11 +108,12 @@ def _load():
     lib.fork_mlp_forward.argtypes = [P, P, U64, P]
     lib.fork_mlp_grad.argtypes = [P, P, P, U64, P, P]
     lib.fork_mlp_train.argtypes = [P, P, P, U64, U32, U32, ctypes.c_float, U64, P]
+    lib.fork_sweep.argtypes = [P, U32, U32, U32, P]
     lib.fork_destroy.argtypes = [P]
     lib.fork_destroy.restype = None
     lib.fork_last_error.restype = ctypes.c_char_p
     for n in ("fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions",
-              "fork_trace", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train"):
+              "fork_trace", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train", "fork_sweep"):
         getattr(lib, n).restype = I
     return lib
 
@@ -224,6 +233,20 @@ class ForkGraph:
         arr = np.empty(self.num_vertices, dtype)
         _check(lib.fork_fetch(self._ctx, qid, field, ctypes.c_void_p(arr.ctypes.data), arr.nbytes, 0))
         return arr
+
+    def sweep(self, first, n, max_size=SWEEP_MAX) -> list:
+        """Sweep cuts of resident PPR queries first .. first + n - 1 (see fork_sweep):
+        one dict per query with the best prefix and the least conductance per
+        size range [2^j, 2^(j+1))."""
+        arr = (fork_sweep_t * max(1, n))()
+        _check(lib.fork_sweep(self._ctx, first, n, max_size, ctypes.cast(arr, ctypes.c_void_p)))
+        out = []
+        for i in range(n):
+            r = arr[i]
+            out.append({"support": r.support, "swept": r.swept, "best_size": r.best_size, "flags": r.flags,
+                        "best_conductance": r.best_conductance, "best_cut": r.best_cut,
+                        "best_volume": r.best_volume, "size_min": list(r.size_min)})
+        return out
 
     def digest(self, qid) -> dict:
         d = fork_digest()

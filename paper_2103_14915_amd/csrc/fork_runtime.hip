@@ -29,6 +29,13 @@ hipError_t launch_fill64(unsigned long long*, unsigned long long, unsigned long 
 hipError_t launch_seed(const GraphDev&, const QueryDev&, const BufDev&, const uint32_t*, hipStream_t);
 hipError_t launch_digest(const QueryDev&, uint32_t, unsigned long long*, const uint32_t*, hipStream_t);
 hipError_t launch_gather(const uint32_t*, const uint32_t*, uint32_t*, uint32_t, hipStream_t);
+hipError_t launch_indeg(const uint32_t*, unsigned long long, uint32_t*, hipStream_t);
+hipError_t launch_rfill(const uint32_t*, const uint32_t*, uint32_t, const uint32_t*, uint32_t*, uint32_t*, hipStream_t);
+hipError_t launch_sdeg(const uint32_t*, const uint32_t*, uint32_t, uint32_t*, hipStream_t);
+hipError_t launch_sweep(const uint32_t*, const unsigned long long*, uint32_t, uint32_t, const uint32_t*, const uint32_t*,
+                        const uint32_t*, const uint32_t*, const uint32_t*, unsigned long long, uint32_t, void*,
+                        hipStream_t);
+size_t sweep_out_bytes();
 hipError_t launch_rnorm(const QueryDev&, uint32_t, const uint32_t*, uint32_t, double*, hipStream_t);
 hipError_t launch_rescan_items(const BufDev&, uint32_t, const uint32_t*, unsigned long long, uint32_t, hipStream_t);
 hipError_t launch_mlp_score(const GraphDev&, const BufDev&, const float*, float*, float*, void*, uint32_t, hipStream_t);
@@ -83,6 +90,8 @@ struct fork_ctx {
     uint32_t* d_pos = nullptr;     // [nv] internal position of caller vertex v
     uint32_t* d_orig = nullptr;    // [nv] caller id of internal vertex u
     uint32_t* d_gather = nullptr;  // [nv] staging for fetches to host memory
+    // reverse adjacency and undirected degrees (sweep cuts; built on first use)
+    uint32_t *d_rrow = nullptr, *d_rcol = nullptr, *d_sdeg = nullptr;
     // graph
     uint32_t* d_rowptr = nullptr;
     uint32_t* d_col = nullptr;
@@ -194,7 +203,7 @@ extern "C" void fork_destroy(fork_ctx* c) {
                     c->d_ccount, c->d_ring, c->d_pcount, c->d_pbest_sp, c->d_pbest_lv, c->d_pbest_pr,
                     c->d_pfirst, c->d_plast, c->d_pvisits, c->d_pn, c->d_sel, c->d_pqn, c->d_pready, c->d_pqmin,
                     c->d_score, c->d_mlp,
-                    c->d_ctl, c->d_gstat, c->d_feat, c->d_tr, c->d_final, c->d_pos, c->d_orig, c->d_gather};
+                    c->d_ctl, c->d_gstat, c->d_feat, c->d_tr, c->d_final, c->d_pos, c->d_orig, c->d_gather, c->d_rrow, c->d_rcol, c->d_sdeg};
     for (void* p : ptrs) if (p) hipFree(p);
     if (c->h_ctl) hipHostFree(c->h_ctl);
     for (auto& e : c->ev) if (e) hipEventDestroy(e);
@@ -1012,6 +1021,76 @@ extern "C" int fork_fetch(fork_ctx* c, uint32_t qid, int field, void* dst, uint6
         return FORK_OK;
     }
     HIPCHK(hipMemcpy(dst, src, (size_t)c->nv * 4, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return FORK_OK;
+}
+
+// Reverse adjacency (in-edges) and d(v) = out + in degree, on the device.
+static int build_reverse(fork_ctx* c) {
+    if (c->d_sdeg) return FORK_OK;
+    int rc;
+    uint32_t* indeg = nullptr;
+    if ((rc = dalloc(&indeg, c->nv))) return rc;
+    std::vector<uint32_t> h(c->nv);
+    hipError_t e = hipMemset(indeg, 0, (size_t)c->nv * 4);
+    if (e == hipSuccess) e = fk::launch_indeg(c->d_col, c->ne, indeg, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(h.data(), indeg, (size_t)c->nv * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { hipFree(indeg); return fail(FORK_E_DEVICE, "in-degrees: %s", hipGetErrorString(e)); }
+    std::vector<uint32_t> rrow(c->nv + 1, 0);
+    for (uint32_t v = 0; v < c->nv; ++v) rrow[v + 1] = rrow[v] + h[v];
+    if ((rc = dalloc(&c->d_rrow, c->nv + 1)) || (rc = dalloc(&c->d_rcol, c->ne)) || (rc = dalloc(&c->d_sdeg, c->nv))) {
+        hipFree(indeg);
+        hipFree(c->d_rrow); hipFree(c->d_rcol); hipFree(c->d_sdeg);
+        c->d_rrow = c->d_rcol = c->d_sdeg = nullptr;
+        return rc;
+    }
+    e = hipMemcpy(c->d_rrow, rrow.data(), (c->nv + 1ull) * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(indeg, 0, (size_t)c->nv * 4);  // reused as the fill cursor
+    if (e == hipSuccess) e = fk::launch_rfill(c->d_rowptr, c->d_col, c->nv, c->d_rrow, indeg, c->d_rcol, nullptr);
+    if (e == hipSuccess) e = fk::launch_sdeg(c->d_rowptr, c->d_rrow, c->nv, c->d_sdeg, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    hipFree(indeg);
+    if (e != hipSuccess) {
+        hipFree(c->d_rrow); hipFree(c->d_rcol); hipFree(c->d_sdeg);
+        c->d_rrow = c->d_rcol = c->d_sdeg = nullptr;
+        return fail(FORK_E_DEVICE, "reverse adjacency: %s", hipGetErrorString(e));
+    }
+    return FORK_OK;
+}
+
+extern "C" int fork_sweep(fork_ctx* c, uint32_t first, uint32_t n, uint32_t max_size, fork_sweep_t* out) {
+    g_err.clear();
+    if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
+    if (!out && n) return fail(FORK_E_INVALID, "out is NULL");
+    if (max_size < 1 || max_size > FORK_SWEEP_MAX) return fail(FORK_E_INVALID, "max_size must be in [1, %d]", FORK_SWEEP_MAX);
+    if ((uint64_t)first + n > c->queries.size()) return fail(FORK_E_INVALID, "query range out of bounds");
+    if (sizeof(fork_sweep_t) != fk::sweep_out_bytes()) return fail(FORK_E_DEVICE, "sweep record layout mismatch");
+    if (n == 0) return FORK_OK;
+    if (!c->ran) return fail(FORK_E_STATE, "queries have not run");
+    for (uint32_t i = first; i < first + n; ++i) {
+        if (c->queries[i].type != FORK_PPR) return fail(FORK_E_INVALID, "query %u is not PPR", i);
+        if (i < c->res_first || i >= c->res_first + c->res_n)
+            return fail(FORK_E_STATE, "query %u is not resident (only the last wave keeps vectors)", i);
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return fail(FORK_E_DEVICE, "hipSetDevice failed");
+    int rc = build_reverse(c);
+    if (rc) return rc;
+    std::vector<unsigned long long> off(n);
+    for (uint32_t i = 0; i < n; ++i) off[i] = c->res_off[first + i - c->res_first];
+    unsigned long long* d_off = nullptr;
+    void* d_out = nullptr;
+    if ((rc = dalloc(&d_off, n))) return rc;
+    if (hipMalloc(&d_out, (size_t)n * sizeof(fork_sweep_t)) != hipSuccess) {
+        hipFree(d_off);
+        return fail(FORK_E_NOMEM, "hipMalloc for sweep results failed");
+    }
+    hipError_t e = hipMemcpy(d_off, off.data(), (size_t)n * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = fk::launch_sweep(c->d_state, d_off, n, c->nv, c->d_rowptr, c->d_col, c->d_rrow, c->d_rcol, c->d_sdeg,
+                             2ull * c->ne, max_size, d_out, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, d_out, (size_t)n * sizeof(fork_sweep_t), hipMemcpyDeviceToHost);
+    hipFree(d_off);
+    hipFree(d_out);
+    if (e != hipSuccess) return fail(FORK_E_DEVICE, "sweep: %s", hipGetErrorString(e));
     return FORK_OK;
 }
 

@@ -36,14 +36,16 @@ def test_exports_every_declared_symbol(fork):
 def test_struct_layouts_match_c(fork, tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "fork.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(fork_config), sizeof(fork_ppr_params),'
-                    ' sizeof(fork_run_opts), sizeof(fork_stats_t), sizeof(fork_digest));return 0;}\n')
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(fork_config), sizeof(fork_ppr_params),'
+                    ' sizeof(fork_run_opts), sizeof(fork_stats_t), sizeof(fork_digest), sizeof(fork_sweep_t));'
+                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     sizes = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert sizes == [ctypes.sizeof(fork.fork_config), ctypes.sizeof(fork.fork_ppr_params),
                      ctypes.sizeof(fork.fork_run_opts), ctypes.sizeof(fork.fork_stats_t),
-                     ctypes.sizeof(fork.fork_digest)]
+                     ctypes.sizeof(fork.fork_digest), ctypes.sizeof(fork.fork_sweep_t)]
+    assert sizes[-1] == 128  # the device kernel's record: 4 x u32, f64, 2 x u64, 11 x f64
 
 
 def test_null_and_invalid_arguments(fork):

@@ -168,6 +168,21 @@ def test_rmat20_ppr4096_full():
     d = [fg.digest(i) for i in range(len(srcs))]
     assert all(x["fsum"] > 0.14 and x["fres"] >= 0 for x in d)
     check_ppr_sample(fork, fg, g, srcs, 0, spec, 8, 1)
+    # sweep cuts of every resident query (the NCP application), a sample against the oracle
+    import time
+    from oracle import ncp
+    fg.sweep(0, 4)  # builds the reverse adjacency
+    t0 = time.perf_counter()
+    res = fg.sweep(0, len(srcs), 1024)
+    say("sweep of", len(srcs), "queries:", round((time.perf_counter() - t0) * 1e3, 1), "ms")
+    assert all(r["flags"] == 0 and r["swept"] == min(r["support"], 1024) for r in res)
+    for i in np.random.default_rng(5).choice(len(srcs), 3, replace=False):
+        p = fg.fetch(int(i), fork.FIELD_P)
+        order, cut, vol, phi = ncp.sweep_profile(g, p, 1024)
+        k, best = ncp.best_cut(phi)
+        r = res[int(i)]
+        assert (r["best_size"], r["best_cut"], r["best_volume"]) == (k, int(cut[k - 1]), int(vol[k - 1]))
+        assert r["best_conductance"] == best
     fg.close()
 
 
