@@ -20,6 +20,8 @@ sequential algorithm, with no blocking or reordering):
 * ``mlp``         -- fp64 forward/backward of the partition-scoring MLP.
 * ``ncp``         -- sweep-cut conductance profiles of PPR vectors and the
                      network community profile (numpy).
+* ``bc``          -- Brandes' dependencies and betweenness centrality over
+                     a batch of sources (numpy, distances from ``sssp``/``bfs``).
 
 Readings where the paper is silent (no PPR formula, alpha, epsilon or
 dangling-vertex rule is printed): the walk is substochastic (a vertex without
