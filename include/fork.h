@@ -246,6 +246,21 @@ int fork_run(fork_ctx *ctx, const fork_run_opts *opts);
 int fork_sweep(fork_ctx *ctx, uint32_t first_query_id, uint32_t n, uint32_t max_size, fork_sweep_t *out);
 
 /*
+ * Betweenness centrality from resident BFS queries: the BC application
+ * (Sections 2 and 7.1: BFSs from sampled sources, then Brandes'
+ * accumulation of dependencies).  Shortest paths are counted as edge
+ * sequences of the multigraph.  For queries first_query_id ..
+ * first_query_id + n - 1 (all BFS and in the resident wave), writes
+ * out[v] = sum over their sources s of delta_s(v), with delta_s(s) = 0, as
+ * double[num_vertices] in the caller's ids (host memory).  Path counts are
+ * fp64 (exact up to 2^53).  Device scratch: 20 bytes per vertex per query,
+ * allocated for the call.  Errors: FORK_E_INVALID (bad range or type),
+ * FORK_E_STATE (not resident), FORK_E_CAPACITY (a query with more than
+ * 16,384 BFS levels).
+ */
+int fork_bc(fork_ctx *ctx, uint32_t first_query_id, uint32_t n, double *out);
+
+/*
  * Copy one query's result: field FORK_FIELD_VALUE (int32[V]), _P or _R
  * (float[V]) or _DIGEST (fork_digest).  dst_bytes must be large enough.
  * dst_on_device != 0: dst is a device pointer (device-to-device copy).

@@ -83,7 +83,7 @@ class fork_digest(ctypes.Structure):
 
 EXPORTS = ["fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions",
            "fork_trace", "fork_destroy", "fork_last_error", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train",
-           "fork_sweep"]
+           "fork_sweep", "fork_bc"]
 SWEEP_MAX, SWEEP_BUCKETS = 1024, 11
 TRACE_WIDTH = 20
 
@@ -109,11 +109,12 @@ def _load():
     lib.fork_mlp_grad.argtypes = [P, P, P, U64, P, P]
     lib.fork_mlp_train.argtypes = [P, P, P, U64, U32, U32, ctypes.c_float, U64, P]
     lib.fork_sweep.argtypes = [P, U32, U32, U32, P]
+    lib.fork_bc.argtypes = [P, U32, U32, P]
     lib.fork_destroy.argtypes = [P]
     lib.fork_destroy.restype = None
     lib.fork_last_error.restype = ctypes.c_char_p
     for n in ("fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions",
-              "fork_trace", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train", "fork_sweep"):
+              "fork_trace", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train", "fork_sweep", "fork_bc"):
         getattr(lib, n).restype = I
     return lib
 
@@ -246,6 +247,13 @@ class ForkGraph:
             out.append({"support": r.support, "swept": r.swept, "best_size": r.best_size, "flags": r.flags,
                         "best_conductance": r.best_conductance, "best_cut": r.best_cut,
                         "best_volume": r.best_volume, "size_min": list(r.size_min)})
+        return out
+
+    def bc(self, first, n) -> np.ndarray:
+        """Betweenness centrality from resident BFS queries first .. first + n - 1
+        (see fork_bc): float64 [V], the sum of the sources' dependencies."""
+        out = np.empty(self.num_vertices, np.float64)
+        _check(lib.fork_bc(self._ctx, first, n, ctypes.c_void_p(out.ctypes.data)))
         return out
 
     def digest(self, qid) -> dict:

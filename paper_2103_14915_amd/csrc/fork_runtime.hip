@@ -36,6 +36,10 @@ hipError_t launch_sweep(const uint32_t*, const unsigned long long*, uint32_t, ui
                         const uint32_t*, const uint32_t*, const uint32_t*, unsigned long long, uint32_t, void*,
                         hipStream_t);
 size_t sweep_out_bytes();
+hipError_t launch_bc(const uint32_t*, const unsigned long long*, const uint32_t*, uint32_t, uint32_t, const uint32_t*,
+                     const uint32_t*, const uint32_t*, const uint32_t*, uint32_t*, uint32_t*, double*, double*, double*,
+                     uint32_t*, hipStream_t);
+uint32_t bc_level_cap();
 hipError_t launch_rnorm(const QueryDev&, uint32_t, const uint32_t*, uint32_t, double*, hipStream_t);
 hipError_t launch_rescan_items(const BufDev&, uint32_t, const uint32_t*, unsigned long long, uint32_t, hipStream_t);
 hipError_t launch_mlp_score(const GraphDev&, const BufDev&, const float*, float*, float*, void*, uint32_t, hipStream_t);
@@ -1091,6 +1095,63 @@ extern "C" int fork_sweep(fork_ctx* c, uint32_t first, uint32_t n, uint32_t max_
     hipFree(d_off);
     hipFree(d_out);
     if (e != hipSuccess) return fail(FORK_E_DEVICE, "sweep: %s", hipGetErrorString(e));
+    return FORK_OK;
+}
+
+extern "C" int fork_bc(fork_ctx* c, uint32_t first, uint32_t n, double* out) {
+    g_err.clear();
+    if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
+    if (!out) return fail(FORK_E_INVALID, "out is NULL");
+    if ((uint64_t)first + n > c->queries.size()) return fail(FORK_E_INVALID, "query range out of bounds");
+    if (n && !c->ran) return fail(FORK_E_STATE, "queries have not run");
+    for (uint32_t i = first; i < first + n; ++i) {
+        if (c->queries[i].type != FORK_BFS) return fail(FORK_E_INVALID, "query %u is not BFS", i);
+        if (i < c->res_first || i >= c->res_first + c->res_n)
+            return fail(FORK_E_STATE, "query %u is not resident (only the last wave keeps vectors)", i);
+    }
+    if (n == 0) {
+        memset(out, 0, (size_t)c->nv * sizeof(double));
+        return FORK_OK;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return fail(FORK_E_DEVICE, "hipSetDevice failed");
+    int rc = build_reverse(c);
+    if (rc) return rc;
+    std::vector<unsigned long long> off(n);
+    std::vector<uint32_t> src(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        off[i] = c->res_off[first + i - c->res_first];
+        src[i] = c->queries[first + i].src;  // internal id
+    }
+    const size_t nv = c->nv, lcap = fk::bc_level_cap() + 2ull;
+    unsigned long long* d_off = nullptr;
+    uint32_t *d_src = nullptr, *d_order = nullptr, *d_ls = nullptr, *d_err = nullptr;
+    double *d_sigma = nullptr, *d_delta = nullptr, *d_bc = nullptr;
+    auto release = [&]() {
+        hipFree(d_off); hipFree(d_src); hipFree(d_order); hipFree(d_ls); hipFree(d_err);
+        hipFree(d_sigma); hipFree(d_delta); hipFree(d_bc);
+    };
+    if ((rc = dalloc(&d_off, n)) || (rc = dalloc(&d_src, n)) || (rc = dalloc(&d_order, (size_t)n * nv)) ||
+        (rc = dalloc(&d_ls, (size_t)n * lcap)) || (rc = dalloc(&d_err, 1)) || (rc = dalloc(&d_sigma, (size_t)n * nv)) ||
+        (rc = dalloc(&d_delta, (size_t)n * nv)) || (rc = dalloc(&d_bc, nv))) {
+        release();
+        return rc;
+    }
+    std::vector<double> h(nv);
+    uint32_t herr = 0;
+    hipError_t e = hipMemcpy(d_off, off.data(), n * 8ull, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_src, src.data(), n * 4ull, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(d_bc, 0, nv * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(d_err, 0, 4);
+    if (e == hipSuccess)
+        e = fk::launch_bc(c->d_state, d_off, d_src, n, c->nv, c->d_rowptr, c->d_col, c->d_rrow, c->d_rcol, d_order,
+                          d_ls, d_sigma, d_delta, d_bc, d_err, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(h.data(), d_bc, nv * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&herr, d_err, 4, hipMemcpyDeviceToHost);
+    release();
+    if (e != hipSuccess) return fail(FORK_E_DEVICE, "bc: %s", hipGetErrorString(e));
+    if (herr) return fail(FORK_E_CAPACITY, "a query has more than %u BFS levels", fk::bc_level_cap());
+    if (c->h_pos.empty()) memcpy(out, h.data(), nv * sizeof(double));
+    else for (size_t v = 0; v < nv; ++v) out[v] = h[c->h_pos[v]];
     return FORK_OK;
 }
 

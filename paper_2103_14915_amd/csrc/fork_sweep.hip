@@ -308,4 +308,126 @@ hipError_t launch_sweep(const uint32_t* state, const unsigned long long* qoff, u
 }
 size_t sweep_out_bytes() { return sizeof(SweepOut); }
 
+// ------------------------------------------------------------ betweenness
+// Brandes' accumulation over resident BFS queries (the BC application of
+// Sections 2 and 7.1: many BFSs from sampled sources, then dependencies).
+// One workgroup per query, in three steps over the query's levels:
+//   1. counting sort of the reached vertices by level (per-query scratch);
+//   2. sigma (shortest-path counts, fp64), level by level: sigma(v) = sum
+//      over in-edges (u, v) with level(u) = level(v) - 1 of sigma(u);
+//   3. delta, from the deepest level up: delta(v) = sum over out-edges (v, w)
+//      with level(w) = level(v) + 1 of sigma(v) / sigma(w) * (1 + delta(w));
+//      every vertex but the source adds delta(v) to bc[v].
+constexpr int BC_NT = 1024;
+constexpr uint32_t BC_LMAX = 16384;  // most levels per query (the scratch size)
+
+struct BcScratch {
+    uint32_t* order;     // [nq][nv] vertices by level
+    uint32_t* lstart;    // [nq][BC_LMAX + 2] level starts (then fill cursors)
+    double* sigma;       // [nq][nv]
+    double* delta;       // [nq][nv]
+};
+
+__global__ __launch_bounds__(BC_NT) void k_bc(const uint32_t* state, const unsigned long long* qoff, const uint32_t* src,
+                                             uint32_t nv, const uint32_t* rowptr, const uint32_t* col,
+                                             const uint32_t* rrow, const uint32_t* rcol, BcScratch sc, double* bc,
+                                             uint32_t* err) {
+    const uint32_t t = threadIdx.x, q = blockIdx.x;
+    const uint32_t* level = state + qoff[q];
+    uint32_t* order = sc.order + (unsigned long long)q * nv;
+    uint32_t* ls = sc.lstart + (unsigned long long)q * (BC_LMAX + 2);
+    double* sigma = sc.sigma + (unsigned long long)q * nv;
+    double* delta = sc.delta + (unsigned long long)q * nv;
+    __shared__ uint32_t s_max, s_bad;
+    __shared__ uint32_t s_w[BC_NT / WAVE];
+    if (t == 0) { s_max = 0; s_bad = 0; }
+    for (uint32_t i = t; i < BC_LMAX + 2; i += BC_NT) ls[i] = 0;
+    __syncthreads();
+    // 1. level histogram
+    for (uint32_t v = t; v < nv; v += BC_NT) {
+        const uint32_t l = level[v];
+        sigma[v] = 0.0;
+        delta[v] = 0.0;
+        if (l == INF) continue;
+        if (l >= BC_LMAX) { s_bad = 1; continue; }
+        atomicAdd(&ls[l + 1], 1u);
+        atomicMax(&s_max, l);
+    }
+    __syncthreads();
+    if (s_bad) {
+        if (t == 0) atomicOr(err, 1u);
+        return;
+    }
+    const uint32_t L = s_max;  // deepest level
+    // exclusive prefix over levels 0..L (ls[l] = start of level l), chunked by the block
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 <= L + 1; b0 += BC_NT) {
+        const uint32_t i = b0 + t;
+        uint32_t x = i <= L + 1 ? ls[i] : 0u;
+        const uint32_t lane = t & (WAVE - 1), w = t / WAVE;
+        uint32_t incl = wscan_incl(x, lane);
+        if (lane == WAVE - 1) s_w[w] = incl;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (uint32_t k = 0; k < BC_NT / WAVE; ++k) { before += k < w ? s_w[k] : 0u; tot += s_w[k]; }
+        __syncthreads();
+        if (i <= L + 1) ls[i] = carry + before + incl;  // inclusive over shifted counts = start of level i
+        carry += tot;
+        __syncthreads();
+    }
+    // scatter: ls[l] (the start of level l) is level l's fill cursor, so it
+    // ends as the end of level l; level l then spans [ls[l - 1], ls[l]) (from 0 for l = 0)
+    for (uint32_t v = t; v < nv; v += BC_NT) {
+        const uint32_t l = level[v];
+        if (l == INF) continue;
+        order[atomicAdd(&ls[l], 1u)] = v;
+    }
+    __syncthreads();
+    // 2. sigma
+    if (t == 0) sigma[src[q]] = 1.0;
+    __syncthreads();
+    for (uint32_t l = 1; l <= L; ++l) {
+        const uint32_t b = ls[l - 1], e = ls[l];
+        for (uint32_t i = b + t; i < e; i += BC_NT) {
+            const uint32_t v = order[i];
+            double s = 0.0;
+            for (uint32_t k = rrow[v]; k < rrow[v + 1]; ++k) {
+                const uint32_t u = rcol[k];
+                if (level[u] == l - 1) s += sigma[u];
+            }
+            sigma[v] = s;
+        }
+        __syncthreads();
+    }
+    // 3. delta
+    for (int l = (int)L - 1; l >= 0; --l) {
+        const uint32_t b = l ? ls[l - 1] : 0u, e = ls[l];
+        for (uint32_t i = b + t; i < e; i += BC_NT) {
+            const uint32_t v = order[i];
+            double a = 0.0;
+            const double sv = sigma[v];
+            for (uint32_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+                const uint32_t w = col[k];
+                if (level[w] == (uint32_t)l + 1) a += sv / sigma[w] * (1.0 + delta[w]);
+            }
+            delta[v] = a;
+        }
+        __syncthreads();
+    }
+    const uint32_t s0 = src[q];
+    for (uint32_t v = t; v < nv; v += BC_NT)
+        if (v != s0 && level[v] != INF && delta[v] != 0.0) atomicAdd(&bc[v], delta[v]);
+}
+
+hipError_t launch_bc(const uint32_t* state, const unsigned long long* qoff, const uint32_t* src, uint32_t nq,
+                     uint32_t nv, const uint32_t* rowptr, const uint32_t* col, const uint32_t* rrow,
+                     const uint32_t* rcol, uint32_t* order, uint32_t* lstart, double* sigma, double* delta,
+                     double* bc, uint32_t* err, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    BcScratch sc{order, lstart, sigma, delta};
+    hipLaunchKernelGGL(k_bc, dim3(nq), dim3(BC_NT), 0, s, state, qoff, src, nv, rowptr, col, rrow, rcol, sc, bc, err);
+    return hipGetLastError();
+}
+uint32_t bc_level_cap() { return BC_LMAX; }
+
 }  // namespace fk
