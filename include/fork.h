@@ -253,10 +253,14 @@ int fork_sweep(fork_ctx *ctx, uint32_t first_query_id, uint32_t n, uint32_t max_
  * first_query_id + n - 1 (all BFS and in the resident wave), writes
  * out[v] = sum over their sources s of delta_s(v), with delta_s(s) = 0, as
  * double[num_vertices] in the caller's ids (host memory).  Path counts are
- * fp64 (exact up to 2^53).  Device scratch: 20 bytes per vertex per query,
- * allocated for the call.  Errors: FORK_E_INVALID (bad range or type),
- * FORK_E_STATE (not resident), FORK_E_CAPACITY (a query with more than
- * 16,384 BFS levels).
+ * kept in fp64 divided by each BFS level's largest count, so they do not
+ * overflow on graphs with astronomically many shortest paths.  Device
+ * scratch: about 20 bytes per vertex per query, allocated for the call.
+ * Errors: FORK_E_INVALID (bad range or type), FORK_E_STATE (not resident),
+ * FORK_E_CAPACITY (a query with more than 16,384 BFS levels, or path counts
+ * within one level that differ by more than fp64's range, as between the
+ * middle and the ends of a level of a grid of roughly 1,000 x 1,000 or more
+ * seen from a corner; no non-finite value is ever returned).
  */
 int fork_bc(fork_ctx *ctx, uint32_t first_query_id, uint32_t n, double *out);
 

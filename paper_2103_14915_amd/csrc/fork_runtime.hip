@@ -38,7 +38,7 @@ hipError_t launch_sweep(const uint32_t*, const unsigned long long*, uint32_t, ui
 size_t sweep_out_bytes();
 hipError_t launch_bc(const uint32_t*, const unsigned long long*, const uint32_t*, uint32_t, uint32_t, const uint32_t*,
                      const uint32_t*, const uint32_t*, const uint32_t*, uint32_t*, uint32_t*, double*, double*, double*,
-                     uint32_t*, hipStream_t);
+                     double*, uint32_t*, hipStream_t);
 uint32_t bc_level_cap();
 hipError_t launch_rnorm(const QueryDev&, uint32_t, const uint32_t*, uint32_t, double*, hipStream_t);
 hipError_t launch_rescan_items(const BufDev&, uint32_t, const uint32_t*, unsigned long long, uint32_t, hipStream_t);
@@ -1125,14 +1125,15 @@ extern "C" int fork_bc(fork_ctx* c, uint32_t first, uint32_t n, double* out) {
     const size_t nv = c->nv, lcap = fk::bc_level_cap() + 2ull;
     unsigned long long* d_off = nullptr;
     uint32_t *d_src = nullptr, *d_order = nullptr, *d_ls = nullptr, *d_err = nullptr;
-    double *d_sigma = nullptr, *d_delta = nullptr, *d_bc = nullptr;
+    double *d_sigma = nullptr, *d_delta = nullptr, *d_gain = nullptr, *d_bc = nullptr;
     auto release = [&]() {
         hipFree(d_off); hipFree(d_src); hipFree(d_order); hipFree(d_ls); hipFree(d_err);
-        hipFree(d_sigma); hipFree(d_delta); hipFree(d_bc);
+        hipFree(d_sigma); hipFree(d_delta); hipFree(d_gain); hipFree(d_bc);
     };
     if ((rc = dalloc(&d_off, n)) || (rc = dalloc(&d_src, n)) || (rc = dalloc(&d_order, (size_t)n * nv)) ||
         (rc = dalloc(&d_ls, (size_t)n * lcap)) || (rc = dalloc(&d_err, 1)) || (rc = dalloc(&d_sigma, (size_t)n * nv)) ||
-        (rc = dalloc(&d_delta, (size_t)n * nv)) || (rc = dalloc(&d_bc, nv))) {
+        (rc = dalloc(&d_delta, (size_t)n * nv)) || (rc = dalloc(&d_gain, (size_t)n * lcap)) ||
+        (rc = dalloc(&d_bc, nv))) {
         release();
         return rc;
     }
@@ -1144,12 +1145,16 @@ extern "C" int fork_bc(fork_ctx* c, uint32_t first, uint32_t n, double* out) {
     if (e == hipSuccess) e = hipMemset(d_err, 0, 4);
     if (e == hipSuccess)
         e = fk::launch_bc(c->d_state, d_off, d_src, n, c->nv, c->d_rowptr, c->d_col, c->d_rrow, c->d_rcol, d_order,
-                          d_ls, d_sigma, d_delta, d_bc, d_err, nullptr);
+                          d_ls, d_sigma, d_delta, d_gain, d_bc, d_err, nullptr);
     if (e == hipSuccess) e = hipMemcpy(h.data(), d_bc, nv * sizeof(double), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(&herr, d_err, 4, hipMemcpyDeviceToHost);
     release();
     if (e != hipSuccess) return fail(FORK_E_DEVICE, "bc: %s", hipGetErrorString(e));
     if (herr) return fail(FORK_E_CAPACITY, "a query has more than %u BFS levels", fk::bc_level_cap());
+    for (size_t v = 0; v < nv; ++v)
+        if (!std::isfinite(h[v]))
+            return fail(FORK_E_CAPACITY, "path-count ratios within a BFS level leave the fp64 range (vertex %zu); "
+                        "the graph has too many shortest paths of too uneven counts", v);
     if (c->h_pos.empty()) memcpy(out, h.data(), nv * sizeof(double));
     else for (size_t v = 0; v < nv; ++v) out[v] = h[c->h_pos[v]];
     return FORK_OK;

@@ -314,18 +314,24 @@ size_t sweep_out_bytes() { return sizeof(SweepOut); }
 // One workgroup per query, in three steps over the query's levels:
 //   1. counting sort of the reached vertices by level (per-query scratch);
 //   2. sigma (shortest-path counts, fp64), level by level: sigma(v) = sum
-//      over in-edges (u, v) with level(u) = level(v) - 1 of sigma(u);
+//      over in-edges (u, v) with level(u) = level(v) - 1 of sigma(u).  Counts
+//      grow exponentially with depth (a 2048 x 2048 grid has about 10^1230
+//      corner-to-corner paths), so each level is stored divided by its
+//      largest count m_l: s(v) = sigma(v) / (m_1 ... m_l), and only the
+//      per-level factor g_l = m_l (relative to the level before) is kept;
 //   3. delta, from the deepest level up: delta(v) = sum over out-edges (v, w)
-//      with level(w) = level(v) + 1 of sigma(v) / sigma(w) * (1 + delta(w));
-//      every vertex but the source adds delta(v) to bc[v].
+//      with level(w) = level(v) + 1 of sigma(v) / sigma(w) * (1 + delta(w)),
+//      where sigma(v) / sigma(w) = s(v) / (s(w) * g_(l+1)); every vertex but
+//      the source adds delta(v) to bc[v].
 constexpr int BC_NT = 1024;
 constexpr uint32_t BC_LMAX = 16384;  // most levels per query (the scratch size)
 
 struct BcScratch {
     uint32_t* order;     // [nq][nv] vertices by level
     uint32_t* lstart;    // [nq][BC_LMAX + 2] level starts (then fill cursors)
-    double* sigma;       // [nq][nv]
+    double* sigma;       // [nq][nv] path counts, scaled per level
     double* delta;       // [nq][nv]
+    double* gain;        // [nq][BC_LMAX + 2] per-level scale factors
 };
 
 __global__ __launch_bounds__(BC_NT) void k_bc(const uint32_t* state, const unsigned long long* qoff, const uint32_t* src,
@@ -338,7 +344,9 @@ __global__ __launch_bounds__(BC_NT) void k_bc(const uint32_t* state, const unsig
     uint32_t* ls = sc.lstart + (unsigned long long)q * (BC_LMAX + 2);
     double* sigma = sc.sigma + (unsigned long long)q * nv;
     double* delta = sc.delta + (unsigned long long)q * nv;
+    double* gain = sc.gain + (unsigned long long)q * (BC_LMAX + 2);
     __shared__ uint32_t s_max, s_bad;
+    __shared__ unsigned long long s_lmax;
     __shared__ uint32_t s_w[BC_NT / WAVE];
     if (t == 0) { s_max = 0; s_bad = 0; }
     for (uint32_t i = t; i < BC_LMAX + 2; i += BC_NT) ls[i] = 0;
@@ -388,6 +396,8 @@ __global__ __launch_bounds__(BC_NT) void k_bc(const uint32_t* state, const unsig
     __syncthreads();
     for (uint32_t l = 1; l <= L; ++l) {
         const uint32_t b = ls[l - 1], e = ls[l];
+        if (t == 0) s_lmax = 0ull;
+        __syncthreads();
         for (uint32_t i = b + t; i < e; i += BC_NT) {
             const uint32_t v = order[i];
             double s = 0.0;
@@ -396,19 +406,25 @@ __global__ __launch_bounds__(BC_NT) void k_bc(const uint32_t* state, const unsig
                 if (level[u] == l - 1) s += sigma[u];
             }
             sigma[v] = s;
+            atomicMax(&s_lmax, (unsigned long long)__double_as_longlong(s));  // positive doubles order like their bits
         }
+        __syncthreads();
+        const double m = __longlong_as_double((long long)s_lmax);  // > 0: every vertex of the level has a predecessor
+        for (uint32_t i = b + t; i < e; i += BC_NT) sigma[order[i]] /= m;
+        if (t == 0) gain[l] = m;
         __syncthreads();
     }
     // 3. delta
     for (int l = (int)L - 1; l >= 0; --l) {
         const uint32_t b = l ? ls[l - 1] : 0u, e = ls[l];
+        const double gnext = gain[l + 1];
         for (uint32_t i = b + t; i < e; i += BC_NT) {
             const uint32_t v = order[i];
             double a = 0.0;
             const double sv = sigma[v];
             for (uint32_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
                 const uint32_t w = col[k];
-                if (level[w] == (uint32_t)l + 1) a += sv / sigma[w] * (1.0 + delta[w]);
+                if (level[w] == (uint32_t)l + 1) a += sv / (sigma[w] * gnext) * (1.0 + delta[w]);
             }
             delta[v] = a;
         }
@@ -422,9 +438,9 @@ __global__ __launch_bounds__(BC_NT) void k_bc(const uint32_t* state, const unsig
 hipError_t launch_bc(const uint32_t* state, const unsigned long long* qoff, const uint32_t* src, uint32_t nq,
                      uint32_t nv, const uint32_t* rowptr, const uint32_t* col, const uint32_t* rrow,
                      const uint32_t* rcol, uint32_t* order, uint32_t* lstart, double* sigma, double* delta,
-                     double* bc, uint32_t* err, hipStream_t s) {
+                     double* gain, double* bc, uint32_t* err, hipStream_t s) {
     if (nq == 0) return hipSuccess;
-    BcScratch sc{order, lstart, sigma, delta};
+    BcScratch sc{order, lstart, sigma, delta, gain};
     hipLaunchKernelGGL(k_bc, dim3(nq), dim3(BC_NT), 0, s, state, qoff, src, nv, rowptr, col, rrow, rcol, sc, bc, err);
     return hipGetLastError();
 }

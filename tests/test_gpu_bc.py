@@ -68,3 +68,26 @@ def test_bc_errors():
     assert one.shape == (g.num_vertices,) and np.all(one >= 0)
     assert np.all(fg.bc(last, 0) == 0)
     fg.close()
+
+
+def test_bc_on_a_grid_whose_path_counts_overflow_fp64():
+    """On a 640 x 640 grid a corner has about 10^360 shortest paths to the
+    opposite corner, beyond fp64, so plain path counts overflow.  The scaled
+    counts must stay finite, and the total is fixed.  Every shortest s-t path
+    of unit-weight edges has d(s, t) - 1 interior vertices, so summing the
+    dependencies over all vertices gives sum over t of (d(s, t) - 1) per
+    source.  The levels come from the oracle's BFS."""
+    import oracle
+    fork = _fork()
+    n = 640
+    g = fi.grid(n, n, weights=None)
+    srcs = np.array([0, n - 1, n * n - 1, (n // 2) * n + n // 3], np.uint32)  # three corners and an inner vertex
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=8192)
+    first = fg.submit("bfs", srcs)
+    fg.run(max_passes=400000)
+    got = fg.bc(first, len(srcs))
+    fg.close()
+    assert np.all(np.isfinite(got)) and np.all(got >= 0)
+    lv = oracle.bfs(g, srcs).astype(np.int64)
+    expect = float(sum(np.sum(lv[i][lv[i] > 0] - 1) for i in range(len(srcs))))
+    assert got.sum() == pytest.approx(expect, rel=1e-9)
