@@ -54,3 +54,19 @@ def test_rcm_and_auto():
     p = order.auto({"kind": "grid", "rows": 256, "cols": 256}, fi.grid(256, 256, weights=None), pv)
     r, c = np.divmod(np.arange(256 * 256), 256)
     assert np.all(p // pv == (r // 64) * 2 + c // 128)
+
+
+def test_rcm_recovers_a_small_bandwidth_from_a_shuffled_grid():
+    """A 20 x 20 grid under a random relabelling has bandwidth close to |V|;
+    reverse Cuthill-McKee must bring it back to about a row or two."""
+    g0 = fi.grid(20, 20, weights=None)
+    perm = np.random.default_rng(3).permutation(g0.num_vertices)
+    src = np.repeat(np.arange(g0.num_vertices), np.diff(g0.row_ptr.astype(np.int64)))
+    g = fi.from_edges(g0.num_vertices, perm[src], perm[g0.col.astype(np.int64)])
+    s2 = np.repeat(np.arange(g.num_vertices), np.diff(g.row_ptr.astype(np.int64)))
+
+    def bandwidth(pos):
+        return int(np.max(np.abs(pos[s2].astype(np.int64) - pos[g.col.astype(np.int64)].astype(np.int64))))
+
+    assert bandwidth(order.identity(g.num_vertices)) > 300
+    assert bandwidth(order.rcm(g)) <= 2 * 20 + 1
