@@ -56,3 +56,18 @@ def test_diamond_with_parallel_edges_by_hand():
     g2 = fi.from_edges(4, [0, 0, 0, 1, 2], [1, 1, 2, 3, 3], [1, 5, 1, 1, 1])
     np.testing.assert_allclose(bc.dependencies(g2, [0], unit=False)[0], [0.0, 0.5, 0.5, 0.0])
     np.testing.assert_allclose(bc.dependencies(g2, [0], unit=True)[0], [0.0, 2.0 / 3.0, 1.0 / 3.0, 0.0])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dependencies_sum_to_interior_vertices(seed):
+    """With unit weights every shortest s-t path has d(s, t) - 1 interior
+    vertices, so a source's dependencies sum to the sum over reached t of
+    d(s, t) - 1 (levels from the oracle's BFS)."""
+    import oracle
+    g = fi.rmat(8, seed=600 + seed)
+    srcs = fi.sources_uniform(g, 5, 700 + seed)
+    dep = bc.dependencies(g, srcs, unit=True)
+    lv = oracle.bfs(g, srcs).astype(np.int64)
+    for i in range(len(srcs)):
+        reached = lv[i][(lv[i] > 0) & (lv[i] != 0x7FFFFFFF)]
+        assert dep[i].sum() == pytest.approx(float(np.sum(reached - 1)), rel=1e-12)
