@@ -128,3 +128,33 @@ def test_learned_vs_rule_measured_on_the_same_queries():
     say(f"learned vs rule on R-MAT 17 (128 SSSP + 64 PPR): speedup {ratio:.3f} "
         f"(rule {best['priority'] * 1e3:.1f} ms, learned {best['learned'] * 1e3:.1f} ms)")
     assert ratio > 0.25  # no pathological slowdown
+
+
+@pytest.mark.parametrize("lr", [1e-3, 3e-2])
+def test_adam_steps_on_gpu_match_the_fp64_oracle(lr):
+    """Two fork_mlp_train steps with the whole sample set as the batch against
+    oracle.mlp.adam_step fed with the fp64 gradient.  The batch is then the
+    full set at every step, so the GPU's update is the oracle's up to fp32
+    rounding of the gradient.  Where that rounding can flip a gradient's sign
+    (|g| near zero) Adam's step is bounded by lr per step instead."""
+    fork = _fork()
+    rng = np.random.default_rng(11)
+    n = 300
+    x = rng.normal(size=(n, 16)).astype(np.float32)
+    t = (x[:, 0] - 0.5 * np.abs(x[:, 1])).astype(np.float32)
+    theta0 = (omlp.init(9) + rng.normal(0, 0.01, omlp.N_PARAMS)).astype(np.float32)
+    th64 = theta0.astype(np.float64)
+    m = np.zeros(omlp.N_PARAMS)
+    v = np.zeros(omlp.N_PARAMS)
+    gmin = np.full(omlp.N_PARAMS, np.inf)
+    for step in (1, 2):
+        _, g64 = omlp.loss_and_grad(th64, x.astype(np.float64), t.astype(np.float64))
+        gmin = np.minimum(gmin, np.abs(g64))
+        th64, m, v = omlp.adam_step(th64, g64, m, v, step, lr=lr)
+        th_gpu, losses = fork.mlp_train(theta0, x, t, steps=step, batch=n, lr=lr, seed=3)
+        say("adam step", step, "lr", lr, "loss", float(losses[-1]))
+        sure = gmin > 1e-4  # gradient well above fp32 rounding at every step so far
+        assert sure.sum() > 0.5 * omlp.N_PARAMS
+        np.testing.assert_allclose(th_gpu[sure], th64[sure], rtol=0, atol=1e-5 * lr + 1e-6 * np.abs(th64[sure]).max())
+        # every coordinate moved by at most lr per step (Adam's bias-corrected step size)
+        assert np.all(np.abs(th_gpu.astype(np.float64) - theta0) <= step * lr * (1 + 1e-5) + 1e-7)

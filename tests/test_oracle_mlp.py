@@ -77,3 +77,49 @@ def test_adam_decreases_loss():
         _, g = mlp.loss_and_grad(theta, x, t)
         theta, m, v = mlp.adam_step(theta, g, m, v, k, lr=3e-3)
     assert mlp.loss_and_grad(theta, x, t)[0] < 0.1 * l0
+
+
+def test_adam_first_step_is_bias_corrected():
+    """At t = 1 the bias-corrected moments are m^ = g and v^ = g^2 exactly, so
+    every coordinate moves by lr * g / (|g| + eps): almost exactly lr against
+    the sign of its gradient, whatever the gradient's size.  Without the bias
+    correction the step would be lr * (1 - b1) / sqrt(1 - b2) ~ 3.16 lr."""
+    lr = 0.1
+    theta0 = np.array([1.0, -2.0, 0.5, 3.0])
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    th, m, v = mlp.adam_step(theta0, g, np.zeros(4), np.zeros(4), 1, lr=lr)
+    step = theta0 - th
+    np.testing.assert_allclose(step[:3], lr * np.sign(g[:3]), rtol=1e-5)
+    assert step[3] == 0.0
+    # the raw moments are the first exponential-average terms
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-12)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-12)
+
+
+def test_adam_second_step_after_a_sign_flip():
+    """Gradient +1 at t = 1 and -1 at t = 2.  Worked by hand with b1 = 0.9,
+    b2 = 0.999: m2 = b1 (1-b1) - (1-b1) = -(1-b1)^2 = -0.01 and the correction
+    1 - b1^2 = 0.19 give m^ = -1/19; v2 = b2 (1-b2) + (1-b2) = 1 - b2^2, so
+    v^ = 1.  The second step therefore raises theta by lr/19 / (1 + eps).
+    Swapping b1 and b2 would give m^ = -(1-b2)^2/(1-b2^2), about -5e-4."""
+    lr = 0.05
+    th, m, v = mlp.adam_step(np.array([0.0]), np.array([1.0]), np.zeros(1), np.zeros(1), 1, lr=lr)
+    np.testing.assert_allclose(th, [-lr], rtol=1e-7)
+    th2, m2, v2 = mlp.adam_step(th, np.array([-1.0]), m, v, 2, lr=lr)
+    np.testing.assert_allclose(m2, [-0.01], rtol=1e-12)
+    np.testing.assert_allclose(v2, [1 - 0.999 ** 2], rtol=1e-12)
+    np.testing.assert_allclose(th2 - th, [lr / 19 / (1 + 1e-8)], rtol=1e-12)
+
+
+def test_adam_constant_gradient_gives_constant_steps():
+    """With a constant gradient the bias-corrected averages equal g and g^2 at
+    every step, so each step is the same lr * g / (|g| + eps)."""
+    lr = 0.01
+    g = np.array([3.0, -0.25])
+    th = np.zeros(2)
+    m = np.zeros(2)
+    v = np.zeros(2)
+    for t in range(1, 30):
+        nth, m, v = mlp.adam_step(th, g, m, v, t, lr=lr)
+        np.testing.assert_allclose(th - nth, lr * g / (np.abs(g) + 1e-8), rtol=1e-9)
+        th = nth

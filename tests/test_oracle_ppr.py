@@ -112,3 +112,37 @@ def test_invariant_detects_planted_mistake():
     r_bad = r[0].copy()
     r_bad[np.argmax(r_bad)] = 0.0
     assert oracle.ppr_invariant_l1(g, 0, p[0], r_bad, ALPHA) > 1e-7
+
+
+def test_push_terminal_fp32_threshold_decision():
+    """The GPU keeps r in fp32 and decides a push with thr = fp32(eps) (mode 0)
+    or fp32(eps) * fp32(outdeg) (mode 1) in fp32; push_terminal(dtype=float32)
+    takes the same decision.  A residual planted exactly at the fp32
+    threshold is active; one fp32 ulp below it is not."""
+    # vertex 0 has out-degree 3, vertex 1 out-degree 1, vertex 2 none
+    g = fi.from_edges(3, [0, 0, 0, 1], [1, 2, 2, 0])
+    eps = 1e-6  # not representable in fp32: fp32(eps) < eps
+    e32 = np.float32(eps)
+    assert float(e32) < eps
+    for mode in (0, 1):
+        for v in (0, 1, 2):
+            d = int(g.out_degree()[v])
+            thr32 = np.float32(e32 * np.float32(d)) if mode else e32
+            if mode and d == 0:
+                continue  # threshold 0: any positive residual is active
+            r = np.zeros(3, np.float32)
+            r[v] = thr32
+            assert not oracle.push_terminal(g, r, eps, mode, dtype=np.float32), (mode, v)
+            r[v] = np.nextafter(thr32, np.float32(0))
+            assert oracle.push_terminal(g, r, eps, mode, dtype=np.float32), (mode, v)
+    # the fp64 decision differs exactly here: fp32(eps) is below eps in fp64
+    r = np.zeros(3, np.float32)
+    r[1] = e32
+    assert oracle.push_terminal(g, r, eps, 0, dtype=np.float64)
+    assert not oracle.push_terminal(g, r, eps, 0, dtype=np.float32)
+    # a dangling vertex in mode 1 has threshold 0: any positive residual is active
+    r = np.zeros(3, np.float32)
+    r[2] = np.float32(1e-30)
+    assert not oracle.push_terminal(g, r, eps, 1, dtype=np.float32)
+    r[2] = 0.0
+    assert oracle.push_terminal(g, r, eps, 1, dtype=np.float32)
