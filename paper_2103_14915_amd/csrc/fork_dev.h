@@ -42,6 +42,8 @@ struct Ctl {
     unsigned long long c_edges, c_improved, c_emitted, c_consumed, c_vpush, c_yields, c_chunks,
         c_items, c_passes_nonempty, c_intra, c_pruned;
     unsigned long long pending_ops; // operations buffered at select time
+    unsigned int stop;              // set by the select step only: no work left, or a device error
+                                    // (the persistent kernel's exit test, the same for every block)
 };
 
 // A (partition, query) work item of one pass.

@@ -1153,7 +1153,12 @@ __global__ __launch_bounds__(NT) void k_persistent(GraphDev g, QueryDev Q, BufDe
             select_body<NT>(g, B, cfg, (unsigned long long*)dyn, (unsigned int*)((unsigned long long*)dyn + cap), cap);
         }
         grid.sync();
-        if (B.ctl->pending_parts == 0 || B.ctl->err) break;
+        // Every block takes the same exit decision: `stop` is written only by
+        // the select step above, while the other blocks wait at the barrier,
+        // and nothing writes it again before the next select.  (ctl->err can
+        // be raised by a fast block's detach below while a slow block is
+        // still reading it, so it must not decide the exit.)
+        if (__hip_atomic_load(&B.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         const uint32_t nsel = B.ctl->nsel;
         const uint32_t nqp = (Q.nq + WAVE - 1) / WAVE * WAVE;
         const unsigned long long total = (unsigned long long)nsel * nqp;

@@ -27,7 +27,7 @@ __device__ void select_body(const GraphDev& g, const BufDev& B, const PassCfg& c
     const uint32_t np = g.np;
     const uint32_t tid = threadIdx.x;
     if (ctl->err) {  // a failed pass ends the run: select nothing
-        if (tid == 0) { ctl->nsel = 0; ctl->pending_parts = 0; }
+        if (tid == 0) { ctl->nsel = 0; ctl->pending_parts = 0; ctl->stop = 1u; }
         return;
     }
     const uint32_t pass = ctl->pass + 1;
@@ -161,6 +161,7 @@ __device__ void select_body(const GraphDev& g, const BufDev& B, const PassCfg& c
         ctl->nsel = nsel;
         ctl->pending_parts = total_pend;
         ctl->pending_ops = s_pend;
+        ctl->stop = total_pend == 0 ? 1u : 0u;
         ctl->avail_end = ctl->ring_tail;
         ctl->pass = pass;
         if (nsel) ctl->c_passes_nonempty += 1;
