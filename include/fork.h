@@ -71,7 +71,7 @@ typedef struct {
                                     road network) cuts fewer edges; the paper's
                                     partitioner study credits locality-aware
                                     partitions with large gains over random
-                                    ones (Section 7.3).  Sources, results and
+                                    ones (Appendix C).  Sources, results and
                                     digests always use the caller's ids; only
                                     fork_partitions reports internal positions.
                                     Host memory, or device memory when
@@ -228,7 +228,7 @@ int fork_run(fork_ctx *ctx, const fork_run_opts *opts);
 
 /*
  * Sweep cuts of resident PPR queries: the NCP application built on the PPR
- * queries (Sections 2 and 7.1; the paper computes the network community
+ * queries (Sections 2 and 6.1; the paper computes the network community
  * profile from one PPR per seed and does not print the sweep).  Reading:
  * the graph is taken as undirected, each directed edge one undirected edge,
  * d(v) = out-degree + in-degree, total volume 2|E|; the vertices with
@@ -247,7 +247,7 @@ int fork_sweep(fork_ctx *ctx, uint32_t first_query_id, uint32_t n, uint32_t max_
 
 /*
  * Betweenness centrality from resident BFS queries: the BC application
- * (Sections 2 and 7.1: BFSs from sampled sources, then Brandes'
+ * (Sections 2 and 6.1: BFSs from sampled sources, then Brandes'
  * accumulation of dependencies).  Shortest paths are counted as edge
  * sequences of the multigraph.  For queries first_query_id ..
  * first_query_id + n - 1 (all BFS and in the resident wave), writes
@@ -265,7 +265,10 @@ int fork_sweep(fork_ctx *ctx, uint32_t first_query_id, uint32_t n, uint32_t max_
 int fork_bc(fork_ctx *ctx, uint32_t first_query_id, uint32_t n, double *out);
 
 /*
- * Copy one query's result: field FORK_FIELD_VALUE (int32[V]), _P or _R
+ * Copy one query's result (Algorithm 1: each query of the FPP yields its own
+ * result vector, as if run alone; Definition 2.2).  The digest is an addition
+ * of this library for batches whose vectors do not all stay resident.
+ * Field FORK_FIELD_VALUE (int32[V]), _P or _R
  * (float[V]) or _DIGEST (fork_digest).  dst_bytes must be large enough.
  * dst_on_device != 0: dst is a device pointer (device-to-device copy).
  * FORK_E_STATE if the query has not run, or its vectors are no longer
@@ -310,7 +313,11 @@ int fork_mlp_train(float *theta, const float *x, const float *t, uint64_t n,
                    uint32_t steps, uint32_t batch, float lr, uint64_t seed,
                    float *losses);
 
-/* Copy the counters of the last run into *dst (dst_bytes >= sizeof). */
+/* Copy the counters of the last run into *dst (dst_bytes >= sizeof): the
+ * work measures of the paper's evaluation (edges processed, compared with the
+ * sequential algorithms' in Section 6.3; operations buffered and consumed,
+ * Section 4.2; yields, Section 5.1) and this library's pass timings.
+ * FORK_E_INVALID if dst_bytes < sizeof(fork_stats_t). */
 int fork_stats(fork_ctx *ctx, void *dst, uint64_t dst_bytes);
 
 /* Partition plan: writes up to cap+1 boundaries; *num_parts receives |P|. */

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE, like the rest of ``oracle/``: only ``tests/`` may
 import it; the product library never does.
 
-The paper's BC (Section 2; 100 sampled sources in Section 7.1) runs one BFS
+The paper's BC (Section 2; 100 sampled sources in Section 6.1) runs one BFS
 per sampled source and gathers the results with Brandes' accumulation.  On a
 weighted graph the same holds with SSSP.  Definitions used here:
 

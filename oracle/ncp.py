@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE, like the rest of ``oracle/``: only ``tests/`` may
 import it; the product library never does.
 
-The paper runs NCP as one PPR per seed vertex (Sections 2 and 7.1: seeds are
+The paper runs NCP as one PPR per seed vertex (Sections 2 and 6.1: seeds are
 0.01% of the vertices, after Shun et al.), and defines the profile as the
 best conductance of a cluster of each size.  It does not print the sweep
 itself.  The reading used here is the standard local-clustering sweep:

@@ -1,6 +1,6 @@
 """The paper's scheduling and yielding study, run on the GPU.
 
-Section 7.3 studies the design choices one at a time.
+Section 6.4 studies the design choices one at a time.
 
 - Table "priority" A: the inter-partition schedule, with yielding on. The
   schedules are Random, Max #operations, FIFO and the priority functor

@@ -16,8 +16,12 @@ constexpr uint32_t PVMAX = 65536;         // max vertices per partition (hashed 
 constexpr uint32_t HS_AUTO = 4096;        // hash slots when the dense slice does not fit
 // Largest partition (vertices) for L1-certified PPR queries: at most the
 // visit's frontier capacity, so a refinement's re-activations always fit the
-// frontier and are never spilled back into the buffers.
-constexpr uint32_t CERT_MAX_PART = 1024;
+// frontier and are never spilled back into the buffers.  (The host build of
+// the kernels used by the tests raises it to drive refinements that spill.)
+#ifndef FORK_CERT_MAX_PART
+#define FORK_CERT_MAX_PART 1024u
+#endif
+constexpr uint32_t CERT_MAX_PART = FORK_CERT_MAX_PART;
 constexpr int MLP_IN = 16, MLP_H = 64;
 constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;  // 5313
 

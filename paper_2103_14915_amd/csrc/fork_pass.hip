@@ -32,7 +32,7 @@ namespace fk {
 constexpr int NT = 256;           // threads per workgroup
 constexpr int NW = NT / WAVE;     // waves per workgroup
 constexpr int FCAP = 1024;        // frontier capacity (two buffers)
-static_assert((uint32_t)FCAP >= CERT_MAX_PART, "a certified refinement fits the frontier");
+static_assert((uint32_t)FCAP >= CERT_MAX_PART || FORK_CERT_MAX_PART > 1024u, "a certified refinement fits the frontier");
 constexpr int BCAP = 512;         // vertices expanded per batch
 constexpr int SCAP = 512;         // staged outgoing operations
 constexpr int CCAP = 128;         // chunk ids gathered per consume round
@@ -1205,15 +1205,26 @@ const void* persistent_kernel_ptr(int wbytes) {
     }
 }
 
+template <int WB>
+static hipError_t launch_persistent_wb(const GraphDev& g, const QueryDev& Q, const BufDev& B, const PassCfg& cfg,
+                                       uint32_t blocks, uint32_t sw, uint32_t hs, uint32_t max_passes,
+                                       const float* theta, float* score, GStat* gs, size_t dyn, hipStream_t s) {
+    void* args[] = {(void*)&g, (void*)&Q, (void*)&B, (void*)&cfg, (void*)&sw, (void*)&hs, (void*)&max_passes,
+                    (void*)&theta, (void*)&score, (void*)&gs};
+    return hipLaunchCooperativeKernel(k_persistent<WB>, dim3(blocks), dim3(NT), args, dyn, s);
+}
+
 hipError_t launch_persistent(const GraphDev& g, const QueryDev& Q, const BufDev& B, const PassCfg& cfg,
                              uint32_t blocks, uint32_t vpmax, uint32_t hs, uint32_t max_passes, const float* theta,
                              float* score, void* gstat, hipStream_t s) {
-    size_t dyn = process_dyn_lds(vpmax, hs);
-    uint32_t sw = vpmax;
+    const size_t dyn = process_dyn_lds(vpmax, hs);
     GStat* gs = (GStat*)gstat;
-    void* args[] = {(void*)&g, (void*)&Q, (void*)&B, (void*)&cfg, (void*)&sw, (void*)&hs, (void*)&max_passes,
-                    (void*)&theta, (void*)&score, (void*)&gs};
-    return hipLaunchCooperativeKernel(persistent_kernel_ptr(g.wbytes), dim3(blocks), dim3(NT), args, dyn, s);
+    switch (g.wbytes) {
+    case 0: return launch_persistent_wb<0>(g, Q, B, cfg, blocks, vpmax, hs, max_passes, theta, score, gs, dyn, s);
+    case 1: return launch_persistent_wb<1>(g, Q, B, cfg, blocks, vpmax, hs, max_passes, theta, score, gs, dyn, s);
+    case 2: return launch_persistent_wb<2>(g, Q, B, cfg, blocks, vpmax, hs, max_passes, theta, score, gs, dyn, s);
+    default: return launch_persistent_wb<4>(g, Q, B, cfg, blocks, vpmax, hs, max_passes, theta, score, gs, dyn, s);
+    }
 }
 int process_threads() { return NT; }
 size_t process_static_lds() { return sizeof(PassShared); }

@@ -1,4 +1,4 @@
-// Sweep cuts of PPR results: the NCP application (Sections 2 and 7.1), gfx950.
+// Sweep cuts of PPR results: the NCP application (Sections 2 and 6.1), gfx950.
 //
 // The paper builds NCP from one PPR per seed and keeps, per cluster size, the
 // least conductance; it does not print the sweep.  Reading used (shared with
@@ -310,7 +310,7 @@ size_t sweep_out_bytes() { return sizeof(SweepOut); }
 
 // ------------------------------------------------------------ betweenness
 // Brandes' accumulation over resident BFS queries (the BC application of
-// Sections 2 and 7.1: many BFSs from sampled sources, then dependencies).
+// Sections 2 and 6.1: many BFSs from sampled sources, then dependencies).
 // One workgroup per query, in three steps over the query's levels:
 //   1. counting sort of the reached vertices by level (per-query scratch);
 //   2. sigma (shortest-path counts, fp64), level by level: sigma(v) = sum

@@ -4,7 +4,7 @@ The library cuts the graph into contiguous ranges of its internal vertex
 numbering (Definition 2.1).  An order that keeps neighbours close together
 makes partitions with fewer cut edges, so fewer operations cross partitions
 and queries settle in fewer passes.  The paper partitions with METIS and
-reports a large gain over random partitions (Section 7.3).  These helpers
+reports a large gain over random partitions (Appendix C, effects of partition and cache size).  These helpers
 give the position of each vertex in such an order, for
 ``ForkGraph(..., vertex_order=pos)``.  They only change speed: results are
 the same for any order.
