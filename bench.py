@@ -6,13 +6,16 @@
 A step is one complete fork-processing run (state init + every pass of the
 buffered execution until all buffers are empty) over the workload's whole
 query batch, with the graph and sources already resident on the GPU.  The
-default workload is R-MAT scale 20 (1,048,576 vertices, 16,777,216 edges,
-a/b/c/d = 0.57/0.19/0.19/0.05, unweighted) with 4,096 PPR forward-push
-queries (alpha = 0.15, epsilon = 1e-6, push while r >= epsilon * outdeg) from
-seeded uniform sources.
+default workload is the batched SSSP + PPR mix on R-MAT scale 20 (1,048,576
+vertices, 16,777,216 edges, a/b/c/d = 0.57/0.19/0.19/0.05, weights uniform in
+[1, 255]): 1,024 SSSP and 1,024 PPR forward-push queries (alpha = 0.15,
+epsilon = 1e-6, push while r >= epsilon * outdeg), half of the sources
+uniform and half among the top 1% by out-degree.
 
-Prints one JSON line with queries/s, the dominant kernel's roofline figures
-and the CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line with queries/s under the priority rule, the learned
+scheduler's speedup over it on the same queries (identical SSSP results
+required), the dominant kernel's roofline figures and the CPU oracle timed
+on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -28,18 +31,19 @@ METRIC = "queries/sec for batched SSSP+PPR at 1 GPU; learned vs rule schedule sp
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(st: dict, kind: str) -> float:
-    """Bytes the buffered pass must move for the work it did.
+def algorithmic_bytes(st: dict) -> float:
+    """Bytes the method must move for the work it did, counted on the device.
 
-    per edge scanned: 4 B target id (+ weight bytes for SSSP);
-    per edge whose target is in the same partition: 8 B state read+write;
-    per operation emitted: 8 B written; per operation consumed: 8 B read
-    + 8 B state read+write; per vertex expanded: 12 B (SSSP/BFS: row
-    bounds + distance) or 24 B (PPR: row bounds, r exchange, p update)."""
-    wb = st["weight_bytes"] if kind == "sssp" else 0
-    per_v = 24 if kind == "ppr" else 12
-    return (st["edges"] * (4 + wb) + st["intra_edges"] * 8 + st["ops_emitted"] * 8 + st["ops_consumed"] * 16
-            + st["vertex_pushes"] * per_v)
+    SSSP/BFS: 4 B state read per edge relaxation + 4 B per improving write.
+    PPR: 8 B residual read-modify-write per edge push + 24 B per vertex push
+    (8 B p read-modify-write, 4 B residual reset, 8 B row bounds, 4 B degree).
+    Edge data: (4 B target + weight bytes) per out-edge of every partition
+    scheduled in a pass, shared by all of the pass's queries of that partition.
+    Cross-partition operations: 24 B each (a 12 B <q, v, val> written and read
+    back)."""
+    sp_edges = st["edges"] - st["ppr_edges"]
+    return (sp_edges * 4 + st["improved"] * 4 + st["ppr_edges"] * 8 + st["ppr_vertex_pushes"] * 24
+            + st["selected_edges"] * (4 + st["weight_bytes"]) + st["ops_emitted"] * 24)
 
 
 def measured_traffic(workload: str, root: str = ""):
@@ -76,10 +80,32 @@ def certified_push(oracle, g, batch, alpha, eps, mode, target, threads):
         todo = np.asarray(left, np.int64)
 
 
+def host_info():
+    """CPU model and the cores this process may run on (the baseline's threads)."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    aff = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else []
+    spans, i = [], 0
+    while i < len(aff):
+        j = i
+        while j + 1 < len(aff) and aff[j + 1] == aff[j] + 1:
+            j += 1
+        spans.append(f"{aff[i]}-{aff[j]}" if j > i else f"{aff[i]}")
+        i = j + 1
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "affinity": ",".join(spans),
+            "affinity_cpus": len(aff)}
+
+
 def cpu_baseline(g, queries, spec, budget_s=15.0, l1_target=0.0):
     """The CPU oracle, untuned, one query per thread over all host cores."""
     import oracle
-    threads = os.cpu_count() or 1
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     kinds = [(qt, s) for qt, s in queries]
     done, t_total = 0, 0.0
     rng = np.random.default_rng(0)
@@ -108,6 +134,7 @@ def cpu_baseline(g, queries, spec, budget_s=15.0, l1_target=0.0):
                 acc[0] += len(batch)
                 acc[1] += int(np.sum(w))
     return {"value": done / t_total, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "host": host_info(),
             "sequential_edges_per_query": {qt: e / n for qt, (n, e) in work.items()},
             "sample": f"{done} queries ({', '.join(sorted(set(samples)))} per batch) of the same workload, "
                       f"{t_total:.1f} s, fp64 forward push / Dijkstra / BFS, one query per thread"
@@ -125,18 +152,19 @@ def compare_learned(fg, args, run_kw, nq, rule_value):
     kw = dict(run_kw, scheduler="learned", mlp_weights=theta)
     fg.run(**kw)  # warm-up
     torch.cuda.synchronize()
+    steps = max(1, min(args.steps, args.learned_steps))
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         fg.run(**kw)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = fg.stats()
-    learned_value = nq * args.steps / dt
+    learned_value = nq * steps / dt
     same = all((fg.digest(i)["hash"], fg.digest(i)["count"]) == (rule_dig[i]["hash"], rule_dig[i]["count"])
                for i in range(nq) if kinds[i] != fork.PPR)
     return {"rule_queries_per_s": rule_value, "learned_queries_per_s": learned_value,
             "speedup": learned_value / rule_value, "sssp_bfs_digests_identical": bool(same),
-            "learned_passes_per_step": st["passes"], "learned_edges_per_step": st["edges"],
+            "learned_passes_per_step": st["passes"], "learned_edges_per_step": st["edges"], "learned_steps": steps,
             "weights": os.path.basename(args.compare_learned)}
 
 
@@ -145,7 +173,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat20_ppr4096")
+    ap.add_argument("--workload", default="rmat20_sssp_ppr2048")
     ap.add_argument("--scheduler", default="priority")
     ap.add_argument("--parts-per-pass", type=int, default=0)
     ap.add_argument("--partition-vertices", type=int, default=0)
@@ -171,8 +199,10 @@ def main():
     ap.add_argument("--retune", action="store_true", help="with --tune: search again even if a result is cached")
     ap.add_argument("--tune-sample", type=int, default=1024, help="queries per autotuner trial")
     ap.add_argument("--no-tuned", action="store_true", help="ignore cached autotuner results")
-    ap.add_argument("--compare-learned", default="", help="MLP weights (.npy): also time the learned scheduler "
-                    "on the same workload and report the speedup over the rule-based one")
+    ap.add_argument("--compare-learned", default="auto", help="MLP weights (.npy): also time the learned scheduler "
+                    "on the same workload and report the speedup over the rule-based one ('auto': the weights "
+                    "shipped with the package for this graph family; 'none': skip)")
+    ap.add_argument("--learned-steps", type=int, default=5, help="timed steps of the learned scheduler")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -273,7 +303,7 @@ def main():
     for k in ("num_partitions", "weight_bytes"):
         tot[k] = st[k]
     value = nq * args.steps / dt
-    abytes = algorithmic_bytes(tot, kind if kind != "mixed" else "sssp")
+    abytes = algorithmic_bytes(tot)
     prof = measured_traffic(args.workload) if not (args.scale or args.queries or args.l1_target) else None
     launches = max(1, tot["process_launches"])
     avg_ms = tot["process_ms"] / launches
@@ -321,7 +351,11 @@ def main():
                    "work_items_per_step": tot["work_items"] / args.steps,
                    "refine_rounds_per_step": tot["refine_rounds"] / args.steps},
     }
-    if args.compare_learned:
+    if args.compare_learned == "auto":
+        fam = "grid" if spec.get("kind") == "grid" else ""
+        path = os.path.join(os.path.dirname(os.path.abspath(fork.__file__)), f"sched_mlp{'_' + fam if fam else ''}.npy")
+        args.compare_learned = path if os.path.exists(path) else ""
+    if args.compare_learned and args.compare_learned != "none":
         line["learned_vs_rule"] = compare_learned(fg, args, run_kw, nq, value)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(g, queries, spec, args.cpu_budget, args.l1_target)

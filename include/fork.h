@@ -156,6 +156,13 @@ typedef struct {
     uint32_t weight_bytes;     /* bytes per stored edge weight (0 = none)   */
     uint64_t refine_rounds;    /* certified-PPR threshold reductions, summed
                                   over waves                                */
+    uint64_t selected_edges;   /* out-edges of the partitions scheduled, summed
+                                  over passes (edge data staged per pass)   */
+    uint64_t ppr_edges;        /* the PPR queries' share of `edges`          */
+    uint64_t ppr_vertex_pushes;/* the PPR queries' share of `vertex_pushes`  */
+    uint64_t spilled;          /* activated vertices retained as buffered
+                                  operations because the visit's frontier
+                                  was full                                  */
 } fork_stats_t;
 
 /* Per-query digest (fork_fetch field FORK_FIELD_DIGEST).  For SSSP/BFS:

@@ -64,7 +64,9 @@ class fork_stats_t(ctypes.Structure):
                [("init_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("digest_ms", ctypes.c_double),
                 ("process_ms", ctypes.c_double), ("process_launches", ctypes.c_uint64),
                 ("intra_edges", ctypes.c_uint64), ("pruned", ctypes.c_uint64), ("num_partitions", ctypes.c_uint32),
-                ("weight_bytes", ctypes.c_uint32), ("refine_rounds", ctypes.c_uint64)]
+                ("weight_bytes", ctypes.c_uint32), ("refine_rounds", ctypes.c_uint64),
+                ("selected_edges", ctypes.c_uint64), ("ppr_edges", ctypes.c_uint64),
+                ("ppr_vertex_pushes", ctypes.c_uint64), ("spilled", ctypes.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -48,6 +48,9 @@ struct Ctl {
     unsigned long long pending_ops; // operations buffered at select time
     unsigned int stop;              // set by the select step only: no work left, or a device error
                                     // (the persistent kernel's exit test, the same for every block)
+    unsigned long long c_sel_edges; // out-edges of the partitions selected, summed over passes
+    unsigned long long c_edges_ppr, c_vpush_ppr;  // the PPR share of c_edges / c_vpush
+    unsigned long long c_spill;     // activated vertices retained as operations (frontier full)
 };
 
 // A (partition, query) work item of one pass.

@@ -147,6 +147,7 @@ struct ItemCtx {
     uint32_t* bits;     // LDS in-frontier flags (by vertex)
     // per-thread counters
     unsigned long long c_edges, c_intra, c_improved, c_emitted, c_consumed, c_vpush, c_chunks, c_pruned;
+    unsigned long long c_edges_ppr, c_vpush_ppr, c_spill;
     // per-item usefulness (trace runs): work units whose value was final / all
     float it_useful, it_work;
     const uint32_t* gfinal;  // final state of the query (trace runs), else NULL
@@ -547,6 +548,7 @@ __device__ __forceinline__ void push_frontier(ItemCtx& c, PassShared& S, uint32_
     uint32_t p = block_append(want, &S.nf);
     bool fits = want && p < (uint32_t)FCAP;
     if (fits) S.fq[cur][p] = vloc;
+    c.c_spill += (want && !fits) ? 1u : 0u;
     stage(S, want && !fits, c.v0 + vloc, retain_val);
 }
 
@@ -888,6 +890,7 @@ __device__ __forceinline__ void ppr_visit(ItemCtx& c, PassShared& S, uint32_t bu
             S.bpre[j] = push_deg;
         }
         c.c_vpush += pushed;
+        c.c_vpush_ppr += pushed;
         __syncthreads();
         const uint32_t total = batch_scan(S, nb);
         edges += total;
@@ -939,7 +942,7 @@ __device__ __forceinline__ void ppr_visit(ItemCtx& c, PassShared& S, uint32_t bu
         __syncthreads();
         if (t == 0) { S.nf = 0; dev_add(&c.B.ctl->c_yields, 1ull); }
     }
-    if (t == 0) c.c_edges += edges;
+    if (t == 0) { c.c_edges += edges; c.c_edges_ppr += edges; }
 }
 
 // ------------------------------------------------------------ kernels
@@ -1067,17 +1070,20 @@ __device__ __forceinline__ void init_ctx(ItemCtx& c, const GraphDev& g, const Qu
     c.hkeys = dyn + hash_slots;
     c.bits = hash_slots ? nullptr : dyn + slice_words;
     c.c_edges = c.c_intra = c.c_improved = c.c_emitted = c.c_consumed = c.c_vpush = c.c_chunks = c.c_pruned = 0;
+    c.c_edges_ppr = c.c_vpush_ppr = c.c_spill = 0;
 }
 
 __device__ __forceinline__ void publish_counters(const ItemCtx& c, unsigned long long items) {
     const uint32_t t = threadIdx.x;
     const BufDev& B = c.B;
-    unsigned long long v[8] = {c.c_edges, c.c_intra, c.c_improved, c.c_emitted, c.c_consumed, c.c_vpush, c.c_chunks,
-                               c.c_pruned};
-    unsigned long long* dst[8] = {&B.ctl->c_edges, &B.ctl->c_intra, &B.ctl->c_improved, &B.ctl->c_emitted,
-                                  &B.ctl->c_consumed, &B.ctl->c_vpush, &B.ctl->c_chunks, &B.ctl->c_pruned};
+    constexpr int NC = 11;
+    unsigned long long v[NC] = {c.c_edges, c.c_intra, c.c_improved, c.c_emitted, c.c_consumed, c.c_vpush, c.c_chunks,
+                                c.c_pruned, c.c_edges_ppr, c.c_vpush_ppr, c.c_spill};
+    unsigned long long* dst[NC] = {&B.ctl->c_edges, &B.ctl->c_intra, &B.ctl->c_improved, &B.ctl->c_emitted,
+                                   &B.ctl->c_consumed, &B.ctl->c_vpush, &B.ctl->c_chunks, &B.ctl->c_pruned,
+                                   &B.ctl->c_edges_ppr, &B.ctl->c_vpush_ppr, &B.ctl->c_spill};
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NC; ++k) {
         unsigned long long x = v[k];
 #pragma unroll
         for (int o = 32; o; o >>= 1) x += __shfl_xor(x, o);

@@ -848,6 +848,10 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
     st.chunks += h.c_chunks;
     st.intra_edges += h.c_intra;
     st.pruned += h.c_pruned;
+    st.selected_edges += h.c_sel_edges;
+    st.ppr_edges += h.c_edges_ppr;
+    st.ppr_vertex_pushes += h.c_vpush_ppr;
+    st.spilled += h.c_spill;
     st.waves += 1;
     c->res_first = q0;
     c->res_n = nq;

@@ -150,12 +150,15 @@ __device__ void select_body(const GraphDev& g, const BufDev& B, const PassCfg& c
     }
     __syncthreads();
     uint32_t nsel = s_nsel < kmax ? s_nsel : kmax;
+    unsigned long long sel_edges = 0;
     for (uint32_t j = tid; j < nsel; j += NTH) {
         uint32_t P = B.sel[j];
         B.plast[P] = pass;
         B.pvisits[P] += 1;
         B.pn[P] = 0;
+        sel_edges += g.rowptr[g.pstart[P + 1]] - g.rowptr[g.pstart[P]];
     }
+    if (sel_edges) atomicAdd(&ctl->c_sel_edges, sel_edges);
     if (tid < NXCD) { ctl->nitems[tid] = 0; ctl->next[tid] = 0; }
     if (tid == 0) {
         ctl->nsel = nsel;

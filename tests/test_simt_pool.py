@@ -1,0 +1,136 @@
+"""The library's kernels run on the CPU (tests/simt: a host stand-in for the
+HIP runtime in which workgroups are OS threads and lanes are coroutines),
+with an ownership checker of the operation pool after every pass launch:
+each chunk in exactly one place (free ring, one buffer's lists, one work
+item), no cycles, counts matching, every buffered operation inside its
+buffer's partition.
+
+These runs drive the regimes that the GPU tests keep small: a free ring that
+wraps many times, visits whose frontier overflows so that activated vertices
+are retained as operations in the visit's own buffer, hashed slices whose
+probe paths fill up, certified-PPR refinements on partitions larger than the
+frontier, and the persistent kernel.  The checker itself is shown to see
+planted mistakes (a double free, a lost chunk, a misrouted chunk, a wrong
+count), each planted in a run of its own.
+"""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import fpp_inputs as fi
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, os.path.join(ROOT, "tests", "simt"))
+
+pytestmark = pytest.mark.slow
+
+
+@pytest.fixture(scope="module")
+def fs():
+    import fork_simt
+    fork_simt.load()
+    return fork_simt
+
+
+def _clean(fs, lib):
+    c = fs.checker(lib)
+    assert c["checks"] > 0
+    assert c["failures"] == 0, c["message"]
+    return c
+
+
+def test_sssp_and_bfs_exact_with_a_wrapping_free_ring(fs):
+    lib = fs.load()
+    fs.reset_checker(lib)
+    g = fi.rmat(11, seed=21, weights=(1, 255), weight_seed=22)
+    s_sp = fi.sources_uniform(g, 16, 1)
+    s_bfs = fi.sources_uniform(g, 8, 2)
+    fg = fs.SimtGraph(lib, g, partition_vertices=128, pool_bytes=3 << 20)  # 1,527 chunks
+    fg.submit("sssp", s_sp)
+    fg.submit("bfs", s_bfs)
+    fg.run(max_passes=100000)
+    d = np.stack([fg.fetch(i) for i in range(16)])
+    lv = np.stack([fg.fetch(16 + i) for i in range(8)])
+    st = fg.stats()
+    fg.close()
+    np.testing.assert_array_equal(d, oracle.sssp(g, s_sp))
+    np.testing.assert_array_equal(lv, oracle.bfs(g, s_bfs))
+    assert st["waves"] == 1 and st["chunks"] > 2 * 1527  # the pool's chunks were reused more than twice
+    _clean(fs, lib)
+
+
+def test_persistent_kernel_exact_and_consistent(fs):
+    lib = fs.load()
+    fs.reset_checker(lib)
+    g = fi.rmat(10, seed=23, weights=(1, 255), weight_seed=24)
+    srcs = fi.sources_uniform(g, 8, 3)
+    fg = fs.SimtGraph(lib, g, partition_vertices=128, pool_bytes=4 << 20)
+    fg.submit("sssp", srcs)
+    fg.run(max_passes=100000, persistent=1)
+    d = np.stack([fg.fetch(i) for i in range(8)])
+    fg.close()
+    np.testing.assert_array_equal(d, oracle.sssp(g, srcs))
+    _clean(fs, lib)
+
+
+def test_ppr_frontier_spill_and_hash_fallback(fs):
+    """2,048-vertex partitions (twice the frontier) with 256 hash slots and a
+    small threshold: visits retain activated vertices as operations in their
+    own buffer, and most vertices live outside the LDS table."""
+    lib = fs.load()
+    fs.reset_checker(lib)
+    g = fi.rmat(11, seed=31)
+    srcs = fi.sources_uniform(g, 4, 32)
+    eps = 1e-8
+    fg = fs.SimtGraph(lib, g, partition_vertices=2048, pool_bytes=16 << 20)
+    fg.submit("ppr", srcs, epsilon=eps, eps_mode=0)
+    fg.run(max_passes=100000, slice_slots=256)
+    st = fg.stats()
+    P = [fg.fetch(i, 1).astype(np.float64) for i in range(4)]
+    R = [fg.fetch(i, 2) for i in range(4)]
+    fg.close()
+    assert st["spilled"] > 1000, st["spilled"]
+    for i, s in enumerate(srcs):
+        assert oracle.push_terminal(g, R[i], eps, 0, dtype=np.float32)
+        assert oracle.ppr_invariant_l1(g, s, P[i], R[i].astype(np.float64), 0.15) <= 1e-4
+    _clean(fs, lib)
+
+
+def test_certified_refinement_on_partitions_larger_than_the_frontier(fs):
+    """The certified mode's refinement re-activates most of a 4,096-vertex
+    partition at once (the regime in which the GPU run failed): results meet
+    the L1 target and the pool stays consistent."""
+    lib = fs.load()
+    fs.reset_checker(lib)
+    g = fi.rmat(12, seed=31)
+    srcs = fi.sources_uniform(g, 4, 32)
+    fg = fs.SimtGraph(lib, g, partition_vertices=4096, pool_bytes=64 << 20)
+    fg.submit("ppr", srcs, epsilon=1e-6, eps_mode=1, l1_target=1e-4)
+    fg.run(max_passes=100000, slice_slots=256)
+    st = fg.stats()
+    P = np.stack([fg.fetch(i, 1) for i in range(4)]).astype(np.float64)
+    R = np.stack([fg.fetch(i, 2) for i in range(4)]).astype(np.float64)
+    fg.close()
+    assert st["refine_rounds"] >= 1 and st["spilled"] > 1000, st
+    pi = oracle.ppr_exact(g, srcs, 0.15)
+    for i in range(4):
+        assert R[i].sum() <= 0.9e-4 * (1 + 1e-6)
+        assert np.abs(P[i] - pi[i]).sum() <= 1e-4
+    _clean(fs, lib)
+
+
+@pytest.mark.parametrize("plant,expect", [("dup", "already owned"), ("leak", "owned by nothing"),
+                                          ("misroute", "outside partition"), ("count", "bcnt")])
+def test_checker_sees_planted_mistakes(fs, plant, expect):
+    env = dict(os.environ, SIMT_PLANT=plant)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "tests", "simt", "fork_simt.py"), "sssp_small_pool"],
+                       env=env, capture_output=True, text=True, timeout=300, cwd=ROOT)
+    line = [x for x in r.stdout.splitlines() if x.startswith("{")]
+    assert line, (r.returncode, r.stderr[-2000:])
+    c = json.loads(line[-1])["check"]
+    assert c["failures"] >= 1 and expect in c["message"], c
