@@ -156,5 +156,6 @@ def test_adam_steps_on_gpu_match_the_fp64_oracle(lr):
         sure = gmin > 1e-4  # gradient well above fp32 rounding at every step so far
         assert sure.sum() > 0.5 * omlp.N_PARAMS
         np.testing.assert_allclose(th_gpu[sure], th64[sure], rtol=0, atol=1e-5 * lr + 1e-6 * np.abs(th64[sure]).max())
-        # every coordinate moved by at most lr per step (Adam's bias-corrected step size)
-        assert np.all(np.abs(th_gpu.astype(np.float64) - theta0) <= step * lr * (1 + 1e-5) + 1e-7)
+        # Adam's bias-corrected step is at most about lr per coordinate: by
+        # Cauchy-Schwarz |m^|/sqrt(v^) <= 1.0014 at t = 2 (and 1 at t = 1)
+        assert np.all(np.abs(th_gpu.astype(np.float64) - theta0) <= step * lr * 1.0015 + 1e-7)
