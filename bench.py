@@ -175,6 +175,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat20_sssp_ppr2048")
     ap.add_argument("--scheduler", default="priority")
+    ap.add_argument("--engine", default="buffered", choices=["buffered", "grouped"],
+                    help="buffered: one work item per (partition, query); grouped: per (partition, 64 queries)")
     ap.add_argument("--parts-per-pass", type=int, default=0)
     ap.add_argument("--partition-vertices", type=int, default=0)
     ap.add_argument("--delta", type=int, default=0)
@@ -285,9 +287,10 @@ def main():
     kinds = sorted({qt for qt, _ in queries})
     kind = kinds[0] if len(kinds) == 1 else "mixed"
     run_kw = dict(scheduler=args.scheduler, parts_per_pass=args.parts_per_pass, delta=params["delta"],
-                  edge_budget_mu=args.mu, stream=stream, profile=1, persistent=params["persistent"],
+                  edge_budget_mu=args.mu, stream=stream, profile=1,
+                  persistent=params["persistent"] if args.engine == "buffered" else 0,
                   items_per_pass=params["items_per_pass"], window_mode=args.window_mode, window=params["window"],
-                  slice_slots=params.get("slice_slots", 0))
+                  slice_slots=params.get("slice_slots", 0), engine=args.engine)
     for _ in range(args.warmup):
         fg.run(**run_kw)
     torch.cuda.synchronize()
@@ -324,7 +327,7 @@ def main():
         "config": {"workload": args.workload + (f"@scale{args.scale}" if args.scale else "")
                    + (f"@q{args.queries}" if args.queries else "")
                    + (f"+l1cert{args.l1_target:g}" if args.l1_target > 0 else ""), "queries": nq, "types": kinds, "vertices": g.num_vertices,
-                   "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler, "knobs": params, "knobs_source": source,
+                   "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler, "engine": args.engine, "knobs": params, "knobs_source": source,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -349,7 +352,9 @@ def main():
                    "ops_pruned_per_step": tot["pruned"] / args.steps,
                    "vertex_pushes_per_step": tot["vertex_pushes"] / args.steps,
                    "work_items_per_step": tot["work_items"] / args.steps,
-                   "refine_rounds_per_step": tot["refine_rounds"] / args.steps},
+                   "refine_rounds_per_step": tot["refine_rounds"] / args.steps,
+                   "activations_per_step": tot["activations"] / args.steps,
+                   "spilled_per_step": tot["spilled"] / args.steps, "spill_max": st["spill_max"]},
     }
     if args.compare_learned == "auto":
         fam = "grid" if spec.get("kind") == "grid" else ""

@@ -36,7 +36,8 @@ typedef enum {
     FORK_E_NOMEM = -2,         /* device or host allocation failed           */
     FORK_E_DEVICE = -3,        /* HIP runtime error, or no usable GPU        */
     FORK_E_STATE = -4,         /* call not valid in the context's state      */
-    FORK_E_CAPACITY = -5,      /* operation pool exhausted during a run      */
+    FORK_E_CAPACITY = -5,      /* operation pool exhausted, or a visit over the
+                                  frontier-spill bound (fork_stats_t.spill_max) */
     FORK_E_NOT_CONVERGED = -6  /* max_passes reached with work still pending */
 } fork_status;
 
@@ -101,6 +102,19 @@ typedef struct {
     float l1_target; /* 0 = off; else the certified L1 bound   */
 } fork_ppr_params;
 
+/* Execution engines (both run Algorithm 2 with the same scheduler):
+ *   BUFFERED -- one work item per (partition, query): buffered operations are
+ *               chunked lists of <v, val> per (partition, query), consumed into
+ *               an LDS copy of the query's state slice (Sections 3-4 as in the
+ *               paper, one query per workgroup).
+ *   GROUPED  -- one work item per (partition, group of 64 queries of one
+ *               type): the state is vertex-major per group (one 256-byte row
+ *               per vertex, a lane per query), so a visit reads each out-edge
+ *               once for 64 queries; pending operations are consolidated per
+ *               (query, vertex) in the state rows (Section 4.2) and tracked by
+ *               lane masks.  No certified PPR, traces or persistent kernel. */
+enum { FORK_ENGINE_BUFFERED = 0, FORK_ENGINE_GROUPED = 1 };
+
 /* Per-run options.  NULL = defaults (PRIORITY, automatic tuning, stream 0). */
 typedef struct {
     int      scheduler;        /* fork_sched                                     */
@@ -131,6 +145,7 @@ typedef struct {
                                   place in global memory.  Partitions too large
                                   for the dense slice always use a hashed one
                                   (4096 slots when 0 is given)                    */
+    int      engine;           /* FORK_ENGINE_BUFFERED (0) or FORK_ENGINE_GROUPED (1) */
 } fork_run_opts;
 
 /* Counters accumulated over the last fork_run (all waves). */
@@ -163,6 +178,11 @@ typedef struct {
     uint64_t spilled;          /* activated vertices retained as buffered
                                   operations because the visit's frontier
                                   was full                                  */
+    uint64_t activations;      /* grouped engine: (vertex, group) pairs marked
+                                  pending in another partition              */
+    uint64_t spill_max;        /* most vertices one visit retained as
+                                  operations (a visit retaining more than
+                                  16,384 stops the run: FORK_E_CAPACITY)    */
 } fork_stats_t;
 
 /* Per-query digest (fork_fetch field FORK_FIELD_DIGEST).  For SSSP/BFS:

@@ -30,7 +30,14 @@ enum Sched : uint32_t { S_FIFO = 0, S_PRIORITY = 1, S_LEARNED = 2, S_RANDOM = 3,
 
 // error flags in Ctl::err
 constexpr unsigned long long BTW_EMPTY = 0xffffffff00000000ull | (unsigned long long)CH;
-enum : uint32_t { ERR_CAPACITY = 1u, ERR_ITEMS = 2u, ERR_CORRUPT = 4u };
+enum : uint32_t { ERR_CAPACITY = 1u, ERR_ITEMS = 2u, ERR_CORRUPT = 4u, ERR_SPILL = 8u };
+// Most activated vertices one visit of the buffered engine may retain as
+// operations in its own buffer when its frontier is full.  Beyond it the run
+// stops with FORK_E_CAPACITY: that regime (a visit re-activating most of a
+// large partition, its overflow re-emitted pass after pass) is the one in
+// which a GPU run once failed its consistency check for a reason not found,
+// so it is refused rather than run.
+constexpr uint32_t SPILL_MAX = 16384;
 
 // One device control block per context.  Counters are 64-bit.
 struct Ctl {
@@ -51,6 +58,8 @@ struct Ctl {
     unsigned long long c_sel_edges; // out-edges of the partitions selected, summed over passes
     unsigned long long c_edges_ppr, c_vpush_ppr;  // the PPR share of c_edges / c_vpush
     unsigned long long c_spill;     // activated vertices retained as operations (frontier full)
+    unsigned long long c_act;       // grouped engine: (vertex, group) activations in other partitions
+    unsigned int c_spill_max;       // most vertices one visit retained because its frontier was full
 };
 
 // A (partition, query) work item of one pass.
@@ -129,6 +138,25 @@ struct BufDev {
     Item* items;              // [NXCD * item_cap]
     uint32_t item_cap;
     Ctl* ctl;
+};
+
+// Queries of the grouped engine: groups of up to 64 queries of one type,
+// lane l of group g being one query; state rows are vertex-major per group.
+struct GroupDev {
+    uint32_t ng;                      // groups in the wave
+    const uint32_t* gtype;            // [ng] query type
+    const unsigned long long* goff;   // [ng] word offset of the group's state
+    const float* lalpha;              // [ng*64] per lane (PPR)
+    const float* leps;                // [ng*64]
+    const uint32_t* lmode;            // [ng*64]
+    uint32_t* state;                  // SSSP/BFS: dist[V][64]; PPR: r[V][64] then p[V][64]
+    unsigned long long* pend;         // [ng][V] pending lanes
+    uint32_t* bits;                   // [ng][bw] vertices with pending lanes (may hold stale ones)
+    uint32_t bw;                      // bitmap words per group
+    uint32_t* icnt;                   // [np*ng] activations since the pair was last detached
+    uint32_t* ibest;                  // [np*ng] best pending value (SSSP/BFS min; PPR ~residual bits)
+    uint32_t* ifirst;                 // [np*ng] pass of the first activation since the detach
+    uint32_t* gmin;                   // [ng] SSSP/BFS: the group's best pending value (heuristic 2)
 };
 
 struct PassCfg {

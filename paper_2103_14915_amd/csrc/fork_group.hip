@@ -1,0 +1,743 @@
+// The query-grouped engine (gfx950): the fork-processing pattern with the
+// queries of one type taken 64 at a time, one query per lane of a wave.
+//
+// Mapping of the paper's design (Sections 3-5) onto the GPU:
+//   * state is kept vertex-major per group: the 64 queries' values of a
+//     vertex are one 256-byte row, so a visit reads each out-edge once for
+//     all 64 queries (the fork sharing of Section 4.1) and every state access
+//     of a wave is one coalesced row;
+//   * the buffer of a (partition, group) pair holds the consolidated pending
+//     operations <q, v, val> of Section 4.2: at most one per (query, vertex),
+//     with the minimum distance (SSSP/BFS) or the summed residual (PPR).  Its
+//     values live in the state rows, combined there at once by device atomics
+//     (min, or add), and its membership is a 64-bit lane mask per vertex plus
+//     a bitmap of the vertices with pending lanes.  An update to another
+//     partition marks the target pending and counts the activation in that
+//     pair's summary (count, best value, age), which the scheduler reads;
+//   * a visit of (P, g) moves P's pending bits into LDS and works through
+//     them in rounds (Algorithm 2's IntraPartProcess), expanding every
+//     pending lane of a vertex together; activations inside P join the next
+//     round, the rest wait for their partition's visit.  Heuristic 2 of
+//     Section 5.1 holds back lanes beyond the group's window, heuristic 1
+//     ends the visit after an edge budget; held-back work stays pending.
+#include "fork_sched.h"
+
+namespace fk {
+
+constexpr int GW = 64;        // queries per group (one per lane)
+constexpr int GNT = 256;      // threads per workgroup
+constexpr int GNW = GNT / WAVE;
+constexpr int RCAP = 1024;    // vertices per round
+constexpr uint32_t GPVMAX = 16384;  // largest partition the grouped engine visits
+constexpr int LBW = GPVMAX / 32;     // local pending bitmap words
+constexpr int UNR = 8;        // edges in flight per wave step (and marking lanes)
+constexpr int PCAP = 32;      // PPR vertices per round (their shares are kept in LDS)
+static_assert(UNR <= WAVE && RCAP % GNT == 0, "task layout");
+
+// Per-lane pushed shares of a PPR round's vertices.
+struct GCtxShare {
+    float share[PCAP][GW];
+};
+
+struct GShared {
+    uint32_t lbits[LBW];              // pending vertices of the partition (local ids)
+    uint32_t rv[RCAP];                // round: vertex (local id)
+    unsigned long long rm[RCAP];      // round: lanes taken, then lanes expanding
+    uint32_t rnt[RCAP];               // round: edge tasks of the vertex, then its first task
+    uint32_t nr, next;
+    uint32_t lmin[GW];                // per lane: least pending value of the round (SSSP/BFS)
+    uint32_t wred[GNW];
+    unsigned long long edges;         // lane-edges of the visit so far
+    unsigned long long itpos;
+    Item it;
+};
+
+__device__ __forceinline__ unsigned long long gpend_take(unsigned long long* p) {
+    return __hip_atomic_exchange(p, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t fresh_load(uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct GCtx {
+    GraphDev g;
+    GroupDev G;
+    BufDev B;
+    uint32_t P, grp, qt, v0, nvp, pass;
+    uint32_t* st;          // group state rows (SSSP/BFS dist, PPR r)
+    float* pp;             // PPR p rows
+    float alpha, eps;      // this lane's query
+    uint32_t mode;
+    uint32_t win;          // heuristic-2 bound: lanes with value > win wait (INF: none)
+    uint32_t bwin;         // batch width inside a visit: a lane expands values in [lmin, lmin + bwin)
+    unsigned long long c_edges, c_intra, c_improved, c_vpush, c_act, c_edges_ppr, c_vpush_ppr;
+};
+
+// Mark lanes `bits` of vertex u (global id) pending in the group.  Called by
+// one lane.  val: the activation's priority (SSSP/BFS distance; PPR ~residual bits).
+__device__ __forceinline__ void gmark(GCtx& c, GShared& S, uint32_t u, unsigned long long bits, uint32_t val) {
+    const unsigned long long old = dev_or(&c.G.pend[(unsigned long long)c.grp * c.g.nv + u], bits);
+    const uint32_t ul = u - c.v0;
+    if (ul < c.nvp) {
+        if (!old) atomicOr(&S.lbits[ul >> 5], 1u << (ul & 31));
+        return;
+    }
+    const uint32_t Pu = c.g.vpart[u >> c.g.pshift];
+    const unsigned long long pi = (unsigned long long)Pu * c.G.ng + c.grp;
+    // only the mask's old value is waited for; the rest are fire-and-forget atomics
+    if (!old) {
+        dev_or(&c.G.bits[(unsigned long long)c.grp * c.G.bw + (u >> 5)], 1u << (u & 31));
+        dev_add(&c.G.icnt[pi], 1u);
+        dev_min(&c.G.ifirst[pi], c.pass);
+        ++c.c_act;
+    }
+    dev_min(&c.G.ibest[pi], val);
+}
+
+// Re-register vertex vloc of the visited partition as pending in the pair's
+// summary (work held back by a yield).  Called by one lane.
+__device__ __forceinline__ void gkeep(GCtx& c, uint32_t vloc, uint32_t val) {
+    const uint32_t u = c.v0 + vloc;
+    const unsigned long long pi = (unsigned long long)c.P * c.G.ng + c.grp;
+    dev_or(&c.G.bits[(unsigned long long)c.grp * c.G.bw + (u >> 5)], 1u << (u & 31));
+    dev_add(&c.G.icnt[pi], 1u);
+    dev_min(&c.G.ibest[pi], val);
+    dev_min(&c.G.ifirst[pi], c.pass);
+}
+
+template <class T> __device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o; o >>= 1) { T t = __shfl_xor(v, o); v = t < v ? t : v; }
+    return v;
+}
+
+// Build the next round from the local bitmap: up to RCAP vertices, their
+// pending lanes taken from the global masks.  Returns the round size.
+__device__ uint32_t gtake_round(GCtx& c, GShared& S, uint32_t cap) {
+    const uint32_t t = threadIdx.x;
+    if (t == 0) { S.nr = 0; S.next = 0; }
+    __syncthreads();
+    const uint32_t nw = (c.nvp + 31) / 32;
+    for (uint32_t w0 = 0; w0 < nw; w0 += GNT) {
+        const uint32_t w = w0 + t;
+        uint32_t word = w < nw ? S.lbits[w] : 0u;
+        // how many of this word's vertices fit in the round
+        const uint32_t cnt = __popc(word);
+        uint32_t room = 0;
+        if (cnt) {
+            const uint32_t at = atomicAdd(&S.nr, cnt);
+            room = at >= cap ? 0u : (cap - at < cnt ? cap - at : cnt);
+            uint32_t k = 0;
+            while (word && k < room) {
+                const uint32_t b = __ffs(word) - 1;
+                word &= word - 1;
+                const uint32_t vloc = w * 32 + b;
+                S.rv[at + k] = vloc;
+                S.rm[at + k] = gpend_take(&c.G.pend[(unsigned long long)c.grp * c.g.nv + c.v0 + vloc]);
+                ++k;
+            }
+            S.lbits[w] = word;  // what did not fit stays for a later round
+        }
+        __syncthreads();
+        if (S.nr >= cap) break;
+        __syncthreads();
+    }
+    __syncthreads();
+    const uint32_t nr = S.nr < cap ? S.nr : cap;
+    __syncthreads();
+    if (t == 0) S.nr = nr;
+    __syncthreads();
+    return nr;
+}
+
+// SSSP / BFS, first half of a round: each lane's least pending value among
+// the round's vertices (the start of its batch window, Section 4.2's
+// Dijkstra order taken in batches as in Delta-stepping).
+__device__ void ground_min(GCtx& c, GShared& S, uint32_t nr) {
+    const uint32_t t = threadIdx.x, lane = lane_id(), wv = t / WAVE;
+    if (t < (uint32_t)GW) S.lmin[t] = INF;
+    __syncthreads();
+    uint32_t m = INF;
+    for (uint32_t k = wv; k < nr; k += GNW) {
+        if (!((S.rm[k] >> lane) & 1ull)) continue;
+        const uint32_t d = fresh_load(&c.st[(unsigned long long)(c.v0 + S.rv[k]) * GW + lane]);
+        m = d < m ? d : m;
+    }
+    if (m < INF) atomicMin(&S.lmin[lane], m);
+    __syncthreads();
+}
+
+// Exclusive prefix sum over the block of one value per thread.
+__device__ __forceinline__ uint32_t gblock_excl(GShared& S, uint32_t v, uint32_t* total) {
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t incl = wscan_incl(v, lane);
+    if (lane == 63) S.wred[wid] = incl;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < GNW; ++w) {
+        const uint32_t x = S.wred[w];
+        before += (w < (int)wid) ? x : 0u;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+// Number the round's edge tasks: vertex k contributes ceil(deg_k / 64) tasks
+// of up to 64 out-edges (S.rnt[k] holds the count on entry, its first task
+// index on return).  Returns the task total.
+__device__ uint32_t gnumber_tasks(GShared& S, uint32_t nr) {
+    constexpr uint32_t PER = RCAP / GNT;
+    const uint32_t t = threadIdx.x;
+    uint32_t x[PER];
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < PER; ++k) {
+        const uint32_t i = t * PER + k;
+        x[k] = i < nr ? S.rnt[i] : 0u;
+        sum += x[k];
+    }
+    uint32_t total = 0;
+    uint32_t run = gblock_excl(S, sum, &total);
+#pragma unroll
+    for (uint32_t k = 0; k < PER; ++k) {
+        const uint32_t i = t * PER + k;
+        if (i < nr) S.rnt[i] = run;
+        run += x[k];
+    }
+    __syncthreads();
+    return total;
+}
+
+__device__ __forceinline__ uint32_t gtask_vertex(const GShared& S, uint32_t nr, uint32_t task) {
+    uint32_t lo = 0, hi = nr;  // last k with rnt[k] <= task
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (S.rnt[mid] <= task) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// SSSP / BFS, second step of a round: per vertex (one wave each), the lanes
+// that expand now.  Lanes beyond the group's heuristic-2 window wait in the
+// pair's buffer for a later pass; lanes beyond their batch window go back to
+// the partition's pending set for a later round of this visit.
+__device__ void gfilter_sp(GCtx& c, GShared& S, uint32_t nr) {
+    const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE;
+    const uint32_t lo = S.lmin[lane];
+    const unsigned long long hi_ = (unsigned long long)lo + c.bwin;
+    const uint32_t hi = hi_ >= INF ? INF : (uint32_t)hi_;
+    for (uint32_t k = wv; k < nr; k += GNW) {
+        const uint32_t vloc = S.rv[k];
+        const unsigned long long m = S.rm[k];
+        const uint32_t v = c.v0 + vloc;
+        bool act = (m >> lane) & 1ull;
+        const uint32_t d = act ? fresh_load(&c.st[(unsigned long long)v * GW + lane]) : INF;
+        const bool late = act && d > c.win;
+        const unsigned long long lm = wballot(late);
+        if (lm) {
+            const uint32_t dl = wave_min(late ? d : 0xffffffffu);
+            if (lane == 0) {
+                dev_or(&c.G.pend[(unsigned long long)c.grp * c.g.nv + v], lm);
+                gkeep(c, vloc, dl);
+            }
+            act = act && !late;
+        }
+        const bool later = act && d >= hi;
+        const unsigned long long lr = wballot(later);
+        if (lr && lane == 0) {
+            const unsigned long long old = dev_or(&c.G.pend[(unsigned long long)c.grp * c.g.nv + v], lr);
+            if (!old) atomicOr(&S.lbits[vloc >> 5], 1u << (vloc & 31));
+        }
+        act = act && !later;
+        const unsigned long long am = wballot(act);
+        c.c_vpush += act ? 1u : 0u;
+        if (lane == 0) {
+            const uint32_t deg = c.g.rowptr[v + 1] - c.g.rowptr[v];
+            S.rm[k] = am;
+            S.rnt[k] = am ? (deg + GW - 1) / GW : 0u;
+        }
+    }
+    __syncthreads();
+}
+
+// PPR, second step of a round: per vertex (one wave each), take the pending
+// lanes' residuals, push those at or above their threshold into p and keep
+// the share each out-edge receives (Section 4.1's push).
+__device__ void gfilter_ppr(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr) {
+    const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE;
+    for (uint32_t k = wv; k < nr; k += GNW) {
+        const uint32_t vloc = S.rv[k];
+        const unsigned long long m = S.rm[k];
+        const uint32_t v = c.v0 + vloc;
+        const uint32_t deg = c.g.rowptr[v + 1] - c.g.rowptr[v];
+        const bool mine = (m >> lane) & 1ull;
+        const float thr = c.mode ? c.eps * (float)deg : c.eps;
+        float rv = 0.f;
+        if (mine) rv = __hip_atomic_exchange((float*)&c.st[(unsigned long long)v * GW + lane], 0.f, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        const bool push = mine && ppr_active(rv, thr);
+        bool back = false;
+        if (mine && !push && rv != 0.f) {
+            // below the threshold after all: give the residual back (it may cross with what arrived)
+            const float old = __hip_atomic_fetch_add((float*)&c.st[(unsigned long long)v * GW + lane], rv,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            back = !ppr_active(old, thr) && ppr_active(old + rv, thr);
+        }
+        const unsigned long long bk = wballot(back);
+        if (bk && lane == 0) gmark(c, S, v, bk, 0u);
+        const unsigned long long pm = wballot(push);
+        c.c_vpush += push ? 1u : 0u;
+        c.c_vpush_ppr += push ? 1u : 0u;
+        float share = 0.f;
+        if (push) {
+            __hip_atomic_fetch_add(&c.pp[(unsigned long long)v * GW + lane], c.alpha * rv, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (deg) share = (1.f - c.alpha) * rv / (float)deg;
+        }
+        SH.share[k][lane] = share;
+        if (lane == 0) {
+            S.rm[k] = deg ? pm : 0ull;
+            S.rnt[k] = (pm && deg) ? (deg + GW - 1) / GW : 0u;
+        }
+    }
+    __syncthreads();
+}
+
+// Third step of a round: the edge tasks, shared by the block's waves.  A task
+// is up to 64 consecutive out-edges of one vertex: one vector load fetches
+// their targets (and weights), then UNR edges at a time are relaxed (SSSP/BFS:
+// atomic min of the row entry) or pushed to (PPR: atomic add of the share)
+// by every active lane, and the lanes 0..UNR-1 mark the newly pending targets
+// in parallel.
+template <int WB>
+__device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t ntask) {
+    const uint32_t lane = lane_id();
+    const bool ppr = c.qt == Q_PPR;
+    for (;;) {
+        uint32_t task = 0;
+        if (lane == 0) task = atomicAdd(&S.next, 1u);
+        task = __shfl(task, 0);
+        if (task >= ntask) break;
+        const uint32_t k = gtask_vertex(S, nr, task);
+        const uint32_t v = c.v0 + S.rv[k];
+        const unsigned long long m = S.rm[k];
+        const bool act = (m >> lane) & 1ull;
+        const uint32_t na = __popcll(m);
+        const uint32_t r0 = c.g.rowptr[v], r1 = c.g.rowptr[v + 1];
+        const uint32_t eb = r0 + (task - S.rnt[k]) * GW;
+        const uint32_t cnt = r1 - eb < (uint32_t)GW ? r1 - eb : (uint32_t)GW;
+        // this task's targets (and weights), one per lane
+        const uint32_t myu = lane < cnt ? c.g.col[eb + lane] : 0u;
+        const uint32_t myw = (lane < cnt && !ppr && WB != 0 && c.qt != Q_BFS) ? edge_w<WB>(c.g.w, eb + lane) : 1u;
+        float mythr = 0.f;
+        if (ppr && lane < cnt) {
+            const uint32_t du = c.g.rowptr[myu + 1] - c.g.rowptr[myu];
+            mythr = du;  // degree; scaled per lane below
+        }
+        const uint32_t intra = __popcll(wballot(lane < cnt && myu - c.v0 < c.nvp));
+        uint32_t d = INF;
+        float share = 0.f;
+        if (ppr) share = SH.share[k][lane];
+        else if (act) d = fresh_load(&c.st[(unsigned long long)v * GW + lane]);
+        for (uint32_t j0 = 0; j0 < cnt; j0 += UNR) {
+            uint32_t u[UNR];
+            bool hit[UNR];
+            uint32_t val[UNR];
+#pragma unroll
+            for (int j = 0; j < UNR; ++j) u[j] = __shfl(myu, (int)(j0 + j) & (GW - 1));
+            if (ppr) {
+                float thu[UNR], old[UNR];
+#pragma unroll
+                for (int j = 0; j < UNR; ++j) {
+                    const float du = __shfl(mythr, (int)(j0 + j) & (GW - 1));
+                    thu[j] = c.mode ? c.eps * du : c.eps;
+                }
+#pragma unroll
+                for (int j = 0; j < UNR; ++j)
+                    old[j] = (act && j0 + j < cnt)
+                                 ? __hip_atomic_fetch_add((float*)&c.st[(unsigned long long)u[j] * GW + lane], share,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : 0.f;
+#pragma unroll
+                for (int j = 0; j < UNR; ++j) {
+                    const float nr_ = old[j] + share;
+                    hit[j] = act && j0 + j < cnt && !ppr_active(old[j], thu[j]) && ppr_active(nr_, thu[j]);
+                    val[j] = ~__float_as_uint(nr_);
+                }
+            } else {
+                uint32_t nd[UNR], cur[UNR];
+#pragma unroll
+                for (int j = 0; j < UNR; ++j) {
+                    const uint32_t w = __shfl(myw, (int)(j0 + j) & (GW - 1));
+                    const unsigned long long sum = (unsigned long long)d + w;
+                    nd[j] = sum >= INF ? INF - 1 : (uint32_t)sum;
+                }
+#pragma unroll
+                for (int j = 0; j < UNR; ++j)
+                    cur[j] = (act && j0 + j < cnt) ? c.st[(unsigned long long)u[j] * GW + lane] : 0u;
+#pragma unroll
+                for (int j = 0; j < UNR; ++j) {
+                    bool imp = act && j0 + j < cnt && nd[j] < cur[j];
+                    if (imp) imp = nd[j] < dev_min(&c.st[(unsigned long long)u[j] * GW + lane], nd[j]);
+                    c.c_improved += imp ? 1u : 0u;
+                    hit[j] = imp;
+                    val[j] = nd[j];
+                }
+            }
+            // lane j marks the target of edge j0 + j for every lane that hit it
+            unsigned long long mine_bits = 0;
+            uint32_t mine_val = 0, mine_u = 0;
+#pragma unroll
+            for (int j = 0; j < UNR; ++j) {
+                const unsigned long long bm = wballot(hit[j]);
+                const uint32_t first = bm ? (uint32_t)(__ffsll(bm) - 1) : 0u;
+                const uint32_t vj = __shfl(val[j], (int)first);
+                if (lane == (uint32_t)j) { mine_bits = bm; mine_val = vj; mine_u = u[j]; }
+            }
+            if (mine_bits) gmark(c, S, mine_u, mine_bits, mine_val);
+        }
+        c.c_edges += act ? cnt : 0u;
+        if (ppr) c.c_edges_ppr += act ? cnt : 0u;
+        if (lane == 0) {
+            c.c_intra += (unsigned long long)intra * na;  // lane-edges into the partition, once per wave
+            atomicAdd(&S.edges, (unsigned long long)cnt * na);
+        }
+    }
+}
+
+// One visit of the (partition, group) pair of S.it.
+template <int WB>
+__device__ void gvisit(GCtx& c, GShared& S, GCtxShare& SH, const PassCfg& cfg) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t lane = lane_id();
+    c.qt = c.G.gtype[c.grp];
+    c.v0 = c.g.pstart[c.P];
+    c.nvp = c.g.pstart[c.P + 1] - c.v0;
+    const unsigned long long off = c.G.goff[c.grp];
+    c.st = c.G.state + off;
+    c.pp = (float*)(c.G.state + off + (unsigned long long)c.g.nv * GW);
+    c.alpha = c.G.lalpha[c.grp * GW + lane];
+    c.eps = c.G.leps[c.grp * GW + lane];
+    c.mode = c.G.lmode[c.grp * GW + lane];
+    c.win = INF;
+    c.bwin = c.qt == Q_BFS ? cfg.win_lv : cfg.win_sp;
+    if (c.bwin == 0) c.bwin = INF;
+    if (cfg.gate && c.qt != Q_PPR) {
+        const unsigned long long d = c.qt == Q_BFS ? cfg.yld_lv : cfg.yld_sp;
+        const unsigned long long w = (unsigned long long)c.G.gmin[c.grp] + d;
+        c.win = d == 0 ? INF : (w >= INF ? INF : (uint32_t)w);
+    }
+    // the pair's pending vertices: global bitmap -> LDS
+    const uint32_t nw = (c.nvp + 31) / 32;
+    for (uint32_t w = t; w < nw; w += GNT) {
+        const uint32_t u0 = c.v0 + w * 32;  // first vertex of local word w
+        // the partition starts on a multiple of 2^pshift, which may not be a
+        // multiple of 32: gather the 32 bits from up to two global words
+        const uint32_t gw = u0 >> 5, sh = u0 & 31;
+        const uint32_t lim = c.nvp - w * 32 < 32 ? c.nvp - w * 32 : 32;
+        const uint32_t want = lim == 32 ? 0xffffffffu : ((1u << lim) - 1u);
+        uint32_t* base = c.G.bits + (unsigned long long)c.grp * c.G.bw;
+        uint32_t lo = 0, hi = 0;
+        const uint32_t m_lo = want << sh;
+        if (m_lo) lo = atomicAnd(&base[gw], ~m_lo) & m_lo;
+        if (sh) {
+            const uint32_t m_hi = want >> (32 - sh);
+            if (m_hi) hi = atomicAnd(&base[gw + 1], ~m_hi) & m_hi;
+        }
+        S.lbits[w] = (lo >> sh) | (sh ? (hi << (32 - sh)) : 0u);
+    }
+    if (t == 0) S.edges = 0;
+    __syncthreads();
+    unsigned long long budget = 0;
+    if (cfg.mu > 0.f) {
+        const uint32_t np_items = c.B.pn[c.P];
+        const float e_p = (float)(c.g.rowptr[c.v0 + c.nvp] - c.g.rowptr[c.v0]) * (float)GW;
+        const float bgt = cfg.mu * e_p / (float)(np_items ? np_items : 1u);
+        budget = bgt < 16384.f ? 16384ull : (unsigned long long)bgt;
+    }
+    const bool ppr = c.qt == Q_PPR;
+    for (;;) {
+        const uint32_t nr = gtake_round(c, S, ppr ? (uint32_t)PCAP : (uint32_t)RCAP);
+        if (nr == 0) break;
+        if (ppr) {
+            gfilter_ppr(c, S, SH, nr);
+        } else {
+            ground_min(c, S, nr);
+            gfilter_sp(c, S, nr);
+        }
+        const uint32_t ntask = gnumber_tasks(S, nr);
+        if (t == 0) S.next = 0;
+        __syncthreads();
+        gtasks<WB>(c, S, SH, nr, ntask);
+        __syncthreads();
+        if (budget && S.edges >= budget) break;
+    }
+    __syncthreads();
+    // yield: what is still pending in the partition stays in the pair's buffer
+    for (uint32_t w = t; w < nw; w += GNT) {
+        uint32_t word = S.lbits[w];
+        while (word) {
+            const uint32_t b = __ffs(word) - 1;
+            word &= word - 1;
+            const uint32_t vloc = w * 32 + b;
+            const uint32_t u = c.v0 + vloc;
+            // priority of the held-back vertex: its best pending value (PPR: highest priority)
+            uint32_t val = 0u;
+            if (c.qt != Q_PPR) {
+                const unsigned long long m = __hip_atomic_load(&c.G.pend[(unsigned long long)c.grp * c.g.nv + u],
+                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                val = 0xffffffffu;
+                for (unsigned long long mm = m; mm; mm &= mm - 1) {
+                    const uint32_t l = __ffsll(mm) - 1;
+                    const uint32_t x = fresh_load(&c.st[(unsigned long long)u * GW + l]);
+                    val = x < val ? x : val;
+                }
+            }
+            gkeep(c, vloc, val);
+        }
+        S.lbits[w] = 0u;
+    }
+    __syncthreads();
+}
+
+template <int WB>
+__global__ __launch_bounds__(GNT) void k_gprocess(GraphDev g, GroupDev G, BufDev B, PassCfg cfg) {
+    __shared__ GShared S;
+    __shared__ GCtxShare SH;
+    GCtx c;
+    c.g = g;
+    c.G = G;
+    c.B = B;
+    c.c_edges = c.c_intra = c.c_improved = c.c_vpush = c.c_act = c.c_edges_ppr = c.c_vpush_ppr = 0;
+    const uint32_t t = threadIdx.x;
+    const uint32_t xcd = blockIdx.x % NXCD;
+    c.pass = B.ctl->pass;
+    unsigned long long items = 0;
+    for (;;) {
+        if (t == 0) {
+            unsigned long long pos = ~0ull;
+            if (!__hip_atomic_load(&B.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                for (uint32_t k = 0; k < NXCD; ++k) {
+                    const uint32_t x = (xcd + k) % NXCD;
+                    uint32_t n = B.ctl->nitems[x];
+                    n = n < B.item_cap ? n : B.item_cap;
+                    if (__hip_atomic_load(&B.ctl->next[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) continue;
+                    const uint32_t idx = dev_add(&B.ctl->next[x], 1u);
+                    if (idx < n) { pos = (unsigned long long)x * B.item_cap + idx; break; }
+                }
+            }
+            S.itpos = pos;
+        }
+        __syncthreads();
+        const unsigned long long pos = S.itpos;
+        if (pos == ~0ull) break;
+        if (t == 0) { S.it.part = B.items[pos].part; S.it.q = B.items[pos].q; }
+        __syncthreads();
+        c.P = S.it.part;
+        c.grp = S.it.q;
+        ++items;
+        gvisit<WB>(c, S, SH, cfg);
+    }
+    // counters
+    constexpr int NC = 7;
+    unsigned long long v[NC] = {c.c_edges, c.c_intra, c.c_improved, c.c_vpush, c.c_act, c.c_edges_ppr, c.c_vpush_ppr};
+    unsigned long long* dst[NC] = {&B.ctl->c_edges, &B.ctl->c_intra, &B.ctl->c_improved, &B.ctl->c_vpush,
+                                   &B.ctl->c_act, &B.ctl->c_edges_ppr, &B.ctl->c_vpush_ppr};
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        unsigned long long x = v[k];
+#pragma unroll
+        for (int o = 32; o; o >>= 1) x += __shfl_xor(x, o);
+        if ((t & 63) == 0 && x) dev_add(dst[k], x);
+    }
+    if (t == 0 && items) dev_add(&B.ctl->c_items, items);
+}
+
+// Per group: its best pending SSSP/BFS value over all partitions (the
+// query-global dist_min of heuristic 2, taken over the group's queries).
+__global__ void k_gmin(GroupDev G, uint32_t np) {
+    const uint32_t grp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (grp >= G.ng) return;
+    uint32_t m = 0xffffffffu;
+    if (G.gtype[grp] != Q_PPR)
+        for (uint32_t P = 0; P < np; ++P) {
+            const unsigned long long pi = (unsigned long long)P * G.ng + grp;
+            if (G.icnt[pi]) m = G.ibest[pi] < m ? G.ibest[pi] : m;
+        }
+    G.gmin[grp] = m;
+}
+
+// Partition summaries from the pairs' summaries, in the form the scheduler
+// (select step, learned scorer) reads: pending activations, best SSSP
+// distance / BFS level / PPR residual, pairs pending and ready, age.
+__global__ __launch_bounds__(256) void k_gsum(GroupDev G, BufDev B, PassCfg cfg) {
+    const uint32_t P = blockIdx.x;
+    __shared__ unsigned long long s_cnt;
+    __shared__ unsigned int s_sp, s_lv, s_pr, s_ne, s_rd, s_first, s_hm;
+    if (threadIdx.x == 0) { s_cnt = 0; s_sp = INF; s_lv = INF; s_pr = 0; s_ne = 0; s_rd = 0; s_first = INF; s_hm = 0; }
+    __syncthreads();
+    unsigned long long cnt = 0;
+    uint32_t sp = INF, lv = INF, pr = 0, ne = 0, rd = 0, first = INF, hm = 0;
+    for (uint32_t grp = threadIdx.x; grp < G.ng; grp += blockDim.x) {
+        const unsigned long long pi = (unsigned long long)P * G.ng + grp;
+        const uint32_t cb = G.icnt[pi];
+        if (!cb) continue;
+        const uint32_t v = G.ibest[pi], t = G.gtype[grp];
+        cnt += cb;
+        ++ne;
+        if (t == Q_PPR) { const uint32_t m = ~v; pr = m > pr ? m : pr; }
+        else if (t == Q_BFS) lv = v < lv ? v : lv;
+        else sp = v < sp ? v : sp;
+        rd += bucket_ready(v, t, G.gmin[grp], cfg);
+        hm += (t != Q_PPR && v == G.gmin[grp]) ? 1u : 0u;
+        const uint32_t f = G.ifirst[pi];
+        first = f < first ? f : first;
+    }
+    if (cnt) atomicAdd(&s_cnt, cnt);
+    if (sp < INF) atomicMin(&s_sp, sp);
+    if (lv < INF) atomicMin(&s_lv, lv);
+    if (pr) atomicMax(&s_pr, pr);
+    if (ne) atomicAdd(&s_ne, ne);
+    if (rd) atomicAdd(&s_rd, rd);
+    if (first < INF) atomicMin(&s_first, first);
+    if (hm) atomicAdd(&s_hm, hm);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        B.pcount[P] = s_cnt > 0xffffffffull ? 0xffffffffu : (uint32_t)s_cnt;
+        B.pbest_sp[P] = s_sp;
+        B.pbest_lv[P] = s_lv;
+        B.pbest_pr[P] = s_pr;
+        B.pqn[P] = s_ne;
+        B.pready[P] = s_rd;
+        B.pfirst[P] = s_first;
+        B.pqmin[P] = s_hm;
+    }
+}
+
+// Detach the ready pairs of the selected partitions into work items.
+__global__ __launch_bounds__(256) void k_gworklist(BufDev B, GroupDev G, PassCfg cfg) {
+    const uint32_t j = blockIdx.x;
+    Ctl* ctl = B.ctl;
+    if (ctl->err || j >= ctl->nsel) return;
+    const uint32_t P = B.sel[j];
+    const uint32_t x = j % NXCD;
+    const uint32_t grp = blockIdx.y * 256 + threadIdx.x;
+    bool has = false;
+    unsigned long long pi = 0;
+    if (grp < G.ng) {
+        pi = (unsigned long long)P * G.ng + grp;
+        has = G.icnt[pi] && bucket_ready(G.ibest[pi], G.gtype[grp], G.gmin[grp], cfg);
+    }
+    const unsigned long long mask = wballot(has);
+    const uint32_t n = __popcll(mask);
+    if (!n) return;
+    uint32_t base = 0;
+    if (lane_id() == 0) { base = dev_add(&ctl->nitems[x], n); dev_add(&B.pn[P], n); }
+    base = __shfl(base, 0);
+    if (has) {
+        const uint32_t pos = base + rank_in(mask);
+        if (pos < B.item_cap) {
+            Item* it = &B.items[(unsigned long long)x * B.item_cap + pos];
+            it->part = P;
+            it->q = grp;
+            it->nch = 0;
+            it->rest = -1;
+            G.icnt[pi] = 0;
+            G.ibest[pi] = 0xffffffffu;
+            G.ifirst[pi] = 0xffffffffu;
+        } else {
+            dev_or(&ctl->err, (uint32_t)ERR_ITEMS);
+        }
+    }
+}
+
+// Sources: lane l of group g starts at src[g*64 + l] (0xffffffff: unused lane).
+__global__ void k_gseed(GraphDev g, GroupDev G, const uint32_t* src) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= G.ng * GW) return;
+    const uint32_t grp = i / GW, lane = i % GW, s = src[i];
+    if (s >= g.nv) return;
+    uint32_t* st = G.state + G.goff[grp];
+    const bool ppr = G.gtype[grp] == Q_PPR;
+    if (ppr) ((float*)st)[(unsigned long long)s * GW + lane] = 1.0f;
+    else st[(unsigned long long)s * GW + lane] = 0u;
+    dev_or(&G.pend[(unsigned long long)grp * g.nv + s], 1ull << lane);
+    dev_or(&G.bits[(unsigned long long)grp * G.bw + (s >> 5)], 1u << (s & 31));
+    const uint32_t P = g.vpart[s >> g.pshift];
+    const unsigned long long pi = (unsigned long long)P * G.ng + grp;
+    dev_add(&G.icnt[pi], 1u);
+    dev_min(&G.ibest[pi], ppr ? ~__float_as_uint(1.0f) : 0u);
+    dev_min(&G.ifirst[pi], 0u);
+}
+
+// Group state (vertex-major rows of 64 lanes) -> per-query vectors.  One
+// block transposes a tile of 64 vertices x 64 lanes of one group.
+__global__ __launch_bounds__(256) void k_gout(GroupDev G, uint32_t nv, uint32_t* out, const unsigned long long* qoff,
+                                              const uint32_t* lq) {
+    __shared__ uint32_t tile[GW][GW + 1];
+    const uint32_t grp = blockIdx.y, v0 = blockIdx.x * GW;
+    const bool ppr = G.gtype[grp] == Q_PPR;
+    const uint32_t* src = G.state + G.goff[grp];
+    for (int part = 0; part < (ppr ? 2 : 1); ++part) {
+        // PPR: part 0 = p (the second block of the group state), part 1 = r
+        const uint32_t* s = src + (ppr && part == 0 ? (unsigned long long)nv * GW : 0ull);
+        for (uint32_t i = threadIdx.x; i < GW * GW; i += blockDim.x) {
+            const uint32_t dv = i / GW, l = i % GW;
+            tile[dv][l] = v0 + dv < nv ? s[(unsigned long long)(v0 + dv) * GW + l] : 0u;
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < GW * GW; i += blockDim.x) {
+            const uint32_t l = i / GW, dv = i % GW;
+            const uint32_t q = lq[grp * GW + l];
+            if (q != 0xffffffffu && v0 + dv < nv)
+                out[qoff[q] + (ppr && part == 1 ? nv : 0u) + v0 + dv] = tile[dv][l];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_gprocess(const GraphDev& g, const GroupDev& G, const BufDev& B, const PassCfg& cfg, uint32_t blocks,
+                           hipStream_t s) {
+    switch (g.wbytes) {
+    case 0: hipLaunchKernelGGL((k_gprocess<0>), dim3(blocks), dim3(GNT), 0, s, g, G, B, cfg); break;
+    case 1: hipLaunchKernelGGL((k_gprocess<1>), dim3(blocks), dim3(GNT), 0, s, g, G, B, cfg); break;
+    case 2: hipLaunchKernelGGL((k_gprocess<2>), dim3(blocks), dim3(GNT), 0, s, g, G, B, cfg); break;
+    default: hipLaunchKernelGGL((k_gprocess<4>), dim3(blocks), dim3(GNT), 0, s, g, G, B, cfg); break;
+    }
+    return hipGetLastError();
+}
+const void* gprocess_kernel_ptr(int wbytes) {
+    switch (wbytes) {
+    case 0: return (const void*)k_gprocess<0>;
+    case 1: return (const void*)k_gprocess<1>;
+    case 2: return (const void*)k_gprocess<2>;
+    default: return (const void*)k_gprocess<4>;
+    }
+}
+hipError_t launch_gsummaries(const GraphDev& g, const GroupDev& G, const BufDev& B, const PassCfg& cfg, hipStream_t s) {
+    hipLaunchKernelGGL(k_gmin, dim3((G.ng + 255) / 256), dim3(256), 0, s, G, g.np);
+    hipLaunchKernelGGL(k_gsum, dim3(g.np), dim3(256), 0, s, G, B, cfg);
+    return hipGetLastError();
+}
+hipError_t launch_gworklist(const BufDev& B, const GroupDev& G, const PassCfg& cfg, hipStream_t s) {
+    dim3 grid(cfg.kmax, (G.ng + 255) / 256);
+    hipLaunchKernelGGL(k_gworklist, grid, dim3(256), 0, s, B, G, cfg);
+    return hipGetLastError();
+}
+hipError_t launch_gseed(const GraphDev& g, const GroupDev& G, const uint32_t* src, hipStream_t s) {
+    hipLaunchKernelGGL(k_gseed, dim3((G.ng * GW + 255) / 256), dim3(256), 0, s, g, G, src);
+    return hipGetLastError();
+}
+hipError_t launch_gout(const GroupDev& G, uint32_t nv, uint32_t* out, const unsigned long long* qoff, const uint32_t* lq,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_gout, dim3((nv + GW - 1) / GW, G.ng), dim3(256), 0, s, G, nv, out, qoff, lq);
+    return hipGetLastError();
+}
+int gprocess_threads() { return GNT; }
+size_t group_dev_bytes() { return sizeof(GroupDev); }
+
+}  // namespace fk

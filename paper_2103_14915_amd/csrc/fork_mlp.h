@@ -17,7 +17,7 @@ struct GStat {
 };
 
 // Normalisation ranges over all partitions (one block).
-__device__ void gstat_body(const GraphDev& g, const BufDev& B, GStat* out) {
+__device__ inline void gstat_body(const GraphDev& g, const BufDev& B, GStat* out) {
     __shared__ GStat s;
     if (threadIdx.x == 0) {
         s.sp_min = INF; s.sp_max = 0; s.lv_min = INF; s.lv_max = 0;
@@ -43,7 +43,7 @@ __device__ void gstat_body(const GraphDev& g, const BufDev& B, GStat* out) {
 // their presence flags, recency, visits, partition size, age of the oldest
 // buffered operation, and the share and count of its buffers that hold their
 // query's dist_min.
-__device__ void partition_features(const GraphDev& g, const BufDev& B, const GStat& s, uint32_t pass, uint32_t P,
+__device__ inline void partition_features(const GraphDev& g, const BufDev& B, const GStat& s, uint32_t pass, uint32_t P,
                                    float* x) {
     uint32_t cnt = B.pcount[P];
     uint32_t sp = B.pbest_sp[P], lv = B.pbest_lv[P];

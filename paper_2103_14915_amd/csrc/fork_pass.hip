@@ -62,6 +62,7 @@ struct PassShared {
     uint32_t cpre[CCAP];          // exclusive prefix of ccnt
     uint32_t stash[STASH];        // free chunks owned by this workgroup
     uint32_t nstash, nrefill;
+    uint32_t nspill;              // activated vertices this item retained (frontier full)
     uint32_t wred[NW];
     uint32_t nf, nk, nb, ns, ncl, cur;
     int32_t chnext;
@@ -549,6 +550,8 @@ __device__ __forceinline__ void push_frontier(ItemCtx& c, PassShared& S, uint32_
     bool fits = want && p < (uint32_t)FCAP;
     if (fits) S.fq[cur][p] = vloc;
     c.c_spill += (want && !fits) ? 1u : 0u;
+    const unsigned long long sm = wballot(want && !fits);
+    if (sm && (threadIdx.x & 63) == 0) atomicAdd(&S.nspill, (uint32_t)__popcll(sm));
     stage(S, want && !fits, c.v0 + vloc, retain_val);
 }
 
@@ -1004,7 +1007,7 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
         }
         if (!c.hn)
             for (uint32_t i = t; i < (c.nvp + 31) / 32; i += NT) c.bits[i] = 0u;
-        if (t == 0) { S.nf = 0; S.ns = 0; S.cur = 0; }
+        if (t == 0) { S.nf = 0; S.ns = 0; S.cur = 0; S.nspill = 0; }
         __syncthreads();
         uint32_t budget = 0;
         if (cfg.mu > 0.f) {
@@ -1019,6 +1022,10 @@ __device__ __forceinline__ void process_items(ItemCtx& c, PassShared& S, const P
         else if (c.qt == Q_BFS) sp_visit<0>(c, S, cfg.win_lv, cfg.yld_lv, budget);
         else sp_visit<WB>(c, S, cfg.win_sp, cfg.yld_sp, budget);
         flush(c, S);
+        if (t == 0 && S.nspill) {
+            dev_max(&B.ctl->c_spill_max, S.nspill);
+            if (S.nspill > SPILL_MAX) dev_or(&B.ctl->err, (uint32_t)ERR_SPILL);
+        }
         // write the touched part of the slice back
         if (c.hn) {
             for (uint32_t i = t; i < c.hn; i += NT) {

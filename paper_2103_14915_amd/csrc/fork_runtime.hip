@@ -52,18 +52,25 @@ const void* process_kernel_ptr(int wbytes);
 const void* persistent_kernel_ptr(int wbytes);
 hipError_t launch_persistent(const GraphDev&, const QueryDev&, const BufDev&, const PassCfg&, uint32_t, uint32_t,
                              uint32_t, uint32_t, const float*, float*, void*, hipStream_t);
+hipError_t launch_gprocess(const GraphDev&, const GroupDev&, const BufDev&, const PassCfg&, uint32_t, hipStream_t);
+const void* gprocess_kernel_ptr(int wbytes);
+int gprocess_threads();
+hipError_t launch_gsummaries(const GraphDev&, const GroupDev&, const BufDev&, const PassCfg&, hipStream_t);
+hipError_t launch_gworklist(const BufDev&, const GroupDev&, const PassCfg&, hipStream_t);
+hipError_t launch_gseed(const GraphDev&, const GroupDev&, const uint32_t*, hipStream_t);
+hipError_t launch_gout(const GroupDev&, uint32_t, uint32_t*, const unsigned long long*, const uint32_t*, hipStream_t);
 }  // namespace fk
 
-static thread_local std::string g_err;
+// Message of the last failing call on this thread (a fixed buffer: reporting
+// an error allocates nothing).
+static thread_local char g_err[512];
 
 static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 static int fail(int code, const char* fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -151,14 +158,26 @@ struct fork_ctx {
     fork_stats_t stats{};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> pev;  // pass-kernel timing events (profile mode)
-    int blocks_per_cu = 1, num_cu = 1, pers_blocks_per_cu = 0;
+    int blocks_per_cu = 1, num_cu = 1, pers_blocks_per_cu = 0, group_blocks_per_cu = 0;
+    // grouped engine (grow-only buffers)
+    uint32_t* d_gstate = nullptr;
+    size_t gstate_cap = 0;
+    unsigned long long* d_gpend = nullptr;
+    uint32_t* d_gbits = nullptr;
+    size_t gpend_cap = 0, gbits_cap = 0;
+    uint32_t *d_icnt = nullptr, *d_ibest = nullptr, *d_ifirst = nullptr, *d_gmin = nullptr;
+    size_t pair_cap = 0, grp_cap = 0;
+    uint32_t *d_gtype = nullptr, *d_lmode = nullptr, *d_lq = nullptr, *d_lsrc = nullptr;
+    unsigned long long* d_goff = nullptr;
+    float *d_lalpha = nullptr, *d_leps = nullptr;
     uint32_t hslots = 0;  // hashed LDS slice slots of the current run (0 = dense slice)
     bool dense_ok = true; // the dense slice of the largest partition fits in LDS
+    bool spill_refused = false;  // the last run stopped at the frontier-spill bound
     uint32_t vpmax = 1;  // largest partition (vertices)
     double wmean = 1.0;  // mean edge weight
 };
 
-extern "C" const char* fork_last_error(void) { return g_err.c_str(); }
+extern "C" const char* fork_last_error(void) { return g_err; }
 
 template <class T> static int dalloc(T** p, size_t n) {
     if (n == 0) n = 1;
@@ -209,6 +228,9 @@ extern "C" void fork_destroy(fork_ctx* c) {
                     c->d_score, c->d_mlp,
                     c->d_ctl, c->d_gstat, c->d_feat, c->d_tr, c->d_final, c->d_pos, c->d_orig, c->d_gather, c->d_rrow, c->d_rcol, c->d_sdeg};
     for (void* p : ptrs) if (p) hipFree(p);
+    void* gptrs[] = {c->d_gstate, c->d_gpend, c->d_gbits, c->d_icnt, c->d_ibest, c->d_ifirst, c->d_gmin, c->d_gtype,
+                     c->d_lmode, c->d_lq, c->d_lsrc, c->d_goff, c->d_lalpha, c->d_leps};
+    for (void* p : gptrs) if (p) hipFree(p);
     if (c->h_ctl) hipHostFree(c->h_ctl);
     for (auto& e : c->ev) if (e) hipEventDestroy(e);
     for (auto& e : c->pev) if (e) hipEventDestroy(e);
@@ -261,7 +283,7 @@ static int set_slice(fork_ctx* c, uint32_t hs) {
 
 extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const uint64_t* row_ptr,
                                const uint32_t* col, const uint32_t* weight, const fork_config* cfg_in) {
-    g_err.clear();
+    g_err[0] = 0;
     if (!out) return fail(FORK_E_INVALID, "out is NULL");
     *out = nullptr;
     if (nv == 0) return fail(FORK_E_INVALID, "num_vertices must be >= 1");
@@ -430,7 +452,7 @@ extern "C" int fork_graph_load(fork_ctx** out, uint32_t nv, uint64_t ne, const u
     // the dense slice (one LDS word per partition vertex) when it fits, else a hashed one
     if (set_slice(c, 0) != FORK_OK) {
         (void)hipGetLastError();
-        g_err.clear();
+        g_err[0] = 0;
         c->dense_ok = false;
         if ((rc = set_slice(c, fk::HS_AUTO))) return cleanup(rc);
     }
@@ -450,7 +472,7 @@ extern "C" int fork_partitions(fork_ctx* c, uint32_t* starts, uint32_t cap, uint
 
 extern "C" int fork_submit(fork_ctx* c, int type, const uint32_t* sources, uint32_t n, const void* params,
                            uint32_t* first_id) {
-    g_err.clear();
+    g_err[0] = 0;
     if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
     if (type != FORK_SSSP && type != FORK_BFS && type != FORK_PPR) return fail(FORK_E_INVALID, "bad query type %d", type);
     if (n && !sources) return fail(FORK_E_INVALID, "sources is NULL");
@@ -801,6 +823,12 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
         }
         const fk::Ctl& h = *c->h_ctl;
         if (h.err & fk::ERR_CORRUPT) return fail(FORK_E_DEVICE, "device consistency check failed (flags 0x%x)", h.err);
+        if (h.err & fk::ERR_SPILL) {
+            c->spill_refused = true;
+            return fail(FORK_E_CAPACITY, "a visit retained %u activated vertices as buffered operations (frontier "
+                        "full), more than the bound of %u: this frontier-spill regime is refused; load the graph "
+                        "with smaller partitions", h.c_spill_max, fk::SPILL_MAX);
+        }
         if (h.err & fk::ERR_CAPACITY)
             return fail(FORK_E_CAPACITY, "operation pool exhausted (%llu chunks) with %u queries in flight",
                         c->nch, nq);
@@ -852,6 +880,221 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
     st.ppr_edges += h.c_edges_ppr;
     st.ppr_vertex_pushes += h.c_vpush_ppr;
     st.spilled += h.c_spill;
+    st.spill_max = std::max<uint64_t>(st.spill_max, h.c_spill_max);
+    st.waves += 1;
+    c->res_first = q0;
+    c->res_n = nq;
+    c->res_off.assign(qo.begin(), qo.end());
+    return FORK_OK;
+}
+
+// Grow-only device buffer of n elements.
+template <class T> static int grow(T** p, size_t& cap, size_t n) {
+    if (n <= cap && *p) return FORK_OK;
+    hipFree(*p);
+    *p = nullptr;
+    cap = 0;
+    int rc = dalloc(p, n);
+    if (rc) return rc;
+    cap = n;
+    return FORK_OK;
+}
+
+// One wave on the grouped engine: the wave's queries of each type are taken
+// 64 at a time as lane groups with vertex-major state rows.  The result vectors
+// are written in the per-query layout of run_wave at the end, so fetch,
+// digests, sweeps and BC read them the same way.
+static int run_wave_group(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& o, hipStream_t s,
+                          const fk::PassCfg& cfg, uint64_t& passes_left) {
+    constexpr uint32_t GW = 64;
+    std::vector<uint32_t> qt(nq), qm(nq);
+    std::vector<unsigned long long> qo(nq);
+    std::vector<float> qa(nq), qe(nq);
+    size_t words = 0;
+    bool mixed = false;
+    for (uint32_t i = 0; i < nq; ++i) {
+        const QueryRec& r = c->queries[q0 + i];
+        qt[i] = r.type; qm[i] = r.mode; qa[i] = r.alpha; qe[i] = r.eps;
+        qo[i] = words;
+        words += qwords(c, r.type);
+        if (r.type != c->queries[q0].type) mixed = true;
+    }
+    // lane groups: queries of one type in submit order, 64 to a group
+    std::vector<uint32_t> gtype, lq, lsrc, lmode;
+    std::vector<unsigned long long> goff;
+    std::vector<float> lalpha, leps;
+    size_t gwords = 0;
+    for (uint32_t t : {(uint32_t)FORK_SSSP, (uint32_t)FORK_BFS, (uint32_t)FORK_PPR}) {
+        std::vector<uint32_t> idx;
+        for (uint32_t i = 0; i < nq; ++i) if (qt[i] == t) idx.push_back(i);
+        for (size_t k = 0; k < idx.size(); k += GW) {
+            gtype.push_back(t);
+            goff.push_back(gwords);
+            gwords += (t == FORK_PPR ? 2ull : 1ull) * c->nv * GW;
+            for (uint32_t l = 0; l < GW; ++l) {
+                if (k + l < idx.size()) {
+                    const QueryRec& r = c->queries[q0 + idx[k + l]];
+                    lq.push_back(idx[k + l]); lsrc.push_back(r.src); lmode.push_back(r.mode);
+                    lalpha.push_back(r.alpha); leps.push_back(r.eps);
+                } else {
+                    lq.push_back(0xffffffffu); lsrc.push_back(0xffffffffu); lmode.push_back(0);
+                    lalpha.push_back(0.15f); leps.push_back(1.0f);
+                }
+            }
+        }
+    }
+    const uint32_t ng = (uint32_t)gtype.size();
+    if (c->vpmax > 16384)
+        return fail(FORK_E_INVALID, "the grouped engine needs partitions of at most 16384 vertices (this graph's "
+                    "largest has %u; load it with partition_vertices <= 16384)", c->vpmax);
+    int rc = ensure_wave(c, nq, words, cfg.kmax);
+    if (rc) return rc;
+    if ((uint64_t)ng * ((cfg.kmax + fk::NXCD - 1) / fk::NXCD) > (uint64_t)c->item_cap)
+        return fail(FORK_E_DEVICE, "grouped engine: item list too small");
+    const uint32_t bw = c->nv / 32 + 2;
+    const size_t npairs = (size_t)c->np * ng;
+    if ((rc = grow(&c->d_gstate, c->gstate_cap, gwords))) return rc;
+    if ((rc = grow(&c->d_gpend, c->gpend_cap, (size_t)ng * c->nv))) return rc;
+    if ((rc = grow(&c->d_gbits, c->gbits_cap, (size_t)ng * bw))) return rc;
+    {
+        size_t cap = c->pair_cap;
+        if ((rc = grow(&c->d_icnt, cap, npairs))) return rc;
+        cap = c->pair_cap;
+        if ((rc = grow(&c->d_ibest, cap, npairs))) return rc;
+        cap = c->pair_cap;
+        if ((rc = grow(&c->d_ifirst, cap, npairs))) return rc;
+        c->pair_cap = std::max(c->pair_cap, npairs);
+    }
+    if (c->grp_cap < ng) {
+        void* gp[] = {c->d_gmin, c->d_gtype, c->d_goff, c->d_lq, c->d_lsrc, c->d_lmode, c->d_lalpha, c->d_leps};
+        for (void* q : gp) hipFree(q);
+        c->d_gmin = c->d_gtype = c->d_lq = c->d_lsrc = c->d_lmode = nullptr;
+        c->d_goff = nullptr;
+        c->d_lalpha = c->d_leps = nullptr;
+        c->grp_cap = 0;
+        if ((rc = dalloc(&c->d_gmin, ng)) || (rc = dalloc(&c->d_gtype, ng)) || (rc = dalloc(&c->d_goff, ng)) ||
+            (rc = dalloc(&c->d_lq, (size_t)ng * GW)) || (rc = dalloc(&c->d_lsrc, (size_t)ng * GW)) ||
+            (rc = dalloc(&c->d_lmode, (size_t)ng * GW)) || (rc = dalloc(&c->d_lalpha, (size_t)ng * GW)) ||
+            (rc = dalloc(&c->d_leps, (size_t)ng * GW)))
+            return rc;
+        c->grp_cap = ng;
+    }
+    if (c->group_blocks_per_cu <= 0) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fk::gprocess_kernel_ptr(c->wbytes),
+                                                         fk::gprocess_threads(), 0) != hipSuccess || occ <= 0)
+            return fail(FORK_E_DEVICE, "grouped pass kernel does not fit on a CU");
+        c->group_blocks_per_cu = occ;
+    }
+    HIPCHK(hipMemcpyAsync(c->d_qtype, qt.data(), nq * 4ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_qmode, qm.data(), nq * 4ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_qoff, qo.data(), nq * 8ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_qalpha, qa.data(), nq * 4ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_qeps, qe.data(), nq * 4ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_gtype, gtype.data(), ng * 4ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_goff, goff.data(), ng * 8ull, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_lq, lq.data(), lq.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_lsrc, lsrc.data(), lsrc.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_lmode, lmode.data(), lmode.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_lalpha, lalpha.data(), lalpha.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_leps, leps.data(), leps.size() * 4, hipMemcpyHostToDevice, s));
+    fk::PassCfg pc = cfg;
+    pc.mixed = mixed ? 1u : 0u;
+    pc.trace = 0;
+    fk::QueryDev Q;
+    Q.nq = nq; Q.qc = c->qcap; Q.qtype = c->d_qtype; Q.qoff = c->d_qoff; Q.qalpha = c->d_qalpha;
+    Q.qeps = c->d_qeps; Q.qmode = c->d_qmode; Q.state = c->d_state; Q.final_state = nullptr;
+    fk::GroupDev G;
+    G.ng = ng; G.gtype = c->d_gtype; G.goff = c->d_goff; G.lalpha = c->d_lalpha; G.leps = c->d_leps;
+    G.lmode = c->d_lmode; G.state = c->d_gstate; G.pend = c->d_gpend; G.bits = c->d_gbits; G.bw = bw;
+    G.icnt = c->d_icnt; G.ibest = c->d_ibest; G.ifirst = c->d_ifirst; G.gmin = c->d_gmin;
+    fk::GraphDev g = graph_dev(c);
+    fk::BufDev B = buf_dev(c);
+    HIPCHK(hipEventRecord(c->ev[0], s));
+    for (uint32_t k = 0; k < ng; ++k) {
+        const size_t n = (size_t)c->nv * GW;
+        if (gtype[k] == FORK_PPR) HIPCHK(hipMemsetAsync(c->d_gstate + goff[k], 0, 2 * n * 4, s));
+        else HIPCHK(hipMemsetD32Async((hipDeviceptr_t)(c->d_gstate + goff[k]), (int)fk::INF, n, s));
+    }
+    HIPCHK(hipMemsetAsync(c->d_gpend, 0, (size_t)ng * c->nv * 8, s));
+    HIPCHK(hipMemsetAsync(c->d_gbits, 0, (size_t)ng * bw * 4, s));
+    HIPCHK(hipMemsetAsync(c->d_icnt, 0, npairs * 4, s));
+    HIPCHK(hipMemsetAsync(c->d_ibest, 0xff, npairs * 4, s));
+    HIPCHK(hipMemsetAsync(c->d_ifirst, 0xff, npairs * 4, s));
+    HIPCHK(hipMemsetAsync(c->d_pcount, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->d_pbest_sp, (int)fk::INF, c->np + 1, s));
+    HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->d_pbest_lv, (int)fk::INF, c->np + 1, s));
+    HIPCHK(hipMemsetAsync(c->d_pbest_pr, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->d_pfirst, (int)fk::INF, c->np + 1, s));
+    HIPCHK(hipMemsetAsync(c->d_plast, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetAsync(c->d_pvisits, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetAsync(c->d_pn, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetAsync(c->d_pqn, 0, (c->np + 1) * 4ull, s));
+    HIPCHK(hipMemsetAsync(c->d_pqmin, 0, (c->np + 1) * 4ull, s));
+    fk::Ctl ctl0{};
+    *c->h_ctl = ctl0;
+    HIPCHK(hipMemcpyAsync(c->d_ctl, c->h_ctl, sizeof(fk::Ctl), hipMemcpyHostToDevice, s));
+    HIPCHK(fk::launch_gseed(g, G, c->d_lsrc, s));
+    HIPCHK(hipEventRecord(c->ev[1], s));
+    const uint32_t blocks = (uint32_t)std::max(1, c->num_cu * c->group_blocks_per_cu);
+    uint32_t batch = 1;
+    while (true) {
+        uint32_t nb = batch;
+        if (passes_left != ~0ull) nb = (uint32_t)std::min<uint64_t>(nb, passes_left);
+        if (nb == 0) return fail(FORK_E_NOT_CONVERGED, "max_passes reached with work pending");
+        if (o.profile && c->pev.size() < 2 * nb) {
+            size_t old = c->pev.size();
+            c->pev.resize(2 * nb, nullptr);
+            for (size_t k = old; k < c->pev.size(); ++k) HIPCHK(hipEventCreate(&c->pev[k]));
+        }
+        for (uint32_t k = 0; k < nb; ++k) {
+            HIPCHK(fk::launch_gsummaries(g, G, B, pc, s));
+            if (pc.sched == fk::S_LEARNED)
+                HIPCHK(fk::launch_mlp_score(g, B, c->d_mlp, c->d_score, nullptr, c->d_gstat, 0, s));
+            HIPCHK(fk::launch_select(g, B, pc, s));
+            HIPCHK(fk::launch_gworklist(B, G, pc, s));
+            if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k], s));
+            HIPCHK(fk::launch_gprocess(g, G, B, pc, blocks, s));
+            if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k + 1], s));
+        }
+        if (passes_left != ~0ull) passes_left -= nb;
+        HIPCHK(hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(fk::Ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (o.profile) {
+            for (uint32_t k = 0; k < nb; ++k) {
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, c->pev[2 * k], c->pev[2 * k + 1]));
+                c->stats.process_ms += ms;
+            }
+            c->stats.process_launches += nb;
+        }
+        const fk::Ctl& h = *c->h_ctl;
+        if (h.err) return fail(FORK_E_DEVICE, "device error flags 0x%x", h.err);
+        if (h.pending_parts == 0) break;
+        batch = std::min<uint32_t>(batch * 2, 64);
+    }
+    HIPCHK(fk::launch_gout(G, c->nv, c->d_state, c->d_qoff, c->d_lq, s));
+    HIPCHK(hipEventRecord(c->ev[2], s));
+    HIPCHK(hipStreamSynchronize(s));
+    float t_init = 0, t_run = 0;
+    hipEventElapsedTime(&t_init, c->ev[0], c->ev[1]);
+    hipEventElapsedTime(&t_run, c->ev[1], c->ev[2]);
+    c->resQ = Q;
+    c->dig_pending = true;
+    const fk::Ctl& h = *c->h_ctl;
+    fork_stats_t& st = c->stats;
+    st.init_ms += t_init;
+    st.run_ms += t_run;
+    st.passes += h.pass;
+    st.work_items += h.c_items;
+    st.edges += h.c_edges;
+    st.improved += h.c_improved;
+    st.vertex_pushes += h.c_vpush;
+    st.intra_edges += h.c_intra;
+    st.selected_edges += h.c_sel_edges;
+    st.ppr_edges += h.c_edges_ppr;
+    st.ppr_vertex_pushes += h.c_vpush_ppr;
+    st.activations += h.c_act;
     st.waves += 1;
     c->res_first = q0;
     c->res_n = nq;
@@ -860,7 +1103,7 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
 }
 
 extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
-    g_err.clear();
+    g_err[0] = 0;
     if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
     if (c->queries.empty()) return fail(FORK_E_STATE, "no queries submitted");
     fork_run_opts o{};
@@ -868,6 +1111,14 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     if (opts) o = *opts;
     if (o.scheduler < 0 || o.scheduler > FORK_SCHED_MAXOPS) return fail(FORK_E_INVALID, "bad scheduler %d", o.scheduler);
     if (o.scheduler == FORK_SCHED_LEARNED && !o.mlp_weights) return fail(FORK_E_INVALID, "LEARNED needs mlp_weights");
+    if (o.engine != FORK_ENGINE_BUFFERED && o.engine != FORK_ENGINE_GROUPED)
+        return fail(FORK_E_INVALID, "bad engine %d", o.engine);
+    const bool grouped = o.engine == FORK_ENGINE_GROUPED;
+    if (grouped && (o.persistent || o.trace))
+        return fail(FORK_E_INVALID, "the grouped engine runs per-pass kernels without traces (persistent = trace = 0)");
+    if (grouped)
+        for (const QueryRec& r : c->queries)
+            if (r.l1 > 0.f) return fail(FORK_E_INVALID, "certified PPR (l1_target > 0) runs on the buffered engine");
     if (o.slice_slots && (o.slice_slots < 256 || o.slice_slots > 16384 || (o.slice_slots % 256)))
         return fail(FORK_E_INVALID, "slice_slots must be 0 or a multiple of 256 in [256, 16384], got %u", o.slice_slots);
     if (hipSetDevice(c->device) != hipSuccess) return fail(FORK_E_DEVICE, "hipSetDevice failed");
@@ -893,8 +1144,10 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     size_t budget = (fr + reserve) > ((size_t)2 << 30) ? (fr + reserve) - ((size_t)2 << 30) : 0;
     budget = (size_t)(budget * 0.9);
     uint32_t cap_q = c->max_queries ? c->max_queries : nq_total;
-    // per-query bytes beyond state: buckets (28 B per partition) + items
-    const size_t per_q_extra = (size_t)c->np * 28 + 64;
+    // per-query bytes beyond state: buckets (28 B per partition) + items; the
+    // grouped engine holds its own copy of the state rows plus 8 B of pending
+    // lanes and 4 B of pair summaries per vertex and group
+    const size_t per_q_extra = (size_t)c->np * 28 + 64 + (grouped ? (size_t)c->nv * 8 / 64 + (size_t)c->np * 12 / 64 + 64 : 0);
     fk::PassCfg cfg{};
     cfg.sched = (uint32_t)o.scheduler;
     cfg.seed = (uint32_t)o.seed;
@@ -919,7 +1172,7 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
         size_t bytes = 0;
         uint32_t n = 0;
         while (q0 + n < nq_total && n < cap_q) {
-            size_t b = qwords(c, c->queries[q0 + n].type) * 4 + per_q_extra;
+            size_t b = qwords(c, c->queries[q0 + n].type) * 4 * (grouped ? 2 : 1) + per_q_extra;
             if (n > 0 && bytes + b > budget) break;
             bytes += b;
             ++n;
@@ -934,6 +1187,7 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     cfg.kmax = o.parts_per_pass ? std::min<uint32_t>(o.parts_per_pass, c->np) : c->np;
     cfg.target_items = o.parts_per_pass ? 0u : (o.items_per_pass ? o.items_per_pass : 16u * slots);
     c->stats = fork_stats_t{};
+    c->spill_refused = false;
     c->trace.clear();
     if (o.trace && o.persistent) return fail(FORK_E_INVALID, "trace runs use the per-pass kernels (persistent = 0)");
     c->stats.num_partitions = c->np;
@@ -953,7 +1207,8 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
         }
         uint64_t saved = passes_left;
         fork_stats_t saved_st = c->stats;
-        int rc = run_wave(c, q0, n, o, s, cfg, passes_left, false);
+        int rc = grouped ? run_wave_group(c, q0, n, o, s, cfg, passes_left)
+                         : run_wave(c, q0, n, o, s, cfg, passes_left, false);
         if (rc == FORK_OK && o.trace) {
             // traced re-run: the final state of the first run marks useful work
             size_t words = c->state_words_cap;
@@ -969,7 +1224,7 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
             uint64_t pl = ~0ull;
             rc = run_wave(c, q0, n, o, s, cfg, pl, true);
         }
-        if (rc == FORK_E_CAPACITY && n > 1) {
+        if (rc == FORK_E_CAPACITY && n > 1 && !c->spill_refused) {
             passes_left = saved;
             c->stats = saved_st;
             wave_cap = n / 2;
@@ -986,7 +1241,7 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
 }
 
 extern "C" int fork_fetch(fork_ctx* c, uint32_t qid, int field, void* dst, uint64_t dst_bytes, int dst_on_device) {
-    g_err.clear();
+    g_err[0] = 0;
     if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
     if (!dst) return fail(FORK_E_INVALID, "dst is NULL");
     if (qid >= c->queries.size()) return fail(FORK_E_INVALID, "query id %u out of range", qid);
@@ -1066,7 +1321,7 @@ static int build_reverse(fork_ctx* c) {
 }
 
 extern "C" int fork_sweep(fork_ctx* c, uint32_t first, uint32_t n, uint32_t max_size, fork_sweep_t* out) {
-    g_err.clear();
+    g_err[0] = 0;
     if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
     if (!out && n) return fail(FORK_E_INVALID, "out is NULL");
     if (max_size < 1 || max_size > FORK_SWEEP_MAX) return fail(FORK_E_INVALID, "max_size must be in [1, %d]", FORK_SWEEP_MAX);
@@ -1103,7 +1358,7 @@ extern "C" int fork_sweep(fork_ctx* c, uint32_t first, uint32_t n, uint32_t max_
 }
 
 extern "C" int fork_bc(fork_ctx* c, uint32_t first, uint32_t n, double* out) {
-    g_err.clear();
+    g_err[0] = 0;
     if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
     if (!out) return fail(FORK_E_INVALID, "out is NULL");
     if ((uint64_t)first + n > c->queries.size()) return fail(FORK_E_INVALID, "query range out of bounds");
@@ -1201,7 +1456,7 @@ int mlp_check(const float* theta, const float* x, uint64_t n) {
 }  // namespace
 
 extern "C" int fork_mlp_forward(const float* theta, const float* x, uint64_t n, float* y) {
-    g_err.clear();
+    g_err[0] = 0;
     int rc = mlp_check(theta, x, n);
     if (rc) return rc;
     if (!y) return fail(FORK_E_INVALID, "y is NULL");
@@ -1216,7 +1471,7 @@ extern "C" int fork_mlp_forward(const float* theta, const float* x, uint64_t n, 
 
 extern "C" int fork_mlp_grad(const float* theta, const float* x, const float* t, uint64_t n, float* grad,
                              float* loss) {
-    g_err.clear();
+    g_err[0] = 0;
     int rc = mlp_check(theta, x, n);
     if (rc) return rc;
     if (!t || !grad || !loss || n == 0) return fail(FORK_E_INVALID, "NULL argument or no samples");
@@ -1237,7 +1492,7 @@ extern "C" int fork_mlp_grad(const float* theta, const float* x, const float* t,
 
 extern "C" int fork_mlp_train(float* theta, const float* x, const float* t, uint64_t n, uint32_t steps,
                               uint32_t batch, float lr, uint64_t seed, float* losses) {
-    g_err.clear();
+    g_err[0] = 0;
     int rc = mlp_check(theta, x, n);
     if (rc) return rc;
     if (!t || n == 0 || batch == 0 || !(lr > 0.f)) return fail(FORK_E_INVALID, "bad training arguments");
@@ -1279,3 +1534,4 @@ extern "C" int fork_mlp_train(float* theta, const float* x, const float* t, uint
     if (losses && steps) HIPCHK(hipMemcpy(losses, dl.p, steps * 4ull, hipMemcpyDeviceToHost));
     return FORK_OK;
 }
+

@@ -259,7 +259,7 @@ __device__ __forceinline__ void qmin_one(const BufDev& B, const QueryDev& Q, uin
 // SSSP distance / BFS level / PPR mass, non-empty and ready buffers, age of
 // the oldest buffer.  These are what the priority functor and the learned
 // scorer read.
-__device__ void psum_one(const BufDev& B, const QueryDev& Q, const PassCfg& cfg, uint32_t P) {
+__device__ inline void psum_one(const BufDev& B, const QueryDev& Q, const PassCfg& cfg, uint32_t P) {
     __shared__ unsigned long long s_cnt;
     __shared__ unsigned int s_sp, s_lv, s_pr, s_ne, s_rd, s_first, s_hm;
     if (threadIdx.x == 0) { s_cnt = 0; s_sp = INF; s_lv = INF; s_pr = 0; s_ne = 0; s_rd = 0; s_first = INF; s_hm = 0; }

@@ -76,6 +76,8 @@ class SimtGraph:
 
     def run(self, **kw):
         o = fork.fork_run_opts(scheduler=fork.SCHEDS[kw.pop("scheduler", "priority")])
+        if isinstance(kw.get("engine"), str):
+            kw["engine"] = fork.ENGINES[kw["engine"]]
         for k, v in kw.items():
             setattr(o, k, v)
         self._check(self.lib.fork_run(self.ctx, ctypes.byref(o)))

@@ -134,3 +134,28 @@ def test_checker_sees_planted_mistakes(fs, plant, expect):
     assert line, (r.returncode, r.stderr[-2000:])
     c = json.loads(line[-1])["check"]
     assert c["failures"] >= 1 and expect in c["message"], c
+
+
+def test_grouped_engine_exact_under_concurrency(fs):
+    """The grouped engine on the host (real concurrency between workgroups):
+    SSSP/BFS bit-exact and PPR within the push gates, with a partial group."""
+    lib = fs.load()
+    g = fi.rmat(10, seed=21, weights=(1, 255), weight_seed=22)
+    s_sp = fi.sources_uniform(g, 70, 1)
+    s_bfs = fi.sources_uniform(g, 10, 2)
+    s_pr = fi.sources_uniform(g, 20, 3)
+    fg = fs.SimtGraph(lib, g, partition_vertices=128)
+    fg.submit("sssp", s_sp)
+    fg.submit("bfs", s_bfs)
+    fg.submit("ppr", s_pr, epsilon=1e-6, eps_mode=0)
+    fg.run(max_passes=100000, engine="grouped")
+    np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(70)]), oracle.sssp(g, s_sp))
+    np.testing.assert_array_equal(np.stack([fg.fetch(70 + i) for i in range(10)]), oracle.bfs(g, s_bfs))
+    for i, s in enumerate(s_pr):
+        p = fg.fetch(80 + i, 1).astype(np.float64)
+        r = fg.fetch(80 + i, 2)
+        assert np.all(p >= 0) and np.all(r >= 0)
+        assert oracle.push_terminal(g, r, 1e-6, 0, dtype=np.float32)
+        assert oracle.ppr_invariant_l1(g, s, p, r.astype(np.float64), 0.15) <= 1e-4
+    fg.close()
+
