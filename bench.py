@@ -46,18 +46,18 @@ def algorithmic_bytes(st: dict) -> float:
             + st["selected_edges"] * (4 + st["weight_bytes"]) + st["ops_emitted"] * 24)
 
 
-def measured_traffic(workload: str, root: str = ""):
-    """HBM bytes per launch of k_process from the committed rocprofv3 summary of
-    this workload, if that summary was taken from the current kernel source."""
+def measured_traffic(workload: str, kernel: str = "k_process", root: str = ""):
+    """HBM bytes per launch of the pass kernel from the committed rocprofv3 summary
+    of this workload, if that summary was taken from the current kernel source."""
     from paper_2103_14915_amd import profile_summary as ps
     root = root or os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(root, "profiles", f"k_process_{workload}.md")
+    path = os.path.join(root, "profiles", f"{kernel}_{workload}.md")
     try:
         text = open(path).read()
         blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
-    if blob.get("source_hash") != ps.kernel_source_hash() or "traffic_bytes_per_launch" not in blob:
+    if blob.get("source_hash") != ps.kernel_source_hash(kernel) or "traffic_bytes_per_launch" not in blob:
         return None
     return blob
 
@@ -175,8 +175,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat20_sssp_ppr2048")
     ap.add_argument("--scheduler", default="priority")
-    ap.add_argument("--engine", default="buffered", choices=["buffered", "grouped"],
-                    help="buffered: one work item per (partition, query); grouped: per (partition, 64 queries)")
+    ap.add_argument("--engine", default="", choices=["", "buffered", "grouped"],
+                    help="buffered: one work item per (partition, query); grouped: per (partition, 64 queries); "
+                         "default: the tuned choice")
     ap.add_argument("--parts-per-pass", type=int, default=0)
     ap.add_argument("--partition-vertices", type=int, default=0)
     ap.add_argument("--delta", type=int, default=0)
@@ -205,6 +206,7 @@ def main():
                     "on the same workload and report the speedup over the rule-based one ('auto': the weights "
                     "shipped with the package for this graph family; 'none': skip)")
     ap.add_argument("--learned-steps", type=int, default=5, help="timed steps of the learned scheduler")
+    ap.add_argument("--group-threads", type=int, default=0, help="grouped engine: workgroup size (256/512/1024)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -262,6 +264,15 @@ def main():
             params[k] = v
     if args.slice_slots >= 0:
         params["slice_slots"] = args.slice_slots
+    if args.engine:
+        params["engine"] = args.engine
+    if args.mu:
+        params["mu"] = args.mu
+    if args.group_threads:
+        params["group_threads"] = args.group_threads
+    params = dict(autotune.DEFAULTS, **params)
+    if params["engine"] == "grouped":
+        params["persistent"] = 0
     from paper_2103_14915_amd import order as vorder
     t0 = time.perf_counter()
     if args.order == "auto":
@@ -286,11 +297,8 @@ def main():
         nq += len(s)
     kinds = sorted({qt for qt, _ in queries})
     kind = kinds[0] if len(kinds) == 1 else "mixed"
-    run_kw = dict(scheduler=args.scheduler, parts_per_pass=args.parts_per_pass, delta=params["delta"],
-                  edge_budget_mu=args.mu, stream=stream, profile=1,
-                  persistent=params["persistent"] if args.engine == "buffered" else 0,
-                  items_per_pass=params["items_per_pass"], window_mode=args.window_mode, window=params["window"],
-                  slice_slots=params.get("slice_slots", 0), engine=args.engine)
+    run_kw = dict(autotune.run_kwargs(params), scheduler=args.scheduler, parts_per_pass=args.parts_per_pass,
+                  stream=stream, profile=1, window_mode=args.window_mode)
     for _ in range(args.warmup):
         fg.run(**run_kw)
     torch.cuda.synchronize()
@@ -307,7 +315,8 @@ def main():
         tot[k] = st[k]
     value = nq * args.steps / dt
     abytes = algorithmic_bytes(tot)
-    prof = measured_traffic(args.workload) if not (args.scale or args.queries or args.l1_target) else None
+    kernel = "k_gprocess" if params["engine"] == "grouped" else "k_process"
+    prof = measured_traffic(args.workload, kernel) if not (args.scale or args.queries or args.l1_target) else None
     launches = max(1, tot["process_launches"])
     avg_ms = tot["process_ms"] / launches
     achieved = (abytes / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -327,7 +336,7 @@ def main():
         "config": {"workload": args.workload + (f"@scale{args.scale}" if args.scale else "")
                    + (f"@q{args.queries}" if args.queries else "")
                    + (f"+l1cert{args.l1_target:g}" if args.l1_target > 0 else ""), "queries": nq, "types": kinds, "vertices": g.num_vertices,
-                   "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler, "engine": args.engine, "knobs": params, "knobs_source": source,
+                   "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler, "engine": params["engine"], "knobs": params, "knobs_source": source,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -339,7 +348,7 @@ def main():
                      "l2_hit_rate": prof.get("l2_hit_rate") if prof else None,
                      "wave_wait_share": prof.get("wave_wait_share") if prof else None,
                      "achievable_copy_gbs": prof.get("copy_gbs") if prof else None,
-                     "kernel": "k_process",
+                     "kernel": kernel,
                      "avg_launch_ms": avg_ms, "launches_per_step": launches / args.steps,
                      "algorithmic_bytes_per_launch": abytes / launches,
                      "algorithmic_bytes_per_step": abytes / args.steps},
@@ -354,6 +363,7 @@ def main():
                    "work_items_per_step": tot["work_items"] / args.steps,
                    "refine_rounds_per_step": tot["refine_rounds"] / args.steps,
                    "activations_per_step": tot["activations"] / args.steps,
+                   "expansions_per_step": tot["expansions"] / args.steps,
                    "spilled_per_step": tot["spilled"] / args.steps, "spill_max": st["spill_max"]},
     }
     if args.compare_learned == "auto":

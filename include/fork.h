@@ -146,6 +146,9 @@ typedef struct {
                                   for the dense slice always use a hashed one
                                   (4096 slots when 0 is given)                    */
     int      engine;           /* FORK_ENGINE_BUFFERED (0) or FORK_ENGINE_GROUPED (1) */
+    uint32_t group_threads;    /* grouped engine: threads of the workgroup that
+                                  visits one (partition, group) pair: 256, 512
+                                  or 1024 (0 = 256)                              */
 } fork_run_opts;
 
 /* Counters accumulated over the last fork_run (all waves). */
@@ -180,6 +183,8 @@ typedef struct {
                                   was full                                  */
     uint64_t activations;      /* grouped engine: (vertex, group) pairs marked
                                   pending in another partition              */
+    uint64_t expansions;       /* grouped engine: vertex expansions, each for
+                                  one or more of its group's queries        */
     uint64_t spill_max;        /* most vertices one visit retained as
                                   operations (a visit retaining more than
                                   16,384 stops the run: FORK_E_CAPACITY)    */

@@ -57,7 +57,7 @@ class fork_run_opts(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("mlp_weights", ctypes.c_void_p), ("persistent", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("profile", ctypes.c_int), ("items_per_pass", ctypes.c_uint32),
                 ("trace", ctypes.c_int), ("window_mode", ctypes.c_int), ("window", ctypes.c_uint32),
-                ("slice_slots", ctypes.c_uint32), ("engine", ctypes.c_int)]
+                ("slice_slots", ctypes.c_uint32), ("engine", ctypes.c_int), ("group_threads", ctypes.c_uint32)]
 
 
 class fork_stats_t(ctypes.Structure):
@@ -69,7 +69,7 @@ class fork_stats_t(ctypes.Structure):
                 ("weight_bytes", ctypes.c_uint32), ("refine_rounds", ctypes.c_uint64),
                 ("selected_edges", ctypes.c_uint64), ("ppr_edges", ctypes.c_uint64),
                 ("ppr_vertex_pushes", ctypes.c_uint64), ("spilled", ctypes.c_uint64),
-                ("activations", ctypes.c_uint64), ("spill_max", ctypes.c_uint64)]
+                ("activations", ctypes.c_uint64), ("expansions", ctypes.c_uint64), ("spill_max", ctypes.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -211,7 +211,7 @@ class ForkGraph:
 
     def run(self, scheduler="priority", parts_per_pass=0, delta=0, edge_budget_mu=0.0, max_passes=0,
             stream=None, mlp_weights=None, persistent=0, seed=0, profile=0, items_per_pass=0, trace=0,
-            window_mode=0, window=0, slice_slots=0, engine="buffered"):
+            window_mode=0, window=0, slice_slots=0, engine="buffered", group_threads=0):
         s = SCHEDS[scheduler] if isinstance(scheduler, str) else int(scheduler)
         eng = ENGINES[engine] if isinstance(engine, str) else int(engine)
         w = None
@@ -224,7 +224,7 @@ class ForkGraph:
             sp = stream if isinstance(stream, int) else stream.cuda_stream
         o = fork_run_opts(s, parts_per_pass, delta, edge_budget_mu, max_passes, sp,
                           None if w is None else w.ctypes.data, persistent, seed, profile, items_per_pass, trace,
-                          window_mode, window, slice_slots, eng)
+                          window_mode, window, slice_slots, eng, group_threads)
         _check(lib.fork_run(self._ctx, ctypes.byref(o)))
 
     def fetch(self, qid, field=None, out=None):

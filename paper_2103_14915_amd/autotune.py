@@ -2,11 +2,13 @@
 
 Picks the knobs that the paper fixes by hand (Section 6.1: partition size =
 LLC size; yield thresholds; one partition processed at a time) for the
-MI355X: partition size (vertices per LDS-staged slice), work items queued per
-pass (how many (partition, query) visits run between two scheduling steps),
-the SSSP batch window and the heuristic-2 range Delta, whether the pass
-loop runs in one persistent kernel, and the LDS slice shape (dense, or a hash
-table of touched vertices that lets more workgroups share a CU).  It times short runs on a seeded sample
+MI355X: the engine (one query per work item, or 64 queries per work item in
+vertex-major rows), partition size (vertices per LDS-staged slice), work
+items queued per pass (how many visits run between two scheduling steps),
+the SSSP batch window, the heuristic-2 range Delta and the heuristic-1 edge
+budget mu, whether the pass loop runs in one persistent kernel, and the LDS
+slice shape (dense, or a hash table of touched vertices that lets more
+workgroups share a CU).  It times short runs on a seeded sample
 of the workload's queries and does coordinate descent from the defaults.
 Results are cached in JSON keyed by graph shape, query mix and device.
 
@@ -28,8 +30,23 @@ from . import ForkGraph
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.environ.get("FORK_TUNE_CACHE", os.path.join(HERE, "tune_cache.json"))
 
-DEFAULTS = {"partition_vertices": 16384, "items_per_pass": 0, "window": 0, "delta": 0, "persistent": 0,
-            "slice_slots": 0}
+DEFAULTS = {"engine": "buffered", "partition_vertices": 16384, "items_per_pass": 0, "window": 0, "delta": 0,
+            "mu": 0.0, "persistent": 0, "slice_slots": 0, "group_threads": 0}
+GROUPED_PVMAX = 16384  # largest partition the grouped engine visits
+
+
+def valid(p) -> bool:
+    """Knob combinations the library accepts."""
+    if p.get("engine") == "grouped":
+        return p["partition_vertices"] <= GROUPED_PVMAX and not p["persistent"]
+    return not p.get("group_threads")  # the workgroup size is a grouped-engine knob
+
+
+def run_kwargs(p) -> dict:
+    """fork_run keyword arguments of a knob set."""
+    return dict(engine=p.get("engine", "buffered"), items_per_pass=p["items_per_pass"], window=p["window"],
+                delta=p["delta"], edge_budget_mu=float(p.get("mu", 0.0)), persistent=p["persistent"],
+                slice_slots=p.get("slice_slots", 0), group_threads=int(p.get("group_threads", 0)))
 
 
 def device_name() -> str:
@@ -88,8 +105,7 @@ def _trial(g, sample, spec, p, stream=None) -> float:
             fg.submit(qt, s, alpha=spec.get("alpha", 0.15), epsilon=spec.get("epsilon", 1e-6),
                       eps_mode=spec.get("eps_mode", 0))
             n += len(s)
-        kw = dict(items_per_pass=p["items_per_pass"], window=p["window"], delta=p["delta"],
-                  persistent=p["persistent"], slice_slots=p.get("slice_slots", 0), stream=stream)
+        kw = dict(run_kwargs(p), stream=stream)
         fg.run(**kw)
         t0 = time.perf_counter()
         fg.run(**kw)
@@ -102,14 +118,17 @@ def candidates(g, queries) -> dict:
     kinds = {qt for qt, _ in queries}
     wmean = float(g.weight.mean()) if g.weight is not None else 1.0
     c = {
-        "partition_vertices": [8192, 16384, 32768, 65536],
+        "engine": ["buffered", "grouped"],
+        "partition_vertices": [2048, 4096, 8192, 16384, 32768, 65536],
         "items_per_pass": [0, 2048, 16384, 65536],
         "persistent": [0, 1],
         "slice_slots": [0, 1024, 2048, 2560, 4096],
+        "mu": [0.0, 1.0, 2.0, 4.0],
+        "group_threads": [0, 512, 1024],
     }
     if kinds & {"sssp", "bfs"}:
         w = max(1, int(round(wmean)))
-        c["window"] = [0, max(1, w // 8), max(1, w // 2), 2 * w, 8 * w, 32 * w]
+        c["window"] = [0, max(1, w // 8), max(1, w // 2), 2 * w, 8 * w, 32 * w, 128 * w]
         c["delta"] = [0, 4 * w, 16 * w, 64 * w, 256 * w]
     return c
 
@@ -132,6 +151,8 @@ def tune(g, queries, spec, sample=256, rounds=1, budget_s=240.0, log=print, use_
                 if v == best[name] or time.time() - t_start > budget_s:
                     continue
                 p = dict(best, **{name: v})
+                if not valid(p):
+                    continue
                 try:
                     q = _trial(g, smp, spec, p)
                 except Exception as e:  # noqa: BLE001 - a configuration that fails is just not chosen

@@ -60,6 +60,7 @@ struct Ctl {
     unsigned long long c_spill;     // activated vertices retained as operations (frontier full)
     unsigned long long c_act;       // grouped engine: (vertex, group) activations in other partitions
     unsigned int c_spill_max;       // most vertices one visit retained because its frontier was full
+    unsigned long long c_vtask;     // grouped engine: vertex expansions (each for one or more lanes)
 };
 
 // A (partition, query) work item of one pass.

@@ -25,14 +25,14 @@
 namespace fk {
 
 constexpr int GW = 64;        // queries per group (one per lane)
-constexpr int GNT = 256;      // threads per workgroup
-constexpr int GNW = GNT / WAVE;
+constexpr int GNTMAX = 1024;  // threads per workgroup: 256, 512 or 1024 (chosen at launch)
+constexpr int GNWMAX = GNTMAX / WAVE;
 constexpr int RCAP = 1024;    // vertices per round
 constexpr uint32_t GPVMAX = 16384;  // largest partition the grouped engine visits
 constexpr int LBW = GPVMAX / 32;     // local pending bitmap words
 constexpr int UNR = 8;        // edges in flight per wave step (and marking lanes)
 constexpr int PCAP = 32;      // PPR vertices per round (their shares are kept in LDS)
-static_assert(UNR <= WAVE && RCAP % GNT == 0, "task layout");
+static_assert(UNR <= WAVE && RCAP % GNTMAX == 0, "task layout");
 
 // Per-lane pushed shares of a PPR round's vertices.
 struct GCtxShare {
@@ -46,7 +46,7 @@ struct GShared {
     uint32_t rnt[RCAP];               // round: edge tasks of the vertex, then its first task
     uint32_t nr, next;
     uint32_t lmin[GW];                // per lane: least pending value of the round (SSSP/BFS)
-    uint32_t wred[GNW];
+    uint32_t wred[GNWMAX];
     unsigned long long edges;         // lane-edges of the visit so far
     unsigned long long itpos;
     Item it;
@@ -70,7 +70,7 @@ struct GCtx {
     uint32_t mode;
     uint32_t win;          // heuristic-2 bound: lanes with value > win wait (INF: none)
     uint32_t bwin;         // batch width inside a visit: a lane expands values in [lmin, lmin + bwin)
-    unsigned long long c_edges, c_intra, c_improved, c_vpush, c_act, c_edges_ppr, c_vpush_ppr;
+    unsigned long long c_edges, c_intra, c_improved, c_vpush, c_act, c_edges_ppr, c_vpush_ppr, c_vtask;
 };
 
 // Mark lanes `bits` of vertex u (global id) pending in the group.  Called by
@@ -118,7 +118,7 @@ __device__ uint32_t gtake_round(GCtx& c, GShared& S, uint32_t cap) {
     if (t == 0) { S.nr = 0; S.next = 0; }
     __syncthreads();
     const uint32_t nw = (c.nvp + 31) / 32;
-    for (uint32_t w0 = 0; w0 < nw; w0 += GNT) {
+    for (uint32_t w0 = 0; w0 < nw; w0 += blockDim.x) {
         const uint32_t w = w0 + t;
         uint32_t word = w < nw ? S.lbits[w] : 0u;
         // how many of this word's vertices fit in the round
@@ -158,7 +158,7 @@ __device__ void ground_min(GCtx& c, GShared& S, uint32_t nr) {
     if (t < (uint32_t)GW) S.lmin[t] = INF;
     __syncthreads();
     uint32_t m = INF;
-    for (uint32_t k = wv; k < nr; k += GNW) {
+    for (uint32_t k = wv; k < nr; k += blockDim.x / WAVE) {
         if (!((S.rm[k] >> lane) & 1ull)) continue;
         const uint32_t d = fresh_load(&c.st[(unsigned long long)(c.v0 + S.rv[k]) * GW + lane]);
         m = d < m ? d : m;
@@ -174,8 +174,8 @@ __device__ __forceinline__ uint32_t gblock_excl(GShared& S, uint32_t v, uint32_t
     if (lane == 63) S.wred[wid] = incl;
     __syncthreads();
     uint32_t before = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < GNW; ++w) {
+    const int nwv = (int)(blockDim.x / WAVE);
+    for (int w = 0; w < nwv; ++w) {
         const uint32_t x = S.wred[w];
         before += (w < (int)wid) ? x : 0u;
         tot += x;
@@ -189,22 +189,23 @@ __device__ __forceinline__ uint32_t gblock_excl(GShared& S, uint32_t v, uint32_t
 // of up to 64 out-edges (S.rnt[k] holds the count on entry, its first task
 // index on return).  Returns the task total.
 __device__ uint32_t gnumber_tasks(GShared& S, uint32_t nr) {
-    constexpr uint32_t PER = RCAP / GNT;
+    constexpr uint32_t PERMAX = RCAP / 256;  // entries per thread with the smallest workgroup
+    const uint32_t per = RCAP / blockDim.x;
     const uint32_t t = threadIdx.x;
-    uint32_t x[PER];
+    uint32_t x[PERMAX];
     uint32_t sum = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < PER; ++k) {
-        const uint32_t i = t * PER + k;
-        x[k] = i < nr ? S.rnt[i] : 0u;
+    for (uint32_t k = 0; k < PERMAX; ++k) {
+        const uint32_t i = t * per + k;
+        x[k] = (k < per && i < nr) ? S.rnt[i] : 0u;
         sum += x[k];
     }
     uint32_t total = 0;
     uint32_t run = gblock_excl(S, sum, &total);
 #pragma unroll
-    for (uint32_t k = 0; k < PER; ++k) {
-        const uint32_t i = t * PER + k;
-        if (i < nr) S.rnt[i] = run;
+    for (uint32_t k = 0; k < PERMAX; ++k) {
+        const uint32_t i = t * per + k;
+        if (k < per && i < nr) S.rnt[i] = run;
         run += x[k];
     }
     __syncthreads();
@@ -229,7 +230,7 @@ __device__ void gfilter_sp(GCtx& c, GShared& S, uint32_t nr) {
     const uint32_t lo = S.lmin[lane];
     const unsigned long long hi_ = (unsigned long long)lo + c.bwin;
     const uint32_t hi = hi_ >= INF ? INF : (uint32_t)hi_;
-    for (uint32_t k = wv; k < nr; k += GNW) {
+    for (uint32_t k = wv; k < nr; k += blockDim.x / WAVE) {
         const uint32_t vloc = S.rv[k];
         const unsigned long long m = S.rm[k];
         const uint32_t v = c.v0 + vloc;
@@ -258,6 +259,7 @@ __device__ void gfilter_sp(GCtx& c, GShared& S, uint32_t nr) {
             const uint32_t deg = c.g.rowptr[v + 1] - c.g.rowptr[v];
             S.rm[k] = am;
             S.rnt[k] = am ? (deg + GW - 1) / GW : 0u;
+            c.c_vtask += am ? 1u : 0u;
         }
     }
     __syncthreads();
@@ -268,7 +270,7 @@ __device__ void gfilter_sp(GCtx& c, GShared& S, uint32_t nr) {
 // the share each out-edge receives (Section 4.1's push).
 __device__ void gfilter_ppr(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr) {
     const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE;
-    for (uint32_t k = wv; k < nr; k += GNW) {
+    for (uint32_t k = wv; k < nr; k += blockDim.x / WAVE) {
         const uint32_t vloc = S.rv[k];
         const unsigned long long m = S.rm[k];
         const uint32_t v = c.v0 + vloc;
@@ -301,6 +303,7 @@ __device__ void gfilter_ppr(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr) {
         if (lane == 0) {
             S.rm[k] = deg ? pm : 0ull;
             S.rnt[k] = (pm && deg) ? (deg + GW - 1) / GW : 0u;
+            c.c_vtask += pm ? 1u : 0u;
         }
     }
     __syncthreads();
@@ -432,7 +435,7 @@ __device__ void gvisit(GCtx& c, GShared& S, GCtxShare& SH, const PassCfg& cfg) {
     }
     // the pair's pending vertices: global bitmap -> LDS
     const uint32_t nw = (c.nvp + 31) / 32;
-    for (uint32_t w = t; w < nw; w += GNT) {
+    for (uint32_t w = t; w < nw; w += blockDim.x) {
         const uint32_t u0 = c.v0 + w * 32;  // first vertex of local word w
         // the partition starts on a multiple of 2^pshift, which may not be a
         // multiple of 32: gather the 32 bits from up to two global words
@@ -477,7 +480,7 @@ __device__ void gvisit(GCtx& c, GShared& S, GCtxShare& SH, const PassCfg& cfg) {
     }
     __syncthreads();
     // yield: what is still pending in the partition stays in the pair's buffer
-    for (uint32_t w = t; w < nw; w += GNT) {
+    for (uint32_t w = t; w < nw; w += blockDim.x) {
         uint32_t word = S.lbits[w];
         while (word) {
             const uint32_t b = __ffs(word) - 1;
@@ -504,14 +507,14 @@ __device__ void gvisit(GCtx& c, GShared& S, GCtxShare& SH, const PassCfg& cfg) {
 }
 
 template <int WB>
-__global__ __launch_bounds__(GNT) void k_gprocess(GraphDev g, GroupDev G, BufDev B, PassCfg cfg) {
+__global__ __launch_bounds__(GNTMAX) void k_gprocess(GraphDev g, GroupDev G, BufDev B, PassCfg cfg) {
     __shared__ GShared S;
     __shared__ GCtxShare SH;
     GCtx c;
     c.g = g;
     c.G = G;
     c.B = B;
-    c.c_edges = c.c_intra = c.c_improved = c.c_vpush = c.c_act = c.c_edges_ppr = c.c_vpush_ppr = 0;
+    c.c_edges = c.c_intra = c.c_improved = c.c_vpush = c.c_act = c.c_edges_ppr = c.c_vpush_ppr = c.c_vtask = 0;
     const uint32_t t = threadIdx.x;
     const uint32_t xcd = blockIdx.x % NXCD;
     c.pass = B.ctl->pass;
@@ -542,10 +545,11 @@ __global__ __launch_bounds__(GNT) void k_gprocess(GraphDev g, GroupDev G, BufDev
         gvisit<WB>(c, S, SH, cfg);
     }
     // counters
-    constexpr int NC = 7;
-    unsigned long long v[NC] = {c.c_edges, c.c_intra, c.c_improved, c.c_vpush, c.c_act, c.c_edges_ppr, c.c_vpush_ppr};
+    constexpr int NC = 8;
+    unsigned long long v[NC] = {c.c_edges, c.c_intra, c.c_improved, c.c_vpush, c.c_act, c.c_edges_ppr, c.c_vpush_ppr,
+                                c.c_vtask};
     unsigned long long* dst[NC] = {&B.ctl->c_edges, &B.ctl->c_intra, &B.ctl->c_improved, &B.ctl->c_vpush,
-                                   &B.ctl->c_act, &B.ctl->c_edges_ppr, &B.ctl->c_vpush_ppr};
+                                   &B.ctl->c_act, &B.ctl->c_edges_ppr, &B.ctl->c_vpush_ppr, &B.ctl->c_vtask};
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         unsigned long long x = v[k];
@@ -701,12 +705,13 @@ __global__ __launch_bounds__(256) void k_gout(GroupDev G, uint32_t nv, uint32_t*
 
 // ------------------------------------------------------------ launchers
 hipError_t launch_gprocess(const GraphDev& g, const GroupDev& G, const BufDev& B, const PassCfg& cfg, uint32_t blocks,
-                           hipStream_t s) {
+                           uint32_t nth, hipStream_t s) {
+    if (nth != 256 && nth != 512 && nth != 1024) return hipErrorInvalidValue;
     switch (g.wbytes) {
-    case 0: hipLaunchKernelGGL((k_gprocess<0>), dim3(blocks), dim3(GNT), 0, s, g, G, B, cfg); break;
-    case 1: hipLaunchKernelGGL((k_gprocess<1>), dim3(blocks), dim3(GNT), 0, s, g, G, B, cfg); break;
-    case 2: hipLaunchKernelGGL((k_gprocess<2>), dim3(blocks), dim3(GNT), 0, s, g, G, B, cfg); break;
-    default: hipLaunchKernelGGL((k_gprocess<4>), dim3(blocks), dim3(GNT), 0, s, g, G, B, cfg); break;
+    case 0: hipLaunchKernelGGL((k_gprocess<0>), dim3(blocks), dim3(nth), 0, s, g, G, B, cfg); break;
+    case 1: hipLaunchKernelGGL((k_gprocess<1>), dim3(blocks), dim3(nth), 0, s, g, G, B, cfg); break;
+    case 2: hipLaunchKernelGGL((k_gprocess<2>), dim3(blocks), dim3(nth), 0, s, g, G, B, cfg); break;
+    default: hipLaunchKernelGGL((k_gprocess<4>), dim3(blocks), dim3(nth), 0, s, g, G, B, cfg); break;
     }
     return hipGetLastError();
 }
@@ -737,7 +742,7 @@ hipError_t launch_gout(const GroupDev& G, uint32_t nv, uint32_t* out, const unsi
     hipLaunchKernelGGL(k_gout, dim3((nv + GW - 1) / GW, G.ng), dim3(256), 0, s, G, nv, out, qoff, lq);
     return hipGetLastError();
 }
-int gprocess_threads() { return GNT; }
+int gprocess_threads() { return GNTMAX; }
 size_t group_dev_bytes() { return sizeof(GroupDev); }
 
 }  // namespace fk

@@ -52,7 +52,8 @@ const void* process_kernel_ptr(int wbytes);
 const void* persistent_kernel_ptr(int wbytes);
 hipError_t launch_persistent(const GraphDev&, const QueryDev&, const BufDev&, const PassCfg&, uint32_t, uint32_t,
                              uint32_t, uint32_t, const float*, float*, void*, hipStream_t);
-hipError_t launch_gprocess(const GraphDev&, const GroupDev&, const BufDev&, const PassCfg&, uint32_t, hipStream_t);
+hipError_t launch_gprocess(const GraphDev&, const GroupDev&, const BufDev&, const PassCfg&, uint32_t, uint32_t,
+                           hipStream_t);
 const void* gprocess_kernel_ptr(int wbytes);
 int gprocess_threads();
 hipError_t launch_gsummaries(const GraphDev&, const GroupDev&, const BufDev&, const PassCfg&, hipStream_t);
@@ -979,10 +980,14 @@ static int run_wave_group(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_
             return rc;
         c->grp_cap = ng;
     }
-    if (c->group_blocks_per_cu <= 0) {
+    // workgroup size of the grouped pass (waves that share one pair's visit)
+    const uint32_t gnt = o.group_threads ? o.group_threads : 256u;
+    if (gnt != 256 && gnt != 512 && gnt != 1024)
+        return fail(FORK_E_INVALID, "group_threads must be 0, 256, 512 or 1024, got %u", gnt);
+    {
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fk::gprocess_kernel_ptr(c->wbytes),
-                                                         fk::gprocess_threads(), 0) != hipSuccess || occ <= 0)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fk::gprocess_kernel_ptr(c->wbytes), (int)gnt, 0) !=
+                hipSuccess || occ <= 0)
             return fail(FORK_E_DEVICE, "grouped pass kernel does not fit on a CU");
         c->group_blocks_per_cu = occ;
     }
@@ -1036,7 +1041,9 @@ static int run_wave_group(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_
     HIPCHK(hipMemcpyAsync(c->d_ctl, c->h_ctl, sizeof(fk::Ctl), hipMemcpyHostToDevice, s));
     HIPCHK(fk::launch_gseed(g, G, c->d_lsrc, s));
     HIPCHK(hipEventRecord(c->ev[1], s));
-    const uint32_t blocks = (uint32_t)std::max(1, c->num_cu * c->group_blocks_per_cu);
+    // twice what fits at once: a workgroup that runs out of items exits, and
+    // the next one takes its place on the CU
+    const uint32_t blocks = (uint32_t)std::max(1, 2 * c->num_cu * c->group_blocks_per_cu);
     uint32_t batch = 1;
     while (true) {
         uint32_t nb = batch;
@@ -1054,7 +1061,7 @@ static int run_wave_group(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_
             HIPCHK(fk::launch_select(g, B, pc, s));
             HIPCHK(fk::launch_gworklist(B, G, pc, s));
             if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k], s));
-            HIPCHK(fk::launch_gprocess(g, G, B, pc, blocks, s));
+            HIPCHK(fk::launch_gprocess(g, G, B, pc, blocks, gnt, s));
             if (o.profile) HIPCHK(hipEventRecord(c->pev[2 * k + 1], s));
         }
         if (passes_left != ~0ull) passes_left -= nb;
@@ -1095,6 +1102,7 @@ static int run_wave_group(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_
     st.ppr_edges += h.c_edges_ppr;
     st.ppr_vertex_pushes += h.c_vpush_ppr;
     st.activations += h.c_act;
+    st.expansions += h.c_vtask;
     st.waves += 1;
     c->res_first = q0;
     c->res_n = nq;

@@ -24,14 +24,17 @@ import os
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fork_pass.hip", "fork_util.h", "fork_dev.h",
-                                                          "fork_sched.h", "fork_mlp.h")]
+# the sources each pass kernel is built from
+KERNEL_SOURCES = {
+    "k_process": ("fork_pass.hip", "fork_util.h", "fork_dev.h", "fork_sched.h", "fork_mlp.h"),
+    "k_gprocess": ("fork_group.hip", "fork_util.h", "fork_dev.h", "fork_sched.h"),
+}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kernel: str = "k_process") -> str:
     h = hashlib.sha1()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -77,7 +80,7 @@ def main(argv=None):
     for r in rows[:12]:
         lines.append(f"| {r['Name'][:70]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
-    out = {"kernel": a.kernel, "source_hash": kernel_source_hash()}
+    out = {"kernel": a.kernel, "source_hash": kernel_source_hash(a.kernel)}
     kname, kstat = next(((r["Name"], r) for r in rows if a.kernel in r["Name"]), (None, None))
     if kstat:
         out["avg_launch_ms"] = float(kstat["AverageNs"]) / 1e6
