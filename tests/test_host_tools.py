@@ -120,11 +120,17 @@ def test_bench_traffic_lookup_requires_matching_source(tmp_path):
     prof.mkdir()
     blob = {"kernel": "k_process", "source_hash": ps.kernel_source_hash(), "traffic_bytes_per_launch": 123.0}
     (prof / "k_process_w.md").write_text("x\n```json\n" + json.dumps(blob) + "\n```\n")
-    assert bench.measured_traffic("w", str(tmp_path))["traffic_bytes_per_launch"] == 123.0
+    assert bench.measured_traffic("w", "k_process", str(tmp_path))["traffic_bytes_per_launch"] == 123.0
+    # the grouped engine's kernel has its own summary and source hash
+    assert bench.measured_traffic("w", "k_gprocess", str(tmp_path)) is None
+    gblob = dict(blob, kernel="k_gprocess", source_hash=ps.kernel_source_hash("k_gprocess"))
+    (prof / "k_gprocess_w.md").write_text("x\n```json\n" + json.dumps(gblob) + "\n```\n")
+    assert bench.measured_traffic("w", "k_gprocess", str(tmp_path))["traffic_bytes_per_launch"] == 123.0
+    assert ps.kernel_source_hash("k_gprocess") != ps.kernel_source_hash("k_process")
     blob["source_hash"] = "0" * 16
     (prof / "k_process_w.md").write_text("x\n```json\n" + json.dumps(blob) + "\n```\n")
-    assert bench.measured_traffic("w", str(tmp_path)) is None  # profile of another kernel version
-    assert bench.measured_traffic("missing", str(tmp_path)) is None
+    assert bench.measured_traffic("w", "k_process", str(tmp_path)) is None  # profile of another kernel version
+    assert bench.measured_traffic("missing", "k_process", str(tmp_path)) is None
 
 
 def test_bench_refuses_more_than_one_gpu():
