@@ -187,7 +187,7 @@ typedef struct {
                                   one or more of its group's queries        */
     uint64_t spill_max;        /* most vertices one visit retained as
                                   operations (a visit retaining more than
-                                  16,384 stops the run: FORK_E_CAPACITY)    */
+                                  32,768 stops the run: FORK_E_CAPACITY)    */
 } fork_stats_t;
 
 /* Per-query digest (fork_fetch field FORK_FIELD_DIGEST).  For SSSP/BFS:

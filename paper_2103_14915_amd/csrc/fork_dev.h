@@ -36,8 +36,11 @@ enum : uint32_t { ERR_CAPACITY = 1u, ERR_ITEMS = 2u, ERR_CORRUPT = 4u, ERR_SPILL
 // stops with FORK_E_CAPACITY: that regime (a visit re-activating most of a
 // large partition, its overflow re-emitted pass after pass) is the one in
 // which a GPU run once failed its consistency check for a reason not found,
-// so it is refused rather than run.
-constexpr uint32_t SPILL_MAX = 16384;
+// so it is refused rather than run.  (Vertices kept outside a hashed slice
+// re-enter the frontier once per operation, so a visit of a 4,096-vertex
+// partition with a 256-slot table can retain about 18,000; the refinement
+// that failed retained about 60,000.)
+constexpr uint32_t SPILL_MAX = 32768;
 
 // One device control block per context.  Counters are 64-bit.
 struct Ctl {

@@ -185,10 +185,10 @@ __device__ __forceinline__ uint32_t gblock_excl(GShared& S, uint32_t v, uint32_t
     return before + incl - v;
 }
 
-// Number the round's edge tasks: vertex k contributes ceil(deg_k / 64) tasks
-// of up to 64 out-edges (S.rnt[k] holds the count on entry, its first task
-// index on return).  Returns the task total.
-__device__ uint32_t gnumber_tasks(GShared& S, uint32_t nr) {
+// Number the round's out-edges: S.rnt[k] holds vertex k's expanding out-edge
+// count on entry and the index of its first edge in the round's flat edge
+// list on return.  Returns the round's edge total.
+__device__ uint32_t gnumber_edges(GShared& S, uint32_t nr) {
     constexpr uint32_t PERMAX = RCAP / 256;  // entries per thread with the smallest workgroup
     const uint32_t per = RCAP / blockDim.x;
     const uint32_t t = threadIdx.x;
@@ -212,11 +212,12 @@ __device__ uint32_t gnumber_tasks(GShared& S, uint32_t nr) {
     return total;
 }
 
-__device__ __forceinline__ uint32_t gtask_vertex(const GShared& S, uint32_t nr, uint32_t task) {
-    uint32_t lo = 0, hi = nr;  // last k with rnt[k] <= task
+// Round vertex of flat edge f: the last k with rnt[k] <= f.
+__device__ __forceinline__ uint32_t gedge_vertex(const GShared& S, uint32_t nr, uint32_t f) {
+    uint32_t lo = 0, hi = nr;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (S.rnt[mid] <= task) lo = mid; else hi = mid;
+        if (S.rnt[mid] <= f) lo = mid; else hi = mid;
     }
     return lo;
 }
@@ -258,7 +259,7 @@ __device__ void gfilter_sp(GCtx& c, GShared& S, uint32_t nr) {
         if (lane == 0) {
             const uint32_t deg = c.g.rowptr[v + 1] - c.g.rowptr[v];
             S.rm[k] = am;
-            S.rnt[k] = am ? (deg + GW - 1) / GW : 0u;
+            S.rnt[k] = am ? deg : 0u;
             c.c_vtask += am ? 1u : 0u;
         }
     }
@@ -302,7 +303,7 @@ __device__ void gfilter_ppr(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr) {
         SH.share[k][lane] = share;
         if (lane == 0) {
             S.rm[k] = deg ? pm : 0ull;
-            S.rnt[k] = (pm && deg) ? (deg + GW - 1) / GW : 0u;
+            S.rnt[k] = pm ? deg : 0u;
             c.c_vtask += pm ? 1u : 0u;
         }
     }
@@ -310,47 +311,64 @@ __device__ void gfilter_ppr(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr) {
 }
 
 // Third step of a round: the edge tasks, shared by the block's waves.  A task
-// is up to 64 consecutive out-edges of one vertex: one vector load fetches
-// their targets (and weights), then UNR edges at a time are relaxed (SSSP/BFS:
-// atomic min of the row entry) or pushed to (PPR: atomic add of the share)
-// by every active lane, and the lanes 0..UNR-1 mark the newly pending targets
-// in parallel.
+// is 64 consecutive edges of the round's flat edge list (the expanding
+// vertices' out-edges one after another, so low-degree vertices share a
+// task): lane j finds edge j's source vertex and loads its target (and
+// weight).  Then UNR edges at a time, every query lane that expands the
+// edge's source relaxes (SSSP/BFS: atomic min of the target row's entry) or
+// pushes to (PPR: atomic add of its share) the target, and the lanes
+// 0..UNR-1 mark the newly pending targets in parallel.
 template <int WB>
-__device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t ntask) {
+__device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t nedge) {
     const uint32_t lane = lane_id();
     const bool ppr = c.qt == Q_PPR;
+    const uint32_t ntask = (nedge + GW - 1) / GW;
     for (;;) {
         uint32_t task = 0;
         if (lane == 0) task = atomicAdd(&S.next, 1u);
         task = __shfl(task, 0);
         if (task >= ntask) break;
-        const uint32_t k = gtask_vertex(S, nr, task);
-        const uint32_t v = c.v0 + S.rv[k];
-        const unsigned long long m = S.rm[k];
-        const bool act = (m >> lane) & 1ull;
-        const uint32_t na = __popcll(m);
-        const uint32_t r0 = c.g.rowptr[v], r1 = c.g.rowptr[v + 1];
-        const uint32_t eb = r0 + (task - S.rnt[k]) * GW;
-        const uint32_t cnt = r1 - eb < (uint32_t)GW ? r1 - eb : (uint32_t)GW;
-        // this task's targets (and weights), one per lane
-        const uint32_t myu = lane < cnt ? c.g.col[eb + lane] : 0u;
-        const uint32_t myw = (lane < cnt && !ppr && WB != 0 && c.qt != Q_BFS) ? edge_w<WB>(c.g.w, eb + lane) : 1u;
+        const uint32_t f = task * GW + lane;
+        const uint32_t cnt = nedge - task * GW < (uint32_t)GW ? nedge - task * GW : (uint32_t)GW;
+        // edge `lane` of this task: its round vertex, target and weight
+        uint32_t myk = 0, myu = 0, myw = 1u;
         float mythr = 0.f;
-        if (ppr && lane < cnt) {
-            const uint32_t du = c.g.rowptr[myu + 1] - c.g.rowptr[myu];
-            mythr = du;  // degree; scaled per lane below
+        if (lane < cnt) {
+            myk = gedge_vertex(S, nr, f);
+            const uint32_t v = c.v0 + S.rv[myk];
+            const uint32_t e = c.g.rowptr[v] + (f - S.rnt[myk]);
+            myu = c.g.col[e];
+            if (!ppr && WB != 0 && c.qt != Q_BFS) myw = edge_w<WB>(c.g.w, e);
+            if (ppr) mythr = (float)(c.g.rowptr[myu + 1] - c.g.rowptr[myu]);  // degree, scaled per lane below
         }
-        const uint32_t intra = __popcll(wballot(lane < cnt && myu - c.v0 < c.nvp));
-        uint32_t d = INF;
-        float share = 0.f;
-        if (ppr) share = SH.share[k][lane];
-        else if (act) d = fresh_load(&c.st[(unsigned long long)v * GW + lane]);
+        uint32_t kprev = 0xffffffffu, dprev = INF;
+        float sprev = 0.f;
+        bool aprev = false;
+        unsigned long long lane_edges = 0;
         for (uint32_t j0 = 0; j0 < cnt; j0 += UNR) {
             uint32_t u[UNR];
+            bool act[UNR];
             bool hit[UNR];
             uint32_t val[UNR];
+            uint32_t dsrc[UNR];
+            float shr[UNR];
 #pragma unroll
-            for (int j = 0; j < UNR; ++j) u[j] = __shfl(myu, (int)(j0 + j) & (GW - 1));
+            for (int j = 0; j < UNR; ++j) {
+                const bool ok = j0 + j < cnt;
+                const uint32_t kj = __shfl(myk, (int)(j0 + j) & (GW - 1));
+                u[j] = __shfl(myu, (int)(j0 + j) & (GW - 1));
+                if (ok && kj != kprev) {  // a new source vertex (uniform): its mask and this lane's value
+                    kprev = kj;
+                    const unsigned long long m = S.rm[kj];
+                    aprev = (m >> lane) & 1ull;
+                    if (ppr) sprev = SH.share[kj][lane];
+                    else dprev = aprev ? fresh_load(&c.st[(unsigned long long)(c.v0 + S.rv[kj]) * GW + lane]) : INF;
+                }
+                act[j] = ok && aprev;
+                dsrc[j] = dprev;
+                shr[j] = sprev;
+                c.c_intra += (act[j] && u[j] - c.v0 < c.nvp) ? 1u : 0u;
+            }
             if (ppr) {
                 float thu[UNR], old[UNR];
 #pragma unroll
@@ -360,14 +378,13 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
                 }
 #pragma unroll
                 for (int j = 0; j < UNR; ++j)
-                    old[j] = (act && j0 + j < cnt)
-                                 ? __hip_atomic_fetch_add((float*)&c.st[(unsigned long long)u[j] * GW + lane], share,
-                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                 : 0.f;
+                    old[j] = act[j] ? __hip_atomic_fetch_add((float*)&c.st[(unsigned long long)u[j] * GW + lane], shr[j],
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                    : 0.f;
 #pragma unroll
                 for (int j = 0; j < UNR; ++j) {
-                    const float nr_ = old[j] + share;
-                    hit[j] = act && j0 + j < cnt && !ppr_active(old[j], thu[j]) && ppr_active(nr_, thu[j]);
+                    const float nr_ = old[j] + shr[j];
+                    hit[j] = act[j] && !ppr_active(old[j], thu[j]) && ppr_active(nr_, thu[j]);
                     val[j] = ~__float_as_uint(nr_);
                 }
             } else {
@@ -375,15 +392,14 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
 #pragma unroll
                 for (int j = 0; j < UNR; ++j) {
                     const uint32_t w = __shfl(myw, (int)(j0 + j) & (GW - 1));
-                    const unsigned long long sum = (unsigned long long)d + w;
+                    const unsigned long long sum = (unsigned long long)dsrc[j] + w;
                     nd[j] = sum >= INF ? INF - 1 : (uint32_t)sum;
                 }
 #pragma unroll
-                for (int j = 0; j < UNR; ++j)
-                    cur[j] = (act && j0 + j < cnt) ? c.st[(unsigned long long)u[j] * GW + lane] : 0u;
+                for (int j = 0; j < UNR; ++j) cur[j] = act[j] ? c.st[(unsigned long long)u[j] * GW + lane] : 0u;
 #pragma unroll
                 for (int j = 0; j < UNR; ++j) {
-                    bool imp = act && j0 + j < cnt && nd[j] < cur[j];
+                    bool imp = act[j] && nd[j] < cur[j];
                     if (imp) imp = nd[j] < dev_min(&c.st[(unsigned long long)u[j] * GW + lane], nd[j]);
                     c.c_improved += imp ? 1u : 0u;
                     hit[j] = imp;
@@ -399,15 +415,13 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
                 const uint32_t first = bm ? (uint32_t)(__ffsll(bm) - 1) : 0u;
                 const uint32_t vj = __shfl(val[j], (int)first);
                 if (lane == (uint32_t)j) { mine_bits = bm; mine_val = vj; mine_u = u[j]; }
+                c.c_edges += act[j] ? 1u : 0u;
+                if (ppr) c.c_edges_ppr += act[j] ? 1u : 0u;
+                lane_edges += __popcll(wballot(act[j]));
             }
             if (mine_bits) gmark(c, S, mine_u, mine_bits, mine_val);
         }
-        c.c_edges += act ? cnt : 0u;
-        if (ppr) c.c_edges_ppr += act ? cnt : 0u;
-        if (lane == 0) {
-            c.c_intra += (unsigned long long)intra * na;  // lane-edges into the partition, once per wave
-            atomicAdd(&S.edges, (unsigned long long)cnt * na);
-        }
+        if (lane == 0) atomicAdd(&S.edges, lane_edges);
     }
 }
 
@@ -471,10 +485,10 @@ __device__ void gvisit(GCtx& c, GShared& S, GCtxShare& SH, const PassCfg& cfg) {
             ground_min(c, S, nr);
             gfilter_sp(c, S, nr);
         }
-        const uint32_t ntask = gnumber_tasks(S, nr);
+        const uint32_t nedge = gnumber_edges(S, nr);
         if (t == 0) S.next = 0;
         __syncthreads();
-        gtasks<WB>(c, S, SH, nr, ntask);
+        gtasks<WB>(c, S, SH, nr, nedge);
         __syncthreads();
         if (budget && S.edges >= budget) break;
     }

@@ -312,9 +312,11 @@ def test_hashed_slice_grid_and_bad_slots():
 
 def test_large_partitions_use_hashed_slice():
     """Partitions of 32K-64K vertices do not fit a dense LDS slice: the library
-    picks a hashed slice by itself, and explicit slot counts work too."""
+    picks a hashed slice by itself, and explicit slot counts work too.  On a
+    grid a visit's frontier is a narrow wavefront, so these runs stay below the
+    frontier-spill bound."""
     fork = _fork()
-    g = fi.rmat(17, seed=3, weights=(1, 255), weight_seed=103)
+    g = fi.grid(256, 512, weights=(1, 1000), weight_seed=23)
     s1 = fi.sources_uniform(g, 12, 17)
     s3 = fi.sources_uniform(g, 8, 18)
     ref = oracle.sssp(g, s1)
@@ -324,11 +326,43 @@ def test_large_partitions_use_hashed_slice():
         fg.submit("sssp", s1)
         fg.submit("ppr", s3, alpha=ALPHA, epsilon=1e-6, eps_mode=1)
         fg.run(slice_slots=slots, max_passes=200000)
+        assert fg.stats()["spill_max"] <= 32768
         np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(12)]), ref)
         P = np.stack([fg.fetch(12 + i, fork.FIELD_P) for i in range(8)])
         R = np.stack([fg.fetch(12 + i, fork.FIELD_R) for i in range(8)])
         fg.close()
         check_ppr(g, s3, P, R, 1e-6, 1)
+
+
+def test_large_rmat_partitions_stop_at_the_spill_bound():
+    """On R-MAT 17 a visit of a 32K-64K-vertex partition activates far more
+    vertices than its frontier holds: measured at 36,600-72,400 retained per
+    visit, above the bound of 32,768.  That regime stops with FORK_E_CAPACITY
+    and says why; the batch then runs at 16,384-vertex partitions (about
+    10,800 retained) with exact distances."""
+    fork = _fork()
+    g = fi.rmat(17, seed=3, weights=(1, 255), weight_seed=103)
+    s1 = fi.sources_uniform(g, 12, 17)
+    s3 = fi.sources_uniform(g, 8, 18)
+    say("rmat17 65536-vertex partitions, expecting the spill refusal")
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=65536)
+    fg.submit("sssp", s1)
+    fg.submit("ppr", s3, alpha=ALPHA, epsilon=1e-6, eps_mode=1)
+    with pytest.raises(fork.ForkError) as e:
+        fg.run(max_passes=200000)
+    assert e.value.code == fork.FORK_E_CAPACITY and "frontier-spill" in str(e.value)
+    fg.close()
+    say("rmat17 16384-vertex partitions")
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=16384)
+    fg.submit("sssp", s1)
+    fg.submit("ppr", s3, alpha=ALPHA, epsilon=1e-6, eps_mode=1)
+    fg.run(max_passes=200000)
+    assert 0 < fg.stats()["spill_max"] <= 32768
+    np.testing.assert_array_equal(np.stack([fg.fetch(i) for i in range(12)]), oracle.sssp(g, s1))
+    P = np.stack([fg.fetch(12 + i, fork.FIELD_P) for i in range(8)])
+    R = np.stack([fg.fetch(12 + i, fork.FIELD_R) for i in range(8)])
+    fg.close()
+    check_ppr(g, s3, P, R, 1e-6, 1)
 
 
 def test_four_byte_weights_and_clamped_tentative_sums():
