@@ -345,6 +345,24 @@ int fork_mlp_train(float *theta, const float *x, const float *t, uint64_t n,
                    uint32_t steps, uint32_t batch, float lr, uint64_t seed,
                    float *losses);
 
+/*
+ * fork_mlp_train without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid it).  The same training as fork_mlp_train, but every pointer is
+ * a device pointer on the current device: theta[5313] (updated in place),
+ * x[n][16], t[n], losses[steps] (or NULL); the work is queued on `stream`
+ * (hipStream_t, NULL = the default stream) and the call returns without
+ * waiting for it.  The gradient, Adam's moments and the epoch permutation
+ * live in a fixed array of this library in device memory (one per GPU,
+ * about 190 KB, held until the process ends), so n is limited to 32,768
+ * samples (FORK_E_INVALID beyond).  Calls that overlap on one GPU share that
+ * array and race: serialise them (one stream, or wait between calls).
+ * Nothing is allocated: no hipMalloc/hipFree, no host allocation; every value
+ * that must start at zero is cleared by a kernel at the start of each call.
+ */
+int fork_mlp_train_noalloc(float *theta, const float *x, const float *t, uint64_t n, uint32_t steps,
+                           uint32_t batch, float lr, uint64_t seed, float *losses, void *stream);
+
 /* Copy the counters of the last run into *dst (dst_bytes >= sizeof): the
  * work measures of the paper's evaluation (edges processed, compared with the
  * sequential algorithms' in Section 6.3; operations buffered and consumed,

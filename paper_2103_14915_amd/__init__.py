@@ -88,7 +88,7 @@ class fork_digest(ctypes.Structure):
 
 EXPORTS = ["fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions",
            "fork_trace", "fork_destroy", "fork_last_error", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train",
-           "fork_sweep", "fork_bc"]
+           "fork_sweep", "fork_bc", "fork_mlp_train_noalloc"]
 SWEEP_MAX, SWEEP_BUCKETS = 1024, 11
 TRACE_WIDTH = 20
 
@@ -113,13 +113,15 @@ def _load():
     lib.fork_mlp_forward.argtypes = [P, P, U64, P]
     lib.fork_mlp_grad.argtypes = [P, P, P, U64, P, P]
     lib.fork_mlp_train.argtypes = [P, P, P, U64, U32, U32, ctypes.c_float, U64, P]
+    lib.fork_mlp_train_noalloc.argtypes = [P, P, P, U64, U32, U32, ctypes.c_float, U64, P, P]
     lib.fork_sweep.argtypes = [P, U32, U32, U32, P]
     lib.fork_bc.argtypes = [P, U32, U32, P]
     lib.fork_destroy.argtypes = [P]
     lib.fork_destroy.restype = None
     lib.fork_last_error.restype = ctypes.c_char_p
     for n in ("fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions",
-              "fork_trace", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train", "fork_sweep", "fork_bc"):
+              "fork_trace", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train", "fork_sweep", "fork_bc",
+              "fork_mlp_train_noalloc"):
         getattr(lib, n).restype = I
     return lib
 
@@ -316,3 +318,23 @@ def mlp_train(theta, x, t, steps, batch=256, lr=1e-3, seed=0):
                               losses.ctypes.data))
     return th, losses[:steps]
 
+
+def mlp_train_noalloc(theta, x, t, steps, batch=256, lr=1e-3, seed=0, losses=None, stream=None):
+    """fork_mlp_train_noalloc on device tensors (no allocation inside the library).
+
+    theta: float32 CUDA tensor [5313], updated in place; x [n, 16] and t [n]
+    float32 CUDA tensors; losses: None or a float32 CUDA tensor [steps].  The
+    work is queued on `stream` (default: torch's current stream)."""
+    import torch
+    for name, a in (("theta", theta), ("x", x), ("t", t)) + ((("losses", losses),) if losses is not None else ()):
+        if not (a.is_cuda and a.dtype == torch.float32 and a.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    n = t.numel()
+    if theta.numel() != MLP_NPARAM or x.numel() != 16 * n:
+        raise ValueError("shapes: theta [5313], x [n, 16], t [n]")
+    if losses is not None and losses.numel() < steps:
+        raise ValueError("losses needs `steps` entries")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    sp = s if isinstance(s, int) else s.cuda_stream
+    _check(lib.fork_mlp_train_noalloc(theta.data_ptr(), x.data_ptr(), t.data_ptr(), n, steps, batch, lr, seed,
+                                      None if losses is None else losses.data_ptr(), sp))

@@ -160,6 +160,94 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* theta, const f
 }  // namespace fk
 
 namespace fk {
+hipError_t launch_mlp_grad(const float*, const float*, const float*, const uint32_t*, uint32_t, float*, float*,
+                           hipStream_t);
+hipError_t launch_adam(float*, const float*, float*, float*, uint32_t, float, hipStream_t);
+// ------------------------------------------------------------ training without allocation
+// Scratch of fork_mlp_train_noalloc, one copy per GPU for the life of the
+// process: the gradient, Adam's two moments, a loss sink, the generator
+// state of the epoch shuffles and the sample permutation.
+constexpr uint32_t TRAIN_NMAX = 32768;  // samples (the shuffle runs in one workgroup's LDS)
+constexpr size_t SCR_GRAD = 0, SCR_M = MLP_NPARAM, SCR_V = 2 * MLP_NPARAM, SCR_SINK = 3 * MLP_NPARAM;
+constexpr size_t SCR_RNG = (3 * MLP_NPARAM + 2) & ~(size_t)1;  // 8-byte aligned word index
+constexpr size_t SCR_PERM = SCR_RNG + 2;
+constexpr size_t SCRATCH_WORDS = SCR_PERM + TRAIN_NMAX;
+static __device__ __align__(256) uint32_t scratch[SCRATCH_WORDS];
+
+__global__ void k_fill32(uint32_t* p, uint32_t n, uint32_t v) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+// perm = identity, generator state = seed.
+__global__ void k_perm_init(uint32_t* perm, uint32_t n, unsigned long long* st, unsigned long long seed) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) perm[i] = i;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *st = seed;
+}
+
+// One epoch's shuffle of perm: the Fisher-Yates pass of fork_mlp_train with
+// the same SplitMix64 stream, done by one thread on an LDS copy.
+__global__ __launch_bounds__(256) void k_perm_shuffle(uint32_t* perm, uint32_t n, unsigned long long* st) {
+    extern __shared__ uint32_t dyn[];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) dyn[i] = perm[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = *st;
+        for (uint32_t i = n - 1; i > 0; --i) {
+            s += 0x9E3779B97F4A7C15ull;
+            const uint32_t j = (uint32_t)(mix64(s) % (unsigned long long)(i + 1));
+            const uint32_t x = dyn[i];
+            dyn[i] = dyn[j];
+            dyn[j] = x;
+        }
+        *st = s;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) perm[i] = dyn[i];
+}
+
+uint32_t train_nmax() { return TRAIN_NMAX; }
+// Once per device: the shuffle's LDS copy of the permutation exceeds the default 64 KB.
+hipError_t train_prepare() {
+    return hipFuncSetAttribute((const void*)k_perm_shuffle, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(TRAIN_NMAX * sizeof(uint32_t)));
+}
+size_t train_scratch_bytes() { return sizeof(scratch); }
+// The scratch array's device address on the current device.
+hipError_t train_scratch_address(void** p) { return hipGetSymbolAddress(p, HIP_SYMBOL(scratch)); }
+
+hipError_t launch_train_noalloc(uint32_t* scr, float* theta, const float* X, const float* T, uint32_t n,
+                                uint32_t steps, uint32_t batch, float lr, unsigned long long seed, float* losses,
+                                hipStream_t s) {
+    float* grad = (float*)scr + SCR_GRAD;
+    float* m = (float*)scr + SCR_M;
+    float* v = (float*)scr + SCR_V;
+    float* sink = (float*)scr + SCR_SINK;
+    unsigned long long* st = (unsigned long long*)(scr + SCR_RNG);
+    uint32_t* perm = scr + SCR_PERM;
+    // everything that must start at zero is cleared by a kernel (the array keeps the last call's contents)
+    hipLaunchKernelGGL(k_fill32, dim3(64), dim3(256), 0, s, scr, (uint32_t)(3 * MLP_NPARAM + 1), 0u);
+    if (losses && steps) hipLaunchKernelGGL(k_fill32, dim3(64), dim3(256), 0, s, (uint32_t*)losses, steps, 0u);
+    hipLaunchKernelGGL(k_perm_init, dim3(64), dim3(256), 0, s, perm, n, st, seed);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint64_t pos = n;
+    for (uint32_t k = 1; k <= steps; ++k) {
+        if (pos + batch > n) {
+            hipLaunchKernelGGL(k_perm_shuffle, dim3(1), dim3(256), n * sizeof(uint32_t), s, perm, n, st);
+            pos = 0;
+        }
+        hipLaunchKernelGGL(k_fill32, dim3(8), dim3(256), 0, s, (uint32_t*)grad, (uint32_t)MLP_NPARAM, 0u);
+        e = launch_mlp_grad(theta, X, T, perm + pos, batch, grad, losses ? losses + (k - 1) : sink, s);
+        if (e != hipSuccess) return e;
+        e = launch_adam(theta, grad, m, v, k, lr, s);
+        if (e != hipSuccess) return e;
+        pos += batch;
+    }
+    return hipGetLastError();
+}
+}  // namespace fk
+
+namespace fk {
 hipError_t launch_mlp_grad(const float* theta, const float* X, const float* T, const uint32_t* idx, uint32_t n,
                            float* grad, float* loss, hipStream_t s) {
     hipLaunchKernelGGL(k_mlp_grad, dim3((n + GB - 1) / GB), dim3(256), 0, s, theta, X, T, idx, n, 1.f / (float)n,

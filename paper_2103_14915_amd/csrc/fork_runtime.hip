@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "fork.h"
@@ -60,6 +61,11 @@ hipError_t launch_gsummaries(const GraphDev&, const GroupDev&, const BufDev&, co
 hipError_t launch_gworklist(const BufDev&, const GroupDev&, const PassCfg&, hipStream_t);
 hipError_t launch_gseed(const GraphDev&, const GroupDev&, const uint32_t*, hipStream_t);
 hipError_t launch_gout(const GroupDev&, uint32_t, uint32_t*, const unsigned long long*, const uint32_t*, hipStream_t);
+uint32_t train_nmax();
+hipError_t train_prepare();
+hipError_t train_scratch_address(void**);
+hipError_t launch_train_noalloc(uint32_t*, float*, const float*, const float*, uint32_t, uint32_t, uint32_t, float,
+                                unsigned long long, float*, hipStream_t);
 }  // namespace fk
 
 // Message of the last failing call on this thread (a fixed buffer: reporting
@@ -1543,3 +1549,37 @@ extern "C" int fork_mlp_train(float* theta, const float* x, const float* t, uint
     return FORK_OK;
 }
 
+// ------------------------------------------------------------ training without allocation
+// The scratch array's address, looked up once per device with that device
+// current (each GPU holds its own copy of the array).
+static std::mutex g_scr_m;
+static void* g_scr[64];
+
+extern "C" int fork_mlp_train_noalloc(float* theta, const float* x, const float* t, uint64_t n, uint32_t steps,
+                                      uint32_t batch, float lr, uint64_t seed, float* losses, void* stream) {
+    g_err[0] = 0;
+    if (!theta || !x || !t) return fail(FORK_E_INVALID, "theta, x and t must be device pointers");
+    if (n == 0 || n > fk::train_nmax())
+        return fail(FORK_E_INVALID, "n = %llu samples; the allocation-free trainer takes 1..%u",
+                    (unsigned long long)n, fk::train_nmax());
+    if (batch == 0 || !(lr > 0.f)) return fail(FORK_E_INVALID, "bad training arguments");
+    if (batch > n) batch = (uint32_t)n;
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(FORK_E_DEVICE, "device ordinal %d out of range", dev);
+    void* scr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scr_m);
+        if (!g_scr[dev]) {
+            void* p = nullptr;
+            HIPCHK(fk::train_scratch_address(&p));
+            if (!p) return fail(FORK_E_DEVICE, "no device address for the training scratch");
+            HIPCHK(fk::train_prepare());
+            g_scr[dev] = p;
+        }
+        scr = g_scr[dev];
+    }
+    HIPCHK(fk::launch_train_noalloc((uint32_t*)scr, theta, x, t, (uint32_t)n, steps, batch, lr, seed, losses,
+                                    (hipStream_t)stream));
+    return FORK_OK;
+}

@@ -159,3 +159,31 @@ def test_grouped_engine_exact_under_concurrency(fs):
         assert oracle.ppr_invariant_l1(g, s, p, r.astype(np.float64), 0.15) <= 1e-4
     fg.close()
 
+
+def test_no_alloc_training_on_the_host_build(fs):
+    """fork_mlp_train_noalloc against fork_mlp_train in the host build (where
+    device pointers are host pointers): two calls in a row, the second with
+    fewer samples, reuse the library's fixed scratch array."""
+    import ctypes
+    from oracle import mlp as omlp
+    lib = fs.load()
+    P, U32, U64, F = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float
+    lib.fork_mlp_train.argtypes = [P, P, P, U64, U32, U32, F, U64, P]
+    lib.fork_mlp_train_noalloc.argtypes = [P, P, P, U64, U32, U32, F, U64, P, P]
+    rng = np.random.default_rng(21)
+    theta0 = omlp.init(13).astype(np.float32)
+    for n, steps, batch, lr, seed in ((3000, 7, 256, 3e-3, 5), (500, 4, 128, 1e-3, 6)):
+        x = rng.normal(size=(n, 16)).astype(np.float32)
+        t = (x[:, 0] - np.abs(x[:, 1])).astype(np.float32)
+        a, b = theta0.copy(), theta0.copy()
+        la, lb = np.zeros(steps, np.float32), np.full(steps, 123.0, np.float32)
+        assert lib.fork_mlp_train(a.ctypes.data, x.ctypes.data, t.ctypes.data, n, steps, batch, lr, seed,
+                                  la.ctypes.data) == 0
+        assert lib.fork_mlp_train_noalloc(b.ctypes.data, x.ctypes.data, t.ctypes.data, n, steps, batch, lr, seed,
+                                          lb.ctypes.data, None) == 0
+        np.testing.assert_allclose(lb, la, rtol=1e-5, atol=1e-7)
+        d = np.abs(a.astype(np.float64) - b)
+        assert np.mean(d <= 1e-6 + 1e-5 * np.abs(a)) >= 0.995
+    big = np.zeros((32769, 16), np.float32)
+    assert lib.fork_mlp_train_noalloc(theta0.ctypes.data, big.ctypes.data, big[:, 0].copy().ctypes.data, 32769, 1,
+                                      256, 1e-3, 0, None, None) == -1
