@@ -307,8 +307,9 @@ def main():
     for _ in range(args.steps):
         fg.run(**run_kw)
         st = fg.stats()
-        tot = st if tot is None else {k: tot[k] + st[k] if isinstance(st[k], (int, float)) else st[k]
-                                      for k in st}
+        tot = st if tot is None else {k: tot[k] + st[k] if isinstance(st[k], (int, float))
+                                      else [a + b for a, b in zip(tot[k], st[k])] if isinstance(st[k], list)
+                                      else st[k] for k in st}
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     for k in ("num_partitions", "weight_bytes"):
@@ -364,6 +365,13 @@ def main():
                    "refine_rounds_per_step": tot["refine_rounds"] / args.steps,
                    "activations_per_step": tot["activations"] / args.steps,
                    "expansions_per_step": tot["expansions"] / args.steps,
+                   "rounds_per_step": tot["rounds"] / args.steps, "edge_tasks_per_step": tot["edge_tasks"] / args.steps,
+                   "ppr_edges_per_step": tot["ppr_edges"] / args.steps,
+                   "ppr_vertex_pushes_per_step": tot["ppr_vertex_pushes"] / args.steps,
+                   "improved_per_step": tot["improved"] / args.steps,
+                   "visit_phase_share": ({n: v / max(1, sum(tot["visit_ns"])) for n, v in
+                                          zip(("gather", "take", "filter", "tasks", "yield"), tot["visit_ns"])}
+                                         if sum(tot["visit_ns"]) else None),
                    "spilled_per_step": tot["spilled"] / args.steps, "spill_max": st["spill_max"]},
     }
     if args.compare_learned == "auto":

@@ -188,6 +188,13 @@ typedef struct {
     uint64_t spill_max;        /* most vertices one visit retained as
                                   operations (a visit retaining more than
                                   32,768 stops the run: FORK_E_CAPACITY)    */
+    uint64_t rounds;           /* grouped engine: rounds of the visits (one
+                                  round expands a set of pending vertices)  */
+    uint64_t edge_tasks;       /* grouped engine: 64-edge tasks of the rounds*/
+    uint64_t visit_ns[5];      /* grouped engine: workgroup time in the visit
+                                  phases, summed over workgroups: [0] bitmap
+                                  gather, [1] round take, [2] filter and edge
+                                  numbering, [3] edge tasks, [4] yield      */
 } fork_stats_t;
 
 /* Per-query digest (fork_fetch field FORK_FIELD_DIGEST).  For SSSP/BFS:

@@ -69,10 +69,12 @@ class fork_stats_t(ctypes.Structure):
                 ("weight_bytes", ctypes.c_uint32), ("refine_rounds", ctypes.c_uint64),
                 ("selected_edges", ctypes.c_uint64), ("ppr_edges", ctypes.c_uint64),
                 ("ppr_vertex_pushes", ctypes.c_uint64), ("spilled", ctypes.c_uint64),
-                ("activations", ctypes.c_uint64), ("expansions", ctypes.c_uint64), ("spill_max", ctypes.c_uint64)]
+                ("activations", ctypes.c_uint64), ("expansions", ctypes.c_uint64), ("spill_max", ctypes.c_uint64),
+                ("rounds", ctypes.c_uint64), ("edge_tasks", ctypes.c_uint64), ("visit_ns", ctypes.c_uint64 * 5)]
 
     def as_dict(self):
-        return {n: getattr(self, n) for n, _ in self._fields_}
+        return {n: (list(getattr(self, n)) if isinstance(getattr(self, n), ctypes.Array) else getattr(self, n))
+                for n, _ in self._fields_}
 
 
 class fork_sweep_t(ctypes.Structure):

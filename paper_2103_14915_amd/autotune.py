@@ -37,8 +37,8 @@ GROUPED_PVMAX = 16384  # largest partition the grouped engine visits
 
 def valid(p) -> bool:
     """Knob combinations the library accepts."""
-    if p.get("engine") == "grouped":
-        return p["partition_vertices"] <= GROUPED_PVMAX and not p["persistent"]
+    if p.get("engine") == "grouped":  # the persistent kernel and the LDS slice shape belong to the other engine
+        return p["partition_vertices"] <= GROUPED_PVMAX and not p["persistent"] and not p.get("slice_slots")
     return not p.get("group_threads")  # the workgroup size is a grouped-engine knob
 
 

@@ -64,6 +64,10 @@ struct Ctl {
     unsigned long long c_act;       // grouped engine: (vertex, group) activations in other partitions
     unsigned int c_spill_max;       // most vertices one visit retained because its frontier was full
     unsigned long long c_vtask;     // grouped engine: vertex expansions (each for one or more lanes)
+    unsigned long long c_rounds;    // grouped engine: rounds of the visits
+    unsigned long long c_tasks;     // grouped engine: 64-edge tasks of the rounds
+    unsigned long long c_tphase[5]; // grouped engine: workgroup time (10 ns ticks) in the visit phases:
+                                    // bitmap gather, round take, filter, edge tasks, yield
 };
 
 // A (partition, query) work item of one pass.

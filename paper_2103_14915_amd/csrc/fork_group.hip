@@ -27,30 +27,67 @@ namespace fk {
 constexpr int GW = 64;        // queries per group (one per lane)
 constexpr int GNTMAX = 1024;  // threads per workgroup: 256, 512 or 1024 (chosen at launch)
 constexpr int GNWMAX = GNTMAX / WAVE;
-constexpr int RCAP = 1024;    // vertices per round
+constexpr int RCAP = 512;     // vertices per round
 constexpr uint32_t GPVMAX = 16384;  // largest partition the grouped engine visits
 constexpr int LBW = GPVMAX / 32;     // local pending bitmap words
 constexpr int UNR = 8;        // edges in flight per wave step (and marking lanes)
-constexpr int PCAP = 32;      // PPR vertices per round (their shares are kept in LDS)
-static_assert(UNR <= WAVE && RCAP % GNTMAX == 0, "task layout");
+constexpr int BAT = 4;        // round vertices per wave whose row loads are issued together
+static_assert(UNR <= WAVE && RCAP % 256 == 0, "task layout");
 
-// Per-lane pushed shares of a PPR round's vertices.
-struct GCtxShare {
-    float share[PCAP][GW];
+// Per round vertex and lane, what its out-edges carry: SSSP/BFS the lane's
+// value when the vertex was filtered (a snapshot: the value can only have
+// dropped since, which the vertex's new pending mark covers), PPR the share
+// each out-edge receives.  Kept in LDS so that the edge tasks read no source
+// row from memory.
+union GCtxShare {
+    uint32_t sd[RCAP][GW];
+    float share[RCAP][GW];
 };
+
+// Block counters (LDS), added by one lane per wave from ballot counts.
+enum { K_EDGES, K_INTRA, K_IMPROVED, K_VPUSH, K_ACT, K_EDGES_PPR, K_VPUSH_PPR, K_VTASK, K_ROUNDS, K_TASKS,
+       K_T_GATHER, K_T_TAKE, K_T_FILTER, K_T_TASKS, K_T_YIELD, NCNT };
 
 struct GShared {
     uint32_t lbits[LBW];              // pending vertices of the partition (local ids)
     uint32_t rv[RCAP];                // round: vertex (local id)
     unsigned long long rm[RCAP];      // round: lanes taken, then lanes expanding
-    uint32_t rnt[RCAP];               // round: edge tasks of the vertex, then its first task
+    uint32_t rnt[RCAP];               // round: expanding out-edges of the vertex, then its first flat edge
+    uint32_t rdeg[RCAP];              // round: out-degree of the vertex
     uint32_t nr, next;
     uint32_t lmin[GW];                // per lane: least pending value of the round (SSSP/BFS)
     uint32_t wred[GNWMAX];
     unsigned long long edges;         // lane-edges of the visit so far
     unsigned long long itpos;
+    unsigned long long cnt[NCNT];
+    unsigned long long tk;            // start of the current visit phase (thread 0)
     Item it;
 };
+
+// Wave-uniform count n added to block counter k (call from every lane of a wave).
+__device__ __forceinline__ void gcount(GShared& S, int k, uint32_t n) {
+    if (lane_id() == 0 && n) atomicAdd(&S.cnt[k], (unsigned long long)n);
+}
+
+// Entry `lane` of vertex u's row in a group's state block.  Byte offsets are
+// 32-bit: the grouped engine takes graphs of at most 2^24 vertices.
+__device__ __forceinline__ uint32_t* rowp(uint32_t* base, uint32_t u, uint32_t lane) {
+    return (uint32_t*)((char*)base + (u * (uint32_t)(GW * 4) + lane * 4u));
+}
+__device__ __forceinline__ float* rowf(float* base, uint32_t u, uint32_t lane) {
+    return (float*)((char*)base + (u * (uint32_t)(GW * 4) + lane * 4u));
+}
+
+// The rows of a group's state block as a buffer resource (gfx9 raw buffer,
+// no stride): a lane whose byte offset lies beyond the block reads 0 and
+// touches no memory, so a wave loads rows for its active lanes only without a
+// branch around the load (a branch would make the compiler wait for each load
+// in turn).
+constexpr uint32_t ROW_NONE = 0xfffffffcu;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(uint32_t* base, uint32_t nv) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)(nv * (uint32_t)(GW * 4)), 0x00020000);
+}
+__device__ __forceinline__ uint32_t row_off(uint32_t u, uint32_t lane) { return u * (uint32_t)(GW * 4) + lane * 4u; }
 
 __device__ __forceinline__ unsigned long long gpend_take(unsigned long long* p) {
     return __hip_atomic_exchange(p, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -58,6 +95,9 @@ __device__ __forceinline__ unsigned long long gpend_take(unsigned long long* p) 
 __device__ __forceinline__ uint32_t fresh_load(uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Make this thread's earlier device atomics visible before what follows (a
+// barrier then lets other threads of the block act on them).
+__device__ __forceinline__ void mem_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 
 struct GCtx {
     GraphDev g;
@@ -70,28 +110,38 @@ struct GCtx {
     uint32_t mode;
     uint32_t win;          // heuristic-2 bound: lanes with value > win wait (INF: none)
     uint32_t bwin;         // batch width inside a visit: a lane expands values in [lmin, lmin + bwin)
-    unsigned long long c_edges, c_intra, c_improved, c_vpush, c_act, c_edges_ppr, c_vpush_ppr, c_vtask;
 };
 
 // Mark lanes `bits` of vertex u (global id) pending in the group.  Called by
-// one lane.  val: the activation's priority (SSSP/BFS distance; PPR ~residual bits).
-__device__ __forceinline__ void gmark(GCtx& c, GShared& S, uint32_t u, unsigned long long bits, uint32_t val) {
-    const unsigned long long old = dev_or(&c.G.pend[(unsigned long long)c.grp * c.g.nv + u], bits);
+// one lane.  val: the activation's priority (SSSP/BFS distance; PPR ~residual
+// bits).  Returns true for a new activation registered in another partition.
+//
+// Split in two so that a caller can overlap the wait for the mask's old value
+// with other work: gmark_begin sets the lanes in the mask and returns its old
+// value, gmark_end registers the activation from it.
+__device__ __forceinline__ unsigned long long gmark_begin(GCtx& c, uint32_t u, unsigned long long bits) {
+    return dev_or(&c.G.pend[(unsigned long long)c.grp * c.g.nv + u], bits);
+}
+__device__ __forceinline__ bool gmark_end(GCtx& c, GShared& S, uint32_t u, unsigned long long old, uint32_t val) {
     const uint32_t ul = u - c.v0;
     if (ul < c.nvp) {
         if (!old) atomicOr(&S.lbits[ul >> 5], 1u << (ul & 31));
-        return;
+        return false;
     }
     const uint32_t Pu = c.g.vpart[u >> c.g.pshift];
     const unsigned long long pi = (unsigned long long)Pu * c.G.ng + c.grp;
-    // only the mask's old value is waited for; the rest are fire-and-forget atomics
+    // only the mask's old value is waited for (it orders the mask before the
+    // bitmap bit that announces it); the rest are fire-and-forget atomics
     if (!old) {
         dev_or(&c.G.bits[(unsigned long long)c.grp * c.G.bw + (u >> 5)], 1u << (u & 31));
         dev_add(&c.G.icnt[pi], 1u);
         dev_min(&c.G.ifirst[pi], c.pass);
-        ++c.c_act;
     }
     dev_min(&c.G.ibest[pi], val);
+    return !old;
+}
+__device__ __forceinline__ bool gmark(GCtx& c, GShared& S, uint32_t u, unsigned long long bits, uint32_t val) {
+    return gmark_end(c, S, u, gmark_begin(c, u, bits), val);
 }
 
 // Re-register vertex vloc of the visited partition as pending in the pair's
@@ -111,11 +161,12 @@ template <class T> __device__ __forceinline__ T wave_min(T v) {
     return v;
 }
 
-// Build the next round from the local bitmap: up to RCAP vertices, their
-// pending lanes taken from the global masks.  Returns the round size.
+// Build the next round from the local bitmap: up to `cap` vertices, their
+// pending lanes taken from the global masks (one vertex per thread, so the
+// exchanges are in flight together) and their degrees.  Returns the round size.
 __device__ uint32_t gtake_round(GCtx& c, GShared& S, uint32_t cap) {
     const uint32_t t = threadIdx.x;
-    if (t == 0) { S.nr = 0; S.next = 0; }
+    if (t == 0) S.nr = 0;
     __syncthreads();
     const uint32_t nw = (c.nvp + 31) / 32;
     for (uint32_t w0 = 0; w0 < nw; w0 += blockDim.x) {
@@ -123,29 +174,27 @@ __device__ uint32_t gtake_round(GCtx& c, GShared& S, uint32_t cap) {
         uint32_t word = w < nw ? S.lbits[w] : 0u;
         // how many of this word's vertices fit in the round
         const uint32_t cnt = __popc(word);
-        uint32_t room = 0;
         if (cnt) {
             const uint32_t at = atomicAdd(&S.nr, cnt);
-            room = at >= cap ? 0u : (cap - at < cnt ? cap - at : cnt);
-            uint32_t k = 0;
-            while (word && k < room) {
+            const uint32_t room = at >= cap ? 0u : (cap - at < cnt ? cap - at : cnt);
+            for (uint32_t k = 0; k < room; ++k) {
                 const uint32_t b = __ffs(word) - 1;
                 word &= word - 1;
-                const uint32_t vloc = w * 32 + b;
-                S.rv[at + k] = vloc;
-                S.rm[at + k] = gpend_take(&c.G.pend[(unsigned long long)c.grp * c.g.nv + c.v0 + vloc]);
-                ++k;
+                S.rv[at + k] = w * 32 + b;
             }
             S.lbits[w] = word;  // what did not fit stays for a later round
         }
         __syncthreads();
-        if (S.nr >= cap) break;
+        const bool full = S.nr >= cap;
         __syncthreads();
+        if (full) break;
     }
-    __syncthreads();
     const uint32_t nr = S.nr < cap ? S.nr : cap;
-    __syncthreads();
-    if (t == 0) S.nr = nr;
+    for (uint32_t k = t; k < nr; k += blockDim.x) {
+        const uint32_t v = c.v0 + S.rv[k];
+        S.rm[k] = gpend_take(&c.G.pend[(unsigned long long)c.grp * c.g.nv + v]);
+        S.rdeg[k] = c.g.rowptr[v + 1] - c.g.rowptr[v];
+    }
     __syncthreads();
     return nr;
 }
@@ -154,14 +203,20 @@ __device__ uint32_t gtake_round(GCtx& c, GShared& S, uint32_t cap) {
 // the round's vertices (the start of its batch window, Section 4.2's
 // Dijkstra order taken in batches as in Delta-stepping).
 __device__ void ground_min(GCtx& c, GShared& S, uint32_t nr) {
-    const uint32_t t = threadIdx.x, lane = lane_id(), wv = t / WAVE;
+    const uint32_t t = threadIdx.x, lane = lane_id(), wv = t / WAVE, nwv = blockDim.x / WAVE;
     if (t < (uint32_t)GW) S.lmin[t] = INF;
     __syncthreads();
     uint32_t m = INF;
-    for (uint32_t k = wv; k < nr; k += blockDim.x / WAVE) {
-        if (!((S.rm[k] >> lane) & 1ull)) continue;
-        const uint32_t d = fresh_load(&c.st[(unsigned long long)(c.v0 + S.rv[k]) * GW + lane]);
-        m = d < m ? d : m;
+    for (uint32_t k0 = wv; k0 < nr; k0 += nwv * BAT) {
+        uint32_t d[BAT];
+#pragma unroll
+        for (int i = 0; i < BAT; ++i) {
+            const uint32_t k = k0 + i * nwv;
+            const bool a = k < nr && ((S.rm[k] >> lane) & 1ull);
+            d[i] = a ? fresh_load(rowp(c.st, c.v0 + S.rv[k], lane)) : INF;
+        }
+#pragma unroll
+        for (int i = 0; i < BAT; ++i) m = d[i] < m ? d[i] : m;
     }
     if (m < INF) atomicMin(&S.lmin[lane], m);
     __syncthreads();
@@ -190,7 +245,7 @@ __device__ __forceinline__ uint32_t gblock_excl(GShared& S, uint32_t v, uint32_t
 // list on return.  Returns the round's edge total.
 __device__ uint32_t gnumber_edges(GShared& S, uint32_t nr) {
     constexpr uint32_t PERMAX = RCAP / 256;  // entries per thread with the smallest workgroup
-    const uint32_t per = RCAP / blockDim.x;
+    const uint32_t per = (RCAP + blockDim.x - 1) / blockDim.x;
     const uint32_t t = threadIdx.x;
     uint32_t x[PERMAX];
     uint32_t sum = 0;
@@ -226,43 +281,59 @@ __device__ __forceinline__ uint32_t gedge_vertex(const GShared& S, uint32_t nr, 
 // that expand now.  Lanes beyond the group's heuristic-2 window wait in the
 // pair's buffer for a later pass; lanes beyond their batch window go back to
 // the partition's pending set for a later round of this visit.
-__device__ void gfilter_sp(GCtx& c, GShared& S, uint32_t nr) {
-    const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE;
+__device__ void gfilter_sp(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr) {
+    const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE, nwv = blockDim.x / WAVE;
     const uint32_t lo = S.lmin[lane];
     const unsigned long long hi_ = (unsigned long long)lo + c.bwin;
     const uint32_t hi = hi_ >= INF ? INF : (uint32_t)hi_;
-    for (uint32_t k = wv; k < nr; k += blockDim.x / WAVE) {
-        const uint32_t vloc = S.rv[k];
-        const unsigned long long m = S.rm[k];
-        const uint32_t v = c.v0 + vloc;
-        bool act = (m >> lane) & 1ull;
-        const uint32_t d = act ? fresh_load(&c.st[(unsigned long long)v * GW + lane]) : INF;
-        const bool late = act && d > c.win;
-        const unsigned long long lm = wballot(late);
-        if (lm) {
-            const uint32_t dl = wave_min(late ? d : 0xffffffffu);
-            if (lane == 0) {
-                dev_or(&c.G.pend[(unsigned long long)c.grp * c.g.nv + v], lm);
-                gkeep(c, vloc, dl);
+    uint32_t n_push = 0, n_vt = 0;
+    for (uint32_t k0 = wv; k0 < nr; k0 += nwv * BAT) {
+        uint32_t d[BAT];
+#pragma unroll
+        for (int i = 0; i < BAT; ++i) {
+            const uint32_t k = k0 + i * nwv;
+            const bool a = k < nr && ((S.rm[k] >> lane) & 1ull);
+            d[i] = a ? fresh_load(rowp(c.st, c.v0 + S.rv[k], lane)) : INF;
+        }
+#pragma unroll
+        for (int i = 0; i < BAT; ++i) {
+            const uint32_t k = k0 + i * nwv;
+            if (k >= nr) break;
+            const uint32_t vloc = S.rv[k];
+            const uint32_t v = c.v0 + vloc;
+            bool act = (S.rm[k] >> lane) & 1ull;
+            const bool late = act && d[i] > c.win;
+            const unsigned long long lm = wballot(late);
+            if (lm) {
+                const uint32_t dl = wave_min(late ? d[i] : 0xffffffffu);
+                if (lane == 0) {
+                    dev_or(&c.G.pend[(unsigned long long)c.grp * c.g.nv + v], lm);
+                    gkeep(c, vloc, dl);
+                }
+                act = act && !late;
             }
-            act = act && !late;
-        }
-        const bool later = act && d >= hi;
-        const unsigned long long lr = wballot(later);
-        if (lr && lane == 0) {
-            const unsigned long long old = dev_or(&c.G.pend[(unsigned long long)c.grp * c.g.nv + v], lr);
-            if (!old) atomicOr(&S.lbits[vloc >> 5], 1u << (vloc & 31));
-        }
-        act = act && !later;
-        const unsigned long long am = wballot(act);
-        c.c_vpush += act ? 1u : 0u;
-        if (lane == 0) {
-            const uint32_t deg = c.g.rowptr[v + 1] - c.g.rowptr[v];
-            S.rm[k] = am;
-            S.rnt[k] = am ? deg : 0u;
-            c.c_vtask += am ? 1u : 0u;
+            const bool later = act && d[i] >= hi;
+            const unsigned long long lr = wballot(later);
+            if (lr && lane == 0) {
+                // back to the partition's pending set; the fence below orders the
+                // mask before the next round takes it
+                dev_or(&c.G.pend[(unsigned long long)c.grp * c.g.nv + v], lr);
+                atomicOr(&S.lbits[vloc >> 5], 1u << (vloc & 31));
+            }
+            act = act && !later;
+            const unsigned long long am = wballot(act);
+            SH.sd[k][lane] = d[i];
+            n_push += (uint32_t)__popcll(am);
+            n_vt += am ? 1u : 0u;
+            if (lane == 0) {
+                S.rm[k] = am;
+                S.rnt[k] = am ? S.rdeg[k] : 0u;
+            }
         }
     }
+    gcount(S, K_VPUSH, n_push);
+    gcount(S, K_VTASK, n_vt);
+    mem_release();
     __syncthreads();
 }
 
@@ -270,43 +341,59 @@ __device__ void gfilter_sp(GCtx& c, GShared& S, uint32_t nr) {
 // lanes' residuals, push those at or above their threshold into p and keep
 // the share each out-edge receives (Section 4.1's push).
 __device__ void gfilter_ppr(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr) {
-    const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE;
-    for (uint32_t k = wv; k < nr; k += blockDim.x / WAVE) {
-        const uint32_t vloc = S.rv[k];
-        const unsigned long long m = S.rm[k];
-        const uint32_t v = c.v0 + vloc;
-        const uint32_t deg = c.g.rowptr[v + 1] - c.g.rowptr[v];
-        const bool mine = (m >> lane) & 1ull;
-        const float thr = c.mode ? c.eps * (float)deg : c.eps;
-        float rv = 0.f;
-        if (mine) rv = __hip_atomic_exchange((float*)&c.st[(unsigned long long)v * GW + lane], 0.f, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        const bool push = mine && ppr_active(rv, thr);
-        bool back = false;
-        if (mine && !push && rv != 0.f) {
-            // below the threshold after all: give the residual back (it may cross with what arrived)
-            const float old = __hip_atomic_fetch_add((float*)&c.st[(unsigned long long)v * GW + lane], rv,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            back = !ppr_active(old, thr) && ppr_active(old + rv, thr);
+    const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE, nwv = blockDim.x / WAVE;
+    uint32_t n_push = 0, n_vt = 0, n_act = 0;
+    for (uint32_t k0 = wv; k0 < nr; k0 += nwv * BAT) {
+        float rx[BAT];
+#pragma unroll
+        for (int i = 0; i < BAT; ++i) {
+            const uint32_t k = k0 + i * nwv;
+            const bool mine = k < nr && ((S.rm[k] >> lane) & 1ull);
+            rx[i] = mine ? __hip_atomic_exchange(rowf((float*)c.st, c.v0 + S.rv[k], lane), 0.f, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                         : 0.f;
         }
-        const unsigned long long bk = wballot(back);
-        if (bk && lane == 0) gmark(c, S, v, bk, 0u);
-        const unsigned long long pm = wballot(push);
-        c.c_vpush += push ? 1u : 0u;
-        c.c_vpush_ppr += push ? 1u : 0u;
-        float share = 0.f;
-        if (push) {
-            __hip_atomic_fetch_add(&c.pp[(unsigned long long)v * GW + lane], c.alpha * rv, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            if (deg) share = (1.f - c.alpha) * rv / (float)deg;
-        }
-        SH.share[k][lane] = share;
-        if (lane == 0) {
-            S.rm[k] = deg ? pm : 0ull;
-            S.rnt[k] = pm ? deg : 0u;
-            c.c_vtask += pm ? 1u : 0u;
+#pragma unroll
+        for (int i = 0; i < BAT; ++i) {
+            const uint32_t k = k0 + i * nwv;
+            if (k >= nr) break;
+            const uint32_t v = c.v0 + S.rv[k];
+            const uint32_t deg = S.rdeg[k];
+            const bool mine = (S.rm[k] >> lane) & 1ull;
+            const float rv = rx[i];
+            const float thr = c.mode ? c.eps * (float)deg : c.eps;
+            const bool push = mine && ppr_active(rv, thr);
+            bool back = false;
+            if (mine && !push && rv != 0.f) {
+                // below the threshold after all: give the residual back (it may cross with what arrived)
+                const float old = __hip_atomic_fetch_add(rowf((float*)c.st, v, lane), rv, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                back = !ppr_active(old, thr) && ppr_active(old + rv, thr);
+            }
+            const unsigned long long bk = wballot(back);
+            bool newact = false;
+            if (bk && lane == 0) newact = gmark(c, S, v, bk, 0u);
+            n_act += newact ? 1u : 0u;
+            const unsigned long long pm = wballot(push);
+            n_push += (uint32_t)__popcll(pm);
+            n_vt += pm ? 1u : 0u;
+            float share = 0.f;
+            if (push) {
+                __hip_atomic_fetch_add(rowf(c.pp, v, lane), c.alpha * rv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (deg) share = (1.f - c.alpha) * rv / (float)deg;
+            }
+            SH.share[k][lane] = share;
+            if (lane == 0) {
+                S.rm[k] = deg ? pm : 0ull;
+                S.rnt[k] = pm ? deg : 0u;
+            }
         }
     }
+    n_act = __shfl(n_act, 0);
+    gcount(S, K_ACT, n_act);
+    gcount(S, K_VPUSH, n_push);
+    gcount(S, K_VPUSH_PPR, n_push);
+    gcount(S, K_VTASK, n_vt);
     __syncthreads();
 }
 
@@ -323,11 +410,21 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
     const uint32_t lane = lane_id();
     const bool ppr = c.qt == Q_PPR;
     const uint32_t ntask = (nedge + GW - 1) / GW;
+    // wave-uniform counts of this wave's tasks
+    uint32_t n_edges = 0, n_intra = 0, n_imp = 0, n_act = 0, n_tasks = 0;
+    // the mark begun in the previous step (one per lane 0..UNR-1): target,
+    // priority and the mask's old value, finished while the next step's
+    // memory operations are in flight
+    bool pm_on = false;
+    uint32_t pm_u = 0, pm_val = 0;
+    unsigned long long pm_old = 0;
+    const __amdgpu_buffer_rsrc_t rsrc = row_rsrc(c.st, c.g.nv);
     for (;;) {
         uint32_t task = 0;
         if (lane == 0) task = atomicAdd(&S.next, 1u);
         task = __shfl(task, 0);
         if (task >= ntask) break;
+        ++n_tasks;
         const uint32_t f = task * GW + lane;
         const uint32_t cnt = nedge - task * GW < (uint32_t)GW ? nedge - task * GW : (uint32_t)GW;
         // edge `lane` of this task: its round vertex, target and weight
@@ -341,17 +438,16 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
             if (!ppr && WB != 0 && c.qt != Q_BFS) myw = edge_w<WB>(c.g.w, e);
             if (ppr) mythr = (float)(c.g.rowptr[myu + 1] - c.g.rowptr[myu]);  // degree, scaled per lane below
         }
+        const bool my_intra = myu - c.v0 < c.nvp;
         uint32_t kprev = 0xffffffffu, dprev = INF;
         float sprev = 0.f;
         bool aprev = false;
-        unsigned long long lane_edges = 0;
         for (uint32_t j0 = 0; j0 < cnt; j0 += UNR) {
-            uint32_t u[UNR];
-            bool act[UNR];
-            bool hit[UNR];
-            uint32_t val[UNR];
-            uint32_t dsrc[UNR];
-            float shr[UNR];
+            uint32_t u[UNR];   // targets of edges j0 .. j0 + UNR - 1
+            uint32_t x[UNR];   // SSSP/BFS: distance through the edge; PPR: the pushed share (float bits)
+            uint32_t y[UNR];   // SSSP/BFS: the target's value, then its old value at the atomic min (0: none);
+                               // PPR: the target's residual before the push (float bits)
+            uint32_t actm = 0; // bit j: this lane relaxes / pushes along edge j0 + j
 #pragma unroll
             for (int j = 0; j < UNR; ++j) {
                 const bool ok = j0 + j < cnt;
@@ -362,67 +458,81 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
                     const unsigned long long m = S.rm[kj];
                     aprev = (m >> lane) & 1ull;
                     if (ppr) sprev = SH.share[kj][lane];
-                    else dprev = aprev ? fresh_load(&c.st[(unsigned long long)(c.v0 + S.rv[kj]) * GW + lane]) : INF;
+                    else dprev = aprev ? SH.sd[kj][lane] : INF;
                 }
-                act[j] = ok && aprev;
-                dsrc[j] = dprev;
-                shr[j] = sprev;
-                c.c_intra += (act[j] && u[j] - c.v0 < c.nvp) ? 1u : 0u;
+                actm |= (ok && aprev) ? (1u << j) : 0u;
+                if (ppr) {
+                    x[j] = __float_as_uint(sprev);
+                } else {
+                    const uint32_t w = __shfl(myw, (int)(j0 + j) & (GW - 1));
+                    const unsigned long long sum = (unsigned long long)dprev + w;
+                    x[j] = sum >= INF ? INF - 1 : (uint32_t)sum;
+                }
             }
             if (ppr) {
-                float thu[UNR], old[UNR];
-#pragma unroll
-                for (int j = 0; j < UNR; ++j) {
-                    const float du = __shfl(mythr, (int)(j0 + j) & (GW - 1));
-                    thu[j] = c.mode ? c.eps * du : c.eps;
-                }
 #pragma unroll
                 for (int j = 0; j < UNR; ++j)
-                    old[j] = act[j] ? __hip_atomic_fetch_add((float*)&c.st[(unsigned long long)u[j] * GW + lane], shr[j],
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                    : 0.f;
-#pragma unroll
-                for (int j = 0; j < UNR; ++j) {
-                    const float nr_ = old[j] + shr[j];
-                    hit[j] = act[j] && !ppr_active(old[j], thu[j]) && ppr_active(nr_, thu[j]);
-                    val[j] = ~__float_as_uint(nr_);
-                }
+                    y[j] = ((actm >> j) & 1u) ? __float_as_uint(__hip_atomic_fetch_add(
+                                                    rowf((float*)c.st, u[j], lane), __uint_as_float(x[j]),
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                                              : 0u;
+                if (pm_on) { pm_on = false; n_act += gmark_end(c, S, pm_u, pm_old, pm_val) ? 1u : 0u; }
             } else {
-                uint32_t nd[UNR], cur[UNR];
 #pragma unroll
-                for (int j = 0; j < UNR; ++j) {
-                    const uint32_t w = __shfl(myw, (int)(j0 + j) & (GW - 1));
-                    const unsigned long long sum = (unsigned long long)dsrc[j] + w;
-                    nd[j] = sum >= INF ? INF - 1 : (uint32_t)sum;
-                }
+                for (int j = 0; j < UNR; ++j)
+                    y[j] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, ((actm >> j) & 1u) ? row_off(u[j], lane) : ROW_NONE,
+                                                                0, 0);
+                if (pm_on) { pm_on = false; n_act += gmark_end(c, S, pm_u, pm_old, pm_val) ? 1u : 0u; }
 #pragma unroll
-                for (int j = 0; j < UNR; ++j) cur[j] = act[j] ? c.st[(unsigned long long)u[j] * GW + lane] : 0u;
-#pragma unroll
-                for (int j = 0; j < UNR; ++j) {
-                    bool imp = act[j] && nd[j] < cur[j];
-                    if (imp) imp = nd[j] < dev_min(&c.st[(unsigned long long)u[j] * GW + lane], nd[j]);
-                    c.c_improved += imp ? 1u : 0u;
-                    hit[j] = imp;
-                    val[j] = nd[j];
-                }
+                for (int j = 0; j < UNR; ++j)
+                    y[j] = (((actm >> j) & 1u) && x[j] < y[j]) ? dev_min(rowp(c.st, u[j], lane), x[j]) : 0u;
             }
             // lane j marks the target of edge j0 + j for every lane that hit it
             unsigned long long mine_bits = 0;
             uint32_t mine_val = 0, mine_u = 0;
 #pragma unroll
             for (int j = 0; j < UNR; ++j) {
-                const unsigned long long bm = wballot(hit[j]);
+                const bool act = (actm >> j) & 1u;
+                bool hit;
+                uint32_t val;
+                if (ppr) {
+                    const float du = __shfl(mythr, (int)(j0 + j) & (GW - 1));
+                    const float thu = c.mode ? c.eps * du : c.eps;
+                    const float old = __uint_as_float(y[j]);
+                    const float nr_ = old + __uint_as_float(x[j]);
+                    hit = act && !ppr_active(old, thu) && ppr_active(nr_, thu);
+                    val = ~__float_as_uint(nr_);
+                } else {
+                    hit = x[j] < y[j];  // y[j] = 0 where no atomic was made
+                    val = x[j];
+                }
+                const unsigned long long bm = wballot(hit);
                 const uint32_t first = bm ? (uint32_t)(__ffsll(bm) - 1) : 0u;
-                const uint32_t vj = __shfl(val[j], (int)first);
+                const uint32_t vj = __shfl(val, (int)first);
                 if (lane == (uint32_t)j) { mine_bits = bm; mine_val = vj; mine_u = u[j]; }
-                c.c_edges += act[j] ? 1u : 0u;
-                if (ppr) c.c_edges_ppr += act[j] ? 1u : 0u;
-                lane_edges += __popcll(wballot(act[j]));
+                const uint32_t na = (uint32_t)__popcll(wballot(act));
+                n_edges += na;
+                n_intra += __shfl(my_intra ? 1u : 0u, (int)(j0 + j) & (GW - 1)) * na;
+                n_imp += ppr ? 0u : (uint32_t)__popcll(bm);
             }
-            if (mine_bits) gmark(c, S, mine_u, mine_bits, mine_val);
+            if (mine_bits) {
+                pm_old = gmark_begin(c, mine_u, mine_bits);
+                pm_u = mine_u;
+                pm_val = mine_val;
+                pm_on = true;
+            }
         }
-        if (lane == 0) atomicAdd(&S.edges, lane_edges);
     }
+    if (pm_on) n_act += gmark_end(c, S, pm_u, pm_old, pm_val) ? 1u : 0u;
+    // n_act counted per lane (lanes 0..UNR-1 mark); the rest are wave-uniform
+    for (int o = 32; o; o >>= 1) n_act += __shfl_xor(n_act, o);
+    gcount(S, K_EDGES, n_edges);
+    if (ppr) gcount(S, K_EDGES_PPR, n_edges);
+    gcount(S, K_INTRA, n_intra);
+    gcount(S, K_IMPROVED, n_imp);
+    gcount(S, K_ACT, n_act);
+    gcount(S, K_TASKS, n_tasks);
+    if (lane == 0 && n_edges) atomicAdd(&S.edges, (unsigned long long)n_edges);
 }
 
 // One visit of the (partition, group) pair of S.it.
@@ -447,6 +557,15 @@ __device__ void gvisit(GCtx& c, GShared& S, GCtxShare& SH, const PassCfg& cfg) {
         const unsigned long long w = (unsigned long long)c.G.gmin[c.grp] + d;
         c.win = d == 0 ? INF : (w >= INF ? INF : (uint32_t)w);
     }
+    // time of the visit's phases, read by thread 0 between barriers (10 ns ticks)
+    if (t == 0) S.tk = wall_clock64();
+    auto phase = [&](int k) {
+        if (t == 0) {
+            const unsigned long long now = wall_clock64();
+            S.cnt[k] += now - S.tk;
+            S.tk = now;
+        }
+    };
     // the pair's pending vertices: global bitmap -> LDS
     const uint32_t nw = (c.nvp + 31) / 32;
     for (uint32_t w = t; w < nw; w += blockDim.x) {
@@ -468,6 +587,7 @@ __device__ void gvisit(GCtx& c, GShared& S, GCtxShare& SH, const PassCfg& cfg) {
     }
     if (t == 0) S.edges = 0;
     __syncthreads();
+    phase(K_T_GATHER);
     unsigned long long budget = 0;
     if (cfg.mu > 0.f) {
         const uint32_t np_items = c.B.pn[c.P];
@@ -477,19 +597,22 @@ __device__ void gvisit(GCtx& c, GShared& S, GCtxShare& SH, const PassCfg& cfg) {
     }
     const bool ppr = c.qt == Q_PPR;
     for (;;) {
-        const uint32_t nr = gtake_round(c, S, ppr ? (uint32_t)PCAP : (uint32_t)RCAP);
+        const uint32_t nr = gtake_round(c, S, (uint32_t)RCAP);
+        phase(K_T_TAKE);
         if (nr == 0) break;
         if (ppr) {
             gfilter_ppr(c, S, SH, nr);
         } else {
             ground_min(c, S, nr);
-            gfilter_sp(c, S, nr);
+            gfilter_sp(c, S, SH, nr);
         }
         const uint32_t nedge = gnumber_edges(S, nr);
-        if (t == 0) S.next = 0;
+        if (t == 0) { S.next = 0; S.cnt[K_ROUNDS] += 1; }
         __syncthreads();
+        phase(K_T_FILTER);
         gtasks<WB>(c, S, SH, nr, nedge);
         __syncthreads();
+        phase(K_T_TASKS);
         if (budget && S.edges >= budget) break;
     }
     __syncthreads();
@@ -509,7 +632,7 @@ __device__ void gvisit(GCtx& c, GShared& S, GCtxShare& SH, const PassCfg& cfg) {
                 val = 0xffffffffu;
                 for (unsigned long long mm = m; mm; mm &= mm - 1) {
                     const uint32_t l = __ffsll(mm) - 1;
-                    const uint32_t x = fresh_load(&c.st[(unsigned long long)u * GW + l]);
+                    const uint32_t x = fresh_load(rowp(c.st, u, l));
                     val = x < val ? x : val;
                 }
             }
@@ -518,6 +641,7 @@ __device__ void gvisit(GCtx& c, GShared& S, GCtxShare& SH, const PassCfg& cfg) {
         S.lbits[w] = 0u;
     }
     __syncthreads();
+    phase(K_T_YIELD);
 }
 
 template <int WB>
@@ -528,8 +652,8 @@ __global__ __launch_bounds__(GNTMAX) void k_gprocess(GraphDev g, GroupDev G, Buf
     c.g = g;
     c.G = G;
     c.B = B;
-    c.c_edges = c.c_intra = c.c_improved = c.c_vpush = c.c_act = c.c_edges_ppr = c.c_vpush_ppr = c.c_vtask = 0;
     const uint32_t t = threadIdx.x;
+    if (t < (uint32_t)NCNT) S.cnt[t] = 0;
     const uint32_t xcd = blockIdx.x % NXCD;
     c.pass = B.ctl->pass;
     unsigned long long items = 0;
@@ -559,17 +683,16 @@ __global__ __launch_bounds__(GNTMAX) void k_gprocess(GraphDev g, GroupDev G, Buf
         gvisit<WB>(c, S, SH, cfg);
     }
     // counters
-    constexpr int NC = 8;
-    unsigned long long v[NC] = {c.c_edges, c.c_intra, c.c_improved, c.c_vpush, c.c_act, c.c_edges_ppr, c.c_vpush_ppr,
-                                c.c_vtask};
-    unsigned long long* dst[NC] = {&B.ctl->c_edges, &B.ctl->c_intra, &B.ctl->c_improved, &B.ctl->c_vpush,
-                                   &B.ctl->c_act, &B.ctl->c_edges_ppr, &B.ctl->c_vpush_ppr, &B.ctl->c_vtask};
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        unsigned long long x = v[k];
-#pragma unroll
-        for (int o = 32; o; o >>= 1) x += __shfl_xor(x, o);
-        if ((t & 63) == 0 && x) dev_add(dst[k], x);
+    __syncthreads();
+    if (t < (uint32_t)NCNT && S.cnt[t]) {
+        Ctl* k = B.ctl;
+        unsigned long long* d = t == K_EDGES ? &k->c_edges : t == K_INTRA ? &k->c_intra
+                              : t == K_IMPROVED ? &k->c_improved : t == K_VPUSH ? &k->c_vpush
+                              : t == K_ACT ? &k->c_act : t == K_EDGES_PPR ? &k->c_edges_ppr
+                              : t == K_VPUSH_PPR ? &k->c_vpush_ppr : t == K_VTASK ? &k->c_vtask
+                              : t == K_ROUNDS ? &k->c_rounds : t == K_TASKS ? &k->c_tasks
+                              : &k->c_tphase[t - K_T_GATHER];
+        dev_add(d, S.cnt[t]);
     }
     if (t == 0 && items) dev_add(&B.ctl->c_items, items);
 }

@@ -954,6 +954,9 @@ static int run_wave_group(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_
     if (c->vpmax > 16384)
         return fail(FORK_E_INVALID, "the grouped engine needs partitions of at most 16384 vertices (this graph's "
                     "largest has %u; load it with partition_vertices <= 16384)", c->vpmax);
+    if (c->nv >= (1u << 24))  // its kernels address a group's state rows with 32-bit byte offsets
+        return fail(FORK_E_INVALID, "the grouped engine takes graphs of fewer than 16,777,216 vertices (this one "
+                    "has %u)", c->nv);
     int rc = ensure_wave(c, nq, words, cfg.kmax);
     if (rc) return rc;
     if ((uint64_t)ng * ((cfg.kmax + fk::NXCD - 1) / fk::NXCD) > (uint64_t)c->item_cap)
@@ -1109,6 +1112,9 @@ static int run_wave_group(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_
     st.ppr_vertex_pushes += h.c_vpush_ppr;
     st.activations += h.c_act;
     st.expansions += h.c_vtask;
+    st.rounds += h.c_rounds;
+    st.edge_tasks += h.c_tasks;
+    for (int k = 0; k < 5; ++k) st.visit_ns[k] += 10ull * h.c_tphase[k];
     st.waves += 1;
     c->res_first = q0;
     c->res_n = nq;

@@ -17,6 +17,7 @@
 #include <stddef.h>
 #include <string.h>
 #include <stdio.h>
+#include <time.h>
 #include <math.h>
 #include <cmath>
 #include <algorithm>
@@ -140,6 +141,22 @@ inline uint32_t mbcnt_hi(uint32_t m, uint32_t acc) {
 #define __builtin_amdgcn_readfirstlane(v) ((uint32_t)simt::wave_op(4, (uint64_t)(uint32_t)(v), 0))
 #define __builtin_amdgcn_fence(o, s) __atomic_thread_fence(__ATOMIC_SEQ_CST)
 #define __builtin_amdgcn_wave_barrier() simt::wave_barrier()
+inline unsigned long long wall_clock64() {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return ((unsigned long long)ts.tv_sec * 1000000000ull + (unsigned long long)ts.tv_nsec) / 10ull;
+}
+// raw buffer (no stride): a dword at a byte offset past num_records reads 0
+struct simt_buffer_rsrc { char* base; uint32_t num; };
+typedef simt_buffer_rsrc __amdgpu_buffer_rsrc_t;
+inline simt_buffer_rsrc __builtin_amdgcn_make_buffer_rsrc(void* p, short, int num, int) {
+    return simt_buffer_rsrc{(char*)p, (uint32_t)num};
+}
+inline uint32_t __builtin_amdgcn_raw_buffer_load_b32(simt_buffer_rsrc r, uint32_t off, uint32_t soff, int) {
+    const uint64_t o = (uint64_t)off + soff;
+    if (o + 4 > r.num) return 0u;
+    return __atomic_load_n((uint32_t*)(r.base + o), __ATOMIC_RELAXED);
+}
 
 inline void __syncthreads() { simt::syncthreads(); }
 inline void __threadfence() { __atomic_thread_fence(__ATOMIC_SEQ_CST); }
