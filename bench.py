@@ -320,6 +320,12 @@ def main():
     prof = measured_traffic(args.workload, kernel) if not (args.scale or args.queries or args.l1_target) else None
     launches = max(1, tot["process_launches"])
     avg_ms = tot["process_ms"] / launches
+    # HBM bytes per launch: the profiled traffic over algorithmic bytes (per run; the number of passes
+    # varies between runs) times this run's algorithmic bytes per launch, else the profiled per-launch figure
+    traffic = None
+    if prof:
+        traffic = (prof["traffic_over_algorithmic"] * abytes / launches if prof.get("traffic_over_algorithmic")
+                   else prof["traffic_bytes_per_launch"])
     achieved = (abytes / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     line = {
         "metric": METRIC,
@@ -341,11 +347,12 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": prof["traffic_bytes_per_launch"] if prof else None,
+                     "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "traffic_over_algorithmic": (prof["traffic_bytes_per_launch"] / (abytes / launches))
-                     if prof else None,
+                     "traffic_over_algorithmic": traffic / (abytes / launches) if traffic else None,
                      "profiled_avg_launch_ms": prof.get("avg_launch_ms") if prof else None,
+                     "profiled_kernel_ms_per_step": prof.get("kernel_ms_total") if prof else None,
+                     "kernel_ms_per_step": tot["process_ms"] / args.steps,
                      "l2_hit_rate": prof.get("l2_hit_rate") if prof else None,
                      "wave_wait_share": prof.get("wave_wait_share") if prof else None,
                      "achievable_copy_gbs": prof.get("copy_gbs") if prof else None,

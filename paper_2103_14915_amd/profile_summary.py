@@ -10,7 +10,11 @@ each scaled by the factor that makes the same counter read the true byte count
 of a plain device-to-device copy of known size.  Optional passes add the L2
 hit rate (TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)), the share of wave
 cycles spent waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES), and the copy's own
-achieved bandwidth (the calibration run's JSON line).  The summary records
+achieved bandwidth (the calibration run's JSON line).  Given the bench output
+of the two counter runs (--fetch-log, --write-log), the traffic is also put
+against the algorithmic bytes those runs report, per run: the number of passes
+(launches) of a run can differ from run to run, the work per step does not.
+The summary records
 the hash of the kernel's source so that bench.py reports these figures only
 while the kernel is unchanged.
 """
@@ -50,6 +54,15 @@ def per_kernel(path, counter=None):
     return agg
 
 
+def _bench_alg_bytes(path):
+    """Algorithmic bytes of the profiled step from a bench run's JSON line."""
+    for ln in open(path):
+        ln = ln.strip()
+        if ln.startswith("{") and '"roofline"' in ln:
+            return json.loads(ln)["roofline"].get("algorithmic_bytes_per_step")
+    return None
+
+
 def pick(agg, key):
     for k, v in agg.items():
         if key in k:
@@ -67,6 +80,8 @@ def main(argv=None):
     ap.add_argument("--copy-bytes", type=int, default=0)
     ap.add_argument("--copy-kernel", default="copyBuffer")
     ap.add_argument("--copy-log", help="stdout of the copy calibration run (its JSON line has copy_gbs)")
+    ap.add_argument("--fetch-log", help="stdout of the FETCH_SIZE run (its bench line gives the step's algorithmic bytes)")
+    ap.add_argument("--write-log", help="stdout of the WRITE_SIZE run")
     ap.add_argument("--tcc", help="counter CSV with TCC_HIT_sum and TCC_MISS_sum")
     ap.add_argument("--sq", help="counter CSV with SQ_WAIT_ANY and SQ_WAVE_CYCLES")
     ap.add_argument("--kernel", default="k_process")
@@ -85,6 +100,9 @@ def main(argv=None):
     if kstat:
         out["avg_launch_ms"] = float(kstat["AverageNs"]) / 1e6
         out["calls"] = int(kstat["Calls"])
+        # the profiled command runs one step: the kernel's time per step (the number of launches,
+        # and so the average per launch, varies between runs; the time per step does not)
+        out["kernel_ms_total"] = float(kstat["TotalDurationNs"]) / 1e6
     if a.fetch and a.write and a.copy_fetch and a.copy_write and a.copy_bytes:
         _, (cn, cf) = pick(per_kernel(a.copy_fetch, "FETCH_SIZE"), a.copy_kernel)
         _, (cn2, cw) = pick(per_kernel(a.copy_write, "WRITE_SIZE"), a.copy_kernel)
@@ -100,6 +118,14 @@ def main(argv=None):
                       f"{w_scale:.3f}; scales from a {a.copy_bytes} B device copy): "
                       f"fetch {fetch_b / 1e6:.1f} MB, write {write_b / 1e6:.1f} MB, "
                       f"total {(fetch_b + write_b) / 1e6:.1f} MB over {n1} launches."]
+        if a.fetch_log and a.write_log:
+            fa, wa = _bench_alg_bytes(a.fetch_log), _bench_alg_bytes(a.write_log)
+            if fa and wa:
+                fr, wr = fetch_b * n1 / fa, write_b * n2 / wa
+                out.update({"fetch_over_algorithmic": fr, "write_over_algorithmic": wr,
+                            "traffic_over_algorithmic": fr + wr})
+                lines += ["", f"Against the algorithmic bytes of the same runs ({fa / 1e9:.1f} GB and {wa / 1e9:.1f} GB "
+                              f"per step): fetch {fr:.2f}x, write {wr:.2f}x, total {fr + wr:.2f}x."]
     if a.tcc:
         _, (_, hit) = pick(per_kernel(a.tcc, "TCC_HIT_sum"), a.kernel)
         _, (_, miss) = pick(per_kernel(a.tcc, "TCC_MISS_sum"), a.kernel)

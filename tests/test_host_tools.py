@@ -97,12 +97,19 @@ def test_profile_summary_scales_counters_by_copy_calibration(tmp_path):
                               ["fk::k_select(x)", "TCC_HIT_sum", 1.0], ["fk::k_select(x)", "TCC_MISS_sum", 99.0]] * 2)
     _write_csv(sq, pmc_hdr, [["fk::k_process<0>(x)", "SQ_WAIT_ANY", 60.0], ["fk::k_process<0>(x)", "SQ_WAVE_CYCLES", 80.0]])
     clog.write_text("noise\n" + json.dumps({"copy_calibration_bytes": 1, "copy_gbs": 4321.0}) + "\n")
+    # the counter runs' bench lines: their steps' algorithmic bytes
+    flog, wlog = tmp_path / "f.out", tmp_path / "w.out"
+    flog.write_text(json.dumps({"roofline": {"algorithmic_bytes_per_step": 4 * 1000.0 * 1024 * 2.0}}) + "\n")
+    wlog.write_text("x\n" + json.dumps({"roofline": {"algorithmic_bytes_per_step": 8 * 500.0 * 1024}}) + "\n")
     out = tmp_path / "k.md"
     ps.main(["--stats", str(stats), "--fetch", str(fetch), "--write", str(write), "--copy-fetch", str(cf),
              "--copy-write", str(cw), "--copy-bytes", str(copy_bytes), "--kernel", "k_process",
-             "--tcc", str(tcc), "--sq", str(sq), "--copy-log", str(clog),
-             "--command", "cmd", "--out", str(out)])
+             "--tcc", str(tcc), "--sq", str(sq), "--copy-log", str(clog), "--fetch-log", str(flog),
+             "--write-log", str(wlog), "--command", "cmd", "--out", str(out)])
     blob = json.loads(out.read_text().split("```json", 1)[1].split("```", 1)[0])
+    # 4 launches of 2 MiB fetched against 8 MiB algorithmic; 4 x 0.5 MiB written against 4 MiB
+    assert blob["fetch_over_algorithmic"] == pytest.approx(1.0) and blob["write_over_algorithmic"] == pytest.approx(0.5)
+    assert blob["traffic_over_algorithmic"] == pytest.approx(1.5) and blob["kernel_ms_total"] == pytest.approx(8.0)
     assert blob["l2_hit_rate"] == pytest.approx(0.75)  # the kernel's own counters, not k_select's
     assert blob["wave_wait_share"] == pytest.approx(0.75) and blob["copy_gbs"] == 4321.0
     assert blob["fetch_scale"] == pytest.approx(2.0) and blob["write_scale"] == pytest.approx(1.0)
