@@ -150,7 +150,8 @@ def compare_learned(fg, args, run_kw, nq, rule_value):
     kinds = fg.types
     rule_dig = [fg.digest(i) for i in range(nq)]
     kw = dict(run_kw, scheduler="learned", mlp_weights=theta)
-    fg.run(**kw)  # warm-up
+    for _ in range(min(args.warmup, 1)):  # the rule run's first step paid the one-time allocations
+        fg.run(**kw)
     torch.cuda.synchronize()
     steps = max(1, min(args.steps, args.learned_steps))
     t0 = time.perf_counter()
@@ -171,9 +172,11 @@ def compare_learned(fg, args, run_kw, nq, rule_value):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat20_sssp_ppr2048")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 1 on the scale-23 batch, whose step takes over a minute; else 3)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default: 0 on the scale-23 batch; "
+                    "else 1)")
+    ap.add_argument("--workload", default="rmat23_sssp_ppr65536")
     ap.add_argument("--scheduler", default="priority")
     ap.add_argument("--engine", default="", choices=["", "buffered", "grouped"],
                     help="buffered: one work item per (partition, query); grouped: per (partition, 64 queries); "
@@ -205,7 +208,8 @@ def main():
     ap.add_argument("--compare-learned", default="auto", help="MLP weights (.npy): also time the learned scheduler "
                     "on the same workload and report the speedup over the rule-based one ('auto': the weights "
                     "shipped with the package for this graph family; 'none': skip)")
-    ap.add_argument("--learned-steps", type=int, default=5, help="timed steps of the learned scheduler")
+    ap.add_argument("--learned-steps", type=int, default=None,
+                    help="timed steps of the learned scheduler (default: as --steps, at most 5)")
     ap.add_argument("--group-threads", type=int, default=0, help="grouped engine: workgroup size (256/512/1024)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (HBM counter calibration)")
@@ -226,6 +230,13 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 6,
                           "copy_gbs": 2.0 * n * 4 / (ms * 1e-3) / 1e9}), flush=True)
         return
+    big = args.workload == "rmat23_sssp_ppr65536" and not (args.queries or args.scale)
+    if args.steps is None:
+        args.steps = 1 if big else 3
+    if args.warmup is None:
+        args.warmup = 0 if big else 1
+    if args.learned_steps is None:
+        args.learned_steps = min(args.steps, 5)
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1 "
                                    "(the queries would shard across GPUs with no exchange during a run)"}))
@@ -255,7 +266,11 @@ def main():
                               use_cache=not args.retune, sample=args.tune_sample) \
             if args.tune else autotune.cached(g, queries)
         if tuned:
-            params, source = dict(tuned), ("tuned" if args.tune else "cache")
+            tuned = dict(tuned)
+            subset = tuned.pop("_tuned_on", None)
+            params, source = tuned, ("tuned" if args.tune else "cache")
+            if subset:
+                source += f" (tuned on the query subset {subset} of this graph)"
             print(f"[bench] tuned params ({source}, {time.perf_counter() - t_tune:.1f}s): {params}",
                   file=sys.stderr, flush=True)
     for k, v in (("partition_vertices", args.partition_vertices), ("items_per_pass", args.items_per_pass),
@@ -299,13 +314,20 @@ def main():
     kind = kinds[0] if len(kinds) == 1 else "mixed"
     run_kw = dict(autotune.run_kwargs(params), scheduler=args.scheduler, parts_per_pass=args.parts_per_pass,
                   stream=stream, profile=1, window_mode=args.window_mode)
+    # device buffers of the run's waves, allocated before timing (fork_prepare): setup, like loading the graph
+    t_prep = time.perf_counter()
+    fg.prepare(**run_kw)
+    t_prep = time.perf_counter() - t_prep
     for _ in range(args.warmup):
         fg.run(**run_kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tot = None
+    t_call = 0.0
     for _ in range(args.steps):
+        tc = time.perf_counter()
         fg.run(**run_kw)
+        t_call += time.perf_counter() - tc
         st = fg.stats()
         tot = st if tot is None else {k: tot[k] + st[k] if isinstance(st[k], (int, float))
                                       else [a + b for a, b in zip(tot[k], st[k])] if isinstance(st[k], list)
@@ -361,6 +383,9 @@ def main():
                      "algorithmic_bytes_per_launch": abytes / launches,
                      "algorithmic_bytes_per_step": abytes / args.steps},
         "detail": {"graph_gen_s": t_gen, "vertex_order_s": t_order, "graph_load_s": t_load,
+                   "prepare_s": t_prep,
+                   "run_wall_ms_per_step": tot["wall_ms"] / args.steps, "setup_ms_per_step": tot["setup_ms"] / args.steps,
+                   "python_run_ms_per_step": t_call * 1e3 / args.steps,
                    "init_ms_per_step": tot["init_ms"] / args.steps, "run_ms_per_step": tot["run_ms"] / args.steps,
                    "process_ms_per_step": tot["process_ms"] / args.steps,
                    "passes_per_step": tot["passes"] / args.steps,

@@ -195,6 +195,9 @@ typedef struct {
                                   phases, summed over workgroups: [0] bitmap
                                   gather, [1] round take, [2] filter and edge
                                   numbering, [3] edge tasks, [4] yield      */
+    double wall_ms;            /* host wall-clock time of the fork_run call */
+    double setup_ms;           /* of which before the first wave's device work
+                                  (planning, buffer reservation)            */
 } fork_stats_t;
 
 /* Per-query digest (fork_fetch field FORK_FIELD_DIGEST).  For SSSP/BFS:
@@ -264,6 +267,18 @@ int fork_submit(fork_ctx *ctx, int query_type, const uint32_t *sources,
  * operations are retained, so correctness holds).
  */
 int fork_run(fork_ctx *ctx, const fork_run_opts *opts);
+
+/*
+ * Plan the waves fork_run would make for the submitted queries under opts
+ * and allocate their device buffers (query state, and the grouped engine's
+ * rows and pending sets), without running anything; a following fork_run
+ * with the same queries and options allocates nothing more for them.  The
+ * setup step before Algorithm 2's loop, split off so that a caller can pay
+ * the allocation outside a timed or latency-bound region.  Blocks until the
+ * buffers are allocated.  Errors as fork_run's (FORK_E_NOMEM when one
+ * query's state does not fit in device memory).
+ */
+int fork_prepare(fork_ctx *ctx, const fork_run_opts *opts);
 
 /*
  * Sweep cuts of resident PPR queries: the NCP application built on the PPR

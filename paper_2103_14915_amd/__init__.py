@@ -70,7 +70,8 @@ class fork_stats_t(ctypes.Structure):
                 ("selected_edges", ctypes.c_uint64), ("ppr_edges", ctypes.c_uint64),
                 ("ppr_vertex_pushes", ctypes.c_uint64), ("spilled", ctypes.c_uint64),
                 ("activations", ctypes.c_uint64), ("expansions", ctypes.c_uint64), ("spill_max", ctypes.c_uint64),
-                ("rounds", ctypes.c_uint64), ("edge_tasks", ctypes.c_uint64), ("visit_ns", ctypes.c_uint64 * 5)]
+                ("rounds", ctypes.c_uint64), ("edge_tasks", ctypes.c_uint64), ("visit_ns", ctypes.c_uint64 * 5),
+                ("wall_ms", ctypes.c_double), ("setup_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {n: (list(getattr(self, n)) if isinstance(getattr(self, n), ctypes.Array) else getattr(self, n))
@@ -88,7 +89,7 @@ class fork_digest(ctypes.Structure):
                 ("fsum", ctypes.c_double), ("fres", ctypes.c_double), ("fmax", ctypes.c_double)]
 
 
-EXPORTS = ["fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions",
+EXPORTS = ["fork_graph_load", "fork_submit", "fork_run", "fork_prepare", "fork_fetch", "fork_stats", "fork_partitions",
            "fork_trace", "fork_destroy", "fork_last_error", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train",
            "fork_sweep", "fork_bc", "fork_mlp_train_noalloc"]
 SWEEP_MAX, SWEEP_BUCKETS = 1024, 11
@@ -108,6 +109,7 @@ def _load():
                                     ctypes.POINTER(fork_config)]
     lib.fork_submit.argtypes = [P, I, P, U32, P, ctypes.POINTER(U32)]
     lib.fork_run.argtypes = [P, ctypes.POINTER(fork_run_opts)]
+    lib.fork_prepare.argtypes = [P, ctypes.POINTER(fork_run_opts)]
     lib.fork_fetch.argtypes = [P, U32, I, P, U64, I]
     lib.fork_stats.argtypes = [P, P, U64]
     lib.fork_partitions.argtypes = [P, P, U32, ctypes.POINTER(U32)]
@@ -121,7 +123,7 @@ def _load():
     lib.fork_destroy.argtypes = [P]
     lib.fork_destroy.restype = None
     lib.fork_last_error.restype = ctypes.c_char_p
-    for n in ("fork_graph_load", "fork_submit", "fork_run", "fork_fetch", "fork_stats", "fork_partitions",
+    for n in ("fork_graph_load", "fork_submit", "fork_run", "fork_prepare", "fork_fetch", "fork_stats", "fork_partitions",
               "fork_trace", "fork_mlp_forward", "fork_mlp_grad", "fork_mlp_train", "fork_sweep", "fork_bc",
               "fork_mlp_train_noalloc"):
         getattr(lib, n).restype = I
@@ -215,7 +217,8 @@ class ForkGraph:
 
     def run(self, scheduler="priority", parts_per_pass=0, delta=0, edge_budget_mu=0.0, max_passes=0,
             stream=None, mlp_weights=None, persistent=0, seed=0, profile=0, items_per_pass=0, trace=0,
-            window_mode=0, window=0, slice_slots=0, engine="buffered", group_threads=0):
+            window_mode=0, window=0, slice_slots=0, engine="buffered", group_threads=0, prepare_only=False):
+        """fork_run; with prepare_only, fork_prepare (allocate the run's device buffers, run nothing)."""
         s = SCHEDS[scheduler] if isinstance(scheduler, str) else int(scheduler)
         eng = ENGINES[engine] if isinstance(engine, str) else int(engine)
         w = None
@@ -229,7 +232,11 @@ class ForkGraph:
         o = fork_run_opts(s, parts_per_pass, delta, edge_budget_mu, max_passes, sp,
                           None if w is None else w.ctypes.data, persistent, seed, profile, items_per_pass, trace,
                           window_mode, window, slice_slots, eng, group_threads)
-        _check(lib.fork_run(self._ctx, ctypes.byref(o)))
+        _check((lib.fork_prepare if prepare_only else lib.fork_run)(self._ctx, ctypes.byref(o)))
+
+    def prepare(self, **kw):
+        """fork_prepare with fork_run's keyword arguments."""
+        self.run(prepare_only=True, **kw)
 
     def fetch(self, qid, field=None, out=None):
         """Result vector of query qid (numpy), or written into a device tensor `out`."""

@@ -75,13 +75,36 @@ def _load_cache() -> dict:
         return {}
 
 
+def _split(sig: str):
+    """(graph part, {query type: count}, hash) of a cache signature."""
+    head, mix, hsh = sig.split("-")[0:2], sig.split("-")[2:-1], sig.split("-")[-1]
+    counts = {}
+    for part in "-".join(mix).split(","):
+        qt, _, n = part.partition(":")
+        counts[qt] = int(n) if n.isdigit() else 0
+    return "-".join(head), counts, hsh
+
+
 def cached(g, queries) -> Optional[dict]:
-    """Tuned knobs for this graph and query mix: this device's entry, else any device's."""
+    """Tuned knobs for this graph and query mix: this device's entry, else any
+    device's; else the entry tuned on the largest query subset of the same
+    graph with the same query types (a batch too large to tune in full takes
+    the knobs of a seeded subset of itself)."""
     cache = _load_cache()
     sig = signature(g, queries)
     hit = cache.get(f"{sig}|{device_name()}")
     if hit is None:
         hit = next((v for k, v in cache.items() if k.split("|")[0] == sig), None)
+    if hit is None:
+        graph, counts, hsh = _split(sig)
+        best = None
+        for k, v in cache.items():
+            g2, c2, h2 = _split(k.split("|")[0])
+            if g2 == graph and h2 == hsh and set(c2) == set(counts) and all(c2[t] <= counts[t] for t in counts):
+                n = sum(c2.values())
+                if best is None or n > best[0]:
+                    best = (n, v, ",".join(f"{t}:{c2[t]}" for t in c2))
+        hit = dict(best[1], params=dict(best[1].get("params", {}), _tuned_on=best[2])) if best else None
     return None if hit is None else dict(DEFAULTS, **hit.get("params", {}))
 
 

@@ -180,6 +180,10 @@ struct fork_ctx {
     uint32_t hslots = 0;  // hashed LDS slice slots of the current run (0 = dense slice)
     bool dense_ok = true; // the dense slice of the largest partition fits in LDS
     bool spill_refused = false;  // the last run stopped at the frontier-spill bound
+    // device memory budget of the batch's wave plan, fixed by its first fork_prepare or
+    // fork_run (0: none yet), so that later runs of the batch make the same waves and
+    // find their buffers allocated; reset by fork_submit
+    size_t plan_budget = 0;
     uint32_t vpmax = 1;  // largest partition (vertices)
     double wmean = 1.0;  // mean edge weight
 };
@@ -499,6 +503,7 @@ extern "C" int fork_submit(fork_ctx* c, int type, const uint32_t* sources, uint3
     }
     for (uint32_t i = 0; i < n; ++i)
         if (sources[i] >= c->nv) return fail(FORK_E_INVALID, "source %u out of range (V=%u)", sources[i], c->nv);
+    c->plan_budget = 0;  // the batch changes: plan its waves again
     if (c->ran) {  // a new batch
         c->queries.clear();
         c->digests.clear();
@@ -907,6 +912,70 @@ template <class T> static int grow(T** p, size_t& cap, size_t n) {
     return FORK_OK;
 }
 
+// Pair summaries (np x ng) and per-group arrays (ng groups of 64 lanes) of the
+// grouped engine, grown to hold ng groups.
+static int grow_groups(fork_ctx* c, size_t ng) {
+    constexpr size_t GW = 64;
+    const size_t npairs = (size_t)c->np * ng;
+    int rc;
+    size_t cap = c->pair_cap;
+    if ((rc = grow(&c->d_icnt, cap, npairs))) return rc;
+    cap = c->pair_cap;
+    if ((rc = grow(&c->d_ibest, cap, npairs))) return rc;
+    cap = c->pair_cap;
+    if ((rc = grow(&c->d_ifirst, cap, npairs))) return rc;
+    c->pair_cap = std::max(c->pair_cap, npairs);
+    if (c->grp_cap < ng) {
+        void* gp[] = {c->d_gmin, c->d_gtype, c->d_goff, c->d_lq, c->d_lsrc, c->d_lmode, c->d_lalpha, c->d_leps};
+        for (void* q : gp) hipFree(q);
+        c->d_gmin = c->d_gtype = c->d_lq = c->d_lsrc = c->d_lmode = nullptr;
+        c->d_goff = nullptr;
+        c->d_lalpha = c->d_leps = nullptr;
+        c->grp_cap = 0;
+        if ((rc = dalloc(&c->d_gmin, ng)) || (rc = dalloc(&c->d_gtype, ng)) || (rc = dalloc(&c->d_goff, ng)) ||
+            (rc = dalloc(&c->d_lq, ng * GW)) || (rc = dalloc(&c->d_lsrc, ng * GW)) ||
+            (rc = dalloc(&c->d_lmode, ng * GW)) || (rc = dalloc(&c->d_lalpha, ng * GW)) ||
+            (rc = dalloc(&c->d_leps, ng * GW)))
+            return rc;
+        c->grp_cap = (uint32_t)ng;
+    }
+    return FORK_OK;
+}
+
+// Size the grouped engine's buffers once for the largest wave of a run.  The
+// waves differ in their mix of query types; growing a buffer between waves
+// would free it and allocate it again, and an allocation of this size (up to
+// the device memory budget) takes seconds.
+static int reserve_groups(fork_ctx* c, const std::vector<std::pair<uint32_t, uint32_t>>& waves, uint32_t kmax) {
+    constexpr size_t GW = 64;
+    size_t words = 0, gwords = 0, ng = 0;
+    uint32_t nq = 0;
+    for (const auto& w : waves) {
+        size_t ww = 0, cnt[3] = {0, 0, 0};
+        for (uint32_t i = 0; i < w.second; ++i) {
+            const uint32_t t = c->queries[w.first + i].type;
+            ww += qwords(c, t);
+            ++cnt[t == FORK_SSSP ? 0 : t == FORK_BFS ? 1 : 2];
+        }
+        size_t g = 0, gw = 0;
+        for (int k = 0; k < 3; ++k) {
+            const size_t n = (cnt[k] + GW - 1) / GW;
+            g += n;
+            gw += n * (k == 2 ? 2ull : 1ull) * c->nv * GW;
+        }
+        words = std::max(words, ww);
+        gwords = std::max(gwords, gw);
+        ng = std::max(ng, g);
+        nq = std::max(nq, w.second);
+    }
+    int rc = ensure_wave(c, nq, words, kmax);
+    if (rc) return rc;
+    if ((rc = grow(&c->d_gstate, c->gstate_cap, gwords))) return rc;
+    if ((rc = grow(&c->d_gpend, c->gpend_cap, ng * c->nv))) return rc;
+    if ((rc = grow(&c->d_gbits, c->gbits_cap, ng * (c->nv / 32 + 2)))) return rc;
+    return grow_groups(c, ng);
+}
+
 // One wave on the grouped engine: the wave's queries of each type are taken
 // 64 at a time as lane groups with vertex-major state rows.  The result vectors
 // are written in the per-query layout of run_wave at the end, so fetch,
@@ -966,29 +1035,7 @@ static int run_wave_group(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_
     if ((rc = grow(&c->d_gstate, c->gstate_cap, gwords))) return rc;
     if ((rc = grow(&c->d_gpend, c->gpend_cap, (size_t)ng * c->nv))) return rc;
     if ((rc = grow(&c->d_gbits, c->gbits_cap, (size_t)ng * bw))) return rc;
-    {
-        size_t cap = c->pair_cap;
-        if ((rc = grow(&c->d_icnt, cap, npairs))) return rc;
-        cap = c->pair_cap;
-        if ((rc = grow(&c->d_ibest, cap, npairs))) return rc;
-        cap = c->pair_cap;
-        if ((rc = grow(&c->d_ifirst, cap, npairs))) return rc;
-        c->pair_cap = std::max(c->pair_cap, npairs);
-    }
-    if (c->grp_cap < ng) {
-        void* gp[] = {c->d_gmin, c->d_gtype, c->d_goff, c->d_lq, c->d_lsrc, c->d_lmode, c->d_lalpha, c->d_leps};
-        for (void* q : gp) hipFree(q);
-        c->d_gmin = c->d_gtype = c->d_lq = c->d_lsrc = c->d_lmode = nullptr;
-        c->d_goff = nullptr;
-        c->d_lalpha = c->d_leps = nullptr;
-        c->grp_cap = 0;
-        if ((rc = dalloc(&c->d_gmin, ng)) || (rc = dalloc(&c->d_gtype, ng)) || (rc = dalloc(&c->d_goff, ng)) ||
-            (rc = dalloc(&c->d_lq, (size_t)ng * GW)) || (rc = dalloc(&c->d_lsrc, (size_t)ng * GW)) ||
-            (rc = dalloc(&c->d_lmode, (size_t)ng * GW)) || (rc = dalloc(&c->d_lalpha, (size_t)ng * GW)) ||
-            (rc = dalloc(&c->d_leps, (size_t)ng * GW)))
-            return rc;
-        c->grp_cap = ng;
-    }
+    if ((rc = grow_groups(c, ng))) return rc;
     // workgroup size of the grouped pass (waves that share one pair's visit)
     const uint32_t gnt = o.group_threads ? o.group_threads : 256u;
     if (gnt != 256 && gnt != 512 && gnt != 1024)
@@ -1122,7 +1169,10 @@ static int run_wave_group(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_
     return FORK_OK;
 }
 
-extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
+// fork_run, or with prepare = true fork_prepare: plan the waves and allocate
+// their device buffers, then return without running.
+static int run_impl(fork_ctx* c, const fork_run_opts* opts, bool prepare) {
+    const auto t_entry = std::chrono::steady_clock::now();
     g_err[0] = 0;
     if (!c) return fail(FORK_E_INVALID, "ctx is NULL");
     if (c->queries.empty()) return fail(FORK_E_STATE, "no queries submitted");
@@ -1160,9 +1210,15 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     // wave capacity from free device memory
     size_t fr = 0, tot = 0;
     HIPCHK(hipMemGetInfo(&fr, &tot));
-    size_t reserve = (size_t)c->state_words_cap * 4;  // memory we already hold for state
+    // memory we already hold for state (and, for the grouped engine, its rows and pending sets)
+    size_t reserve = (size_t)c->state_words_cap * 4 +
+                     (grouped ? c->gstate_cap * 4 + c->gpend_cap * 8 + c->gbits_cap * 4 : 0);
     size_t budget = (fr + reserve) > ((size_t)2 << 30) ? (fr + reserve) - ((size_t)2 << 30) : 0;
     budget = (size_t)(budget * 0.9);
+    // the batch's wave plan is fixed, while it still fits (the per-wave
+    // buffers allocated since are small; memory taken by others is not)
+    if (c->plan_budget && c->plan_budget <= budget + ((size_t)1 << 30)) budget = c->plan_budget;
+    else c->plan_budget = budget;
     uint32_t cap_q = c->max_queries ? c->max_queries : nq_total;
     // per-query bytes beyond state: buckets (28 B per partition) + items; the
     // grouped engine holds its own copy of the state rows plus 8 B of pending
@@ -1206,7 +1262,27 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     const uint32_t slots = (uint32_t)std::max(1, c->num_cu * c->blocks_per_cu);
     cfg.kmax = o.parts_per_pass ? std::min<uint32_t>(o.parts_per_pass, c->np) : c->np;
     cfg.target_items = o.parts_per_pass ? 0u : (o.items_per_pass ? o.items_per_pass : 16u * slots);
+    if (grouped) {
+        int rc = reserve_groups(c, waves, cfg.kmax);
+        if (rc) return rc;
+    } else if (prepare) {
+        size_t words = 0;
+        uint32_t nmax = 0;
+        for (const auto& w : waves) {
+            size_t ww = 0;
+            for (uint32_t i = 0; i < w.second; ++i) ww += qwords(c, c->queries[w.first + i].type);
+            words = std::max(words, ww);
+            nmax = std::max(nmax, w.second);
+        }
+        int rc = ensure_wave(c, nmax, words, cfg.kmax);
+        if (rc) return rc;
+    }
+    if (prepare) {
+        HIPCHK(hipDeviceSynchronize());
+        return FORK_OK;
+    }
     c->stats = fork_stats_t{};
+    c->stats.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_entry).count();
     c->spill_refused = false;
     c->trace.clear();
     if (o.trace && o.persistent) return fail(FORK_E_INVALID, "trace runs use the per-pass kernels (persistent = 0)");
@@ -1259,6 +1335,16 @@ extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
     c->ran = true;
     return FORK_OK;
 }
+
+extern "C" int fork_run(fork_ctx* c, const fork_run_opts* opts) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = run_impl(c, opts, false);
+    if (c && rc == FORK_OK)
+        c->stats.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+extern "C" int fork_prepare(fork_ctx* c, const fork_run_opts* opts) { return run_impl(c, opts, true); }
 
 extern "C" int fork_fetch(fork_ctx* c, uint32_t qid, int field, void* dst, uint64_t dst_bytes, int dst_on_device) {
     g_err[0] = 0;

@@ -49,13 +49,13 @@ def load(asan: bool = False):
 class SimtGraph:
     """One context of the CPU build: load, submit, run, fetch."""
 
-    def __init__(self, lib, g, partition_vertices=0, pool_bytes=0):
+    def __init__(self, lib, g, partition_vertices=0, pool_bytes=0, max_queries=0):
         self.lib = lib
         self.g = g
         rp = np.ascontiguousarray(g.row_ptr, np.uint64)
         col = np.ascontiguousarray(g.col, np.uint32)
         w = None if g.weight is None else np.ascontiguousarray(g.weight, np.uint32)
-        cfg = fork.fork_config(partition_vertices=partition_vertices, pool_bytes=pool_bytes)
+        cfg = fork.fork_config(partition_vertices=partition_vertices, pool_bytes=pool_bytes, max_queries=max_queries)
         self.ctx = ctypes.c_void_p()
         self._check(lib.fork_graph_load(ctypes.byref(self.ctx), g.num_vertices, int(col.size), rp.ctypes.data,
                                         col.ctypes.data, None if w is None else w.ctypes.data, ctypes.byref(cfg)))

@@ -422,9 +422,15 @@ struct simt_event {
     std::chrono::steady_clock::time_point t;
 };
 
+namespace { unsigned long long g_alloc_calls = 0; }
+// allocation counters for tests: calls so far and bytes held
+extern "C" unsigned long long simt_alloc_calls() { return g_alloc_calls; }
+extern "C" unsigned long long simt_mem_used() { return g_mem_used; }
+
 hipError_t hipMalloc(void** p, size_t n) {
     size_t cap = (size_t)simt::env_int("SIMT_MEM_MB", 4096) << 20;
     std::lock_guard<std::mutex> lk(g_mem_m);
+    ++g_alloc_calls;
     if (n == 0) n = 1;
     if (g_mem_used + n > cap) { *p = nullptr; return g_last = hipErrorOutOfMemory; }
     size_t sz = (n + 255) & ~(size_t)255;

@@ -53,6 +53,7 @@ def test_null_and_invalid_arguments(fork):
     assert lib.fork_submit(None, fork.SSSP, None, 0, None, None) == fork.FORK_E_INVALID
     assert "NULL" in fork.last_error()
     assert lib.fork_run(None, None) == fork.FORK_E_INVALID
+    assert lib.fork_prepare(None, None) == fork.FORK_E_INVALID
     buf = (ctypes.c_int32 * 4)()
     assert lib.fork_fetch(None, 0, 0, buf, 16, 0) == fork.FORK_E_INVALID
     assert lib.fork_stats(None, buf, 16) == fork.FORK_E_INVALID

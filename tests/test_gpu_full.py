@@ -66,8 +66,8 @@ def run_workload(fork, g, queries, spec, p):
     for qt, s in queries:
         fg.submit(qt, s, alpha=spec.get("alpha", 0.15), epsilon=spec.get("epsilon", 1e-6),
                   eps_mode=spec.get("eps_mode", 0))
-    fg.run(items_per_pass=p["items_per_pass"], window=p["window"], delta=p["delta"], persistent=p["persistent"],
-           slice_slots=p.get("slice_slots", 0))
+    from paper_2103_14915_amd import autotune
+    fg.run(**autotune.run_kwargs(p))
     return fg
 
 
@@ -253,4 +253,26 @@ def test_large_rmat_query_subset(name, take):
         else:
             check_sp_sample(fork, fg, g, s, first, qt, 6, 10 + k)
         first += len(s)
+    fg.close()
+
+
+@pytest.mark.parametrize("name,take", [("rmat20_sssp_ppr2048", 1024), ("rmat23_sssp_ppr65536", 1024)])
+def test_sssp_ppr_mix_in_the_bench_configuration(name, take):
+    """The SSSP+PPR batches on the knobs bench.py takes for them: the scale-20
+    mix in full, and a seeded 2,048-query slice of the scale-23 batch on the
+    knobs tuned on a subset of it (the grouped engine for both).  Sampled SSSP
+    distances are bit-exact against Dijkstra; sampled PPR vectors meet the push
+    gates and the invariant against power iteration."""
+    fork = _fork()
+    spec = fi.WORKLOADS[name]
+    g = fi.make_graph(spec)
+    full = fi.make_sources(g, spec)
+    p = knobs(g, full)
+    assert p.get("engine") == "grouped", p
+    queries = [(qt, s[:take]) for qt, s in full]
+    say(name, [len(s) for _, s in queries], p)
+    fg = run_workload(fork, g, queries, spec, p)
+    assert [qt for qt, _ in queries] == ["sssp", "ppr"]
+    check_sp_sample(fork, fg, g, queries[0][1], 0, "sssp", 6, 31)
+    check_ppr_sample(fork, fg, g, queries[1][1], take, spec, 4, 32)
     fg.close()

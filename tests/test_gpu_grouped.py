@@ -110,6 +110,33 @@ def test_grouped_waves_digests_and_vertex_order():
     assert digs[0] == digs[1]
 
 
+def test_prepare_allocates_without_running():
+    """fork_prepare sizes the buffers for the largest of waves that mix query
+    types differently (SSSP only, both, PPR only), runs nothing (fetch still
+    reports FORK_E_STATE), and the run after it is exact."""
+    fork = _fork()
+    g = fi.rmat(11, seed=79, weights=(1, 255), weight_seed=80)
+    s_sp = fi.sources_uniform(g, 100, 10)
+    s_pr = fi.sources_uniform(g, 100, 11)
+    digs = []
+    for prep in (True, False):
+        fg = fork.ForkGraph.from_graph(g, partition_vertices=512, max_queries=80)
+        fg.submit("sssp", s_sp)
+        fg.submit("ppr", s_pr, alpha=ALPHA, epsilon=1e-5, eps_mode=1)
+        if prep:
+            fg.prepare(engine="grouped", group_threads=1024)
+            with pytest.raises(fork.ForkError) as e:
+                fg.fetch(0)
+            assert e.value.code == fork.FORK_E_STATE
+        fg.run(engine="grouped", group_threads=1024)
+        assert fg.stats()["waves"] == 3
+        digs.append([(fg.digest(i)["hash"], fg.digest(i)["count"]) for i in range(100)])
+        fg.close()
+    assert digs[0] == digs[1]
+    ref = oracle.sssp(g, s_sp)
+    assert all(digs[0][i][1] == int(np.sum(ref[i] != np.int32(0x7FFFFFFF))) for i in range(100))
+
+
 def test_grouped_learned_scheduler_exact():
     fork = _fork()
     g = fi.rmat(12, seed=77, weights=(1, 255), weight_seed=78)

@@ -59,8 +59,27 @@ def test_autotune_cache_falls_back_to_other_device(autotune):
     json.dump({f"{sig}|another-gpu": {"params": {"partition_vertices": 8192}}}, open(autotune.CACHE, "w"))
     got = autotune.cached(g, queries)
     assert got["partition_vertices"] == 8192 and got["slice_slots"] == autotune.DEFAULTS["slice_slots"]
-    other = [("ppr", fi.sources_uniform(g, 9, 6))]
+    other = [("sssp", fi.sources_uniform(g, 8, 6))]
     assert autotune.cached(g, other) is None  # a different query mix is a different key
+    # a batch of 9 takes the entry tuned on its subset of 8
+    assert autotune.cached(g, [("ppr", fi.sources_uniform(g, 9, 6))])["partition_vertices"] == 8192
+
+
+def test_autotune_cache_takes_a_subset_entry_for_a_larger_batch(autotune):
+    """A batch too large to tune in full takes the knobs tuned on the largest
+    seeded subset of the same graph with the same query types."""
+    g = fi.rmat(9, seed=5)
+    small = [("sssp", np.arange(8)), ("ppr", np.arange(8))]
+    mid = [("sssp", np.arange(16)), ("ppr", np.arange(16))]
+    full = [("sssp", np.arange(64)), ("ppr", np.arange(64))]
+    cache = {f"{autotune.signature(g, small)}|d": {"params": {"partition_vertices": 1024}},
+             f"{autotune.signature(g, mid)}|d": {"params": {"partition_vertices": 2048}}}
+    json.dump(cache, open(autotune.CACHE, "w"))
+    assert autotune.cached(g, full)["partition_vertices"] == 2048      # the largest subset
+    assert autotune.cached(g, [("sssp", np.arange(12)), ("ppr", np.arange(12))])["partition_vertices"] == 1024
+    assert autotune.cached(g, [("sssp", np.arange(64))]) is None       # other query types
+    assert autotune.cached(g, [("sssp", np.arange(4)), ("ppr", np.arange(4))]) is None  # no smaller subset
+    assert autotune.cached(fi.rmat(9, seed=6), full) is None           # another graph
 
 
 def test_autotune_sample_keeps_the_mix(autotune):

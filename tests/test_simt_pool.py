@@ -187,3 +187,36 @@ def test_no_alloc_training_on_the_host_build(fs):
     big = np.zeros((32769, 16), np.float32)
     assert lib.fork_mlp_train_noalloc(theta0.ctypes.data, big.ctypes.data, big[:, 0].copy().ctypes.data, 32769, 1,
                                       256, 1e-3, 0, None, None) == -1
+
+
+def test_prepare_leaves_nothing_to_allocate_for_the_run(fs):
+    """fork_prepare allocates every device buffer of a grouped run whose waves
+    mix query types differently (PPR only, both, SSSP only); the runs after it
+    allocate nothing, and the last wave's SSSP vectors are exact."""
+    import ctypes
+    import paper_2103_14915_amd as fork
+    lib = fs.load()
+    lib.simt_alloc_calls.restype = ctypes.c_uint64
+    lib.fork_prepare.argtypes = [ctypes.c_void_p, ctypes.POINTER(fork.fork_run_opts)]
+    lib.fork_prepare.restype = ctypes.c_int
+    g = fi.rmat(10, seed=79, weights=(1, 255), weight_seed=80)
+    s_sp, s_pr = fi.sources_uniform(g, 100, 10), fi.sources_uniform(g, 100, 11)
+    ref = oracle.sssp(g, s_sp[60:])
+    for prep in (True, False):
+        sg = fs.SimtGraph(lib, g, partition_vertices=256, max_queries=80)
+        sg.submit("ppr", s_pr, alpha=0.15, epsilon=1e-4, eps_mode=1)
+        sg.submit("sssp", s_sp)
+        o = fork.fork_run_opts()
+        o.engine, o.group_threads = fork.ENGINES["grouped"], 256
+        if prep:
+            assert lib.fork_prepare(sg.ctx, ctypes.byref(o)) == 0
+            n0 = lib.simt_alloc_calls()
+            assert lib.fork_run(sg.ctx, ctypes.byref(o)) == 0
+            assert lib.fork_run(sg.ctx, ctypes.byref(o)) == 0
+            assert lib.simt_alloc_calls() == n0
+        else:
+            assert lib.fork_run(sg.ctx, ctypes.byref(o)) == 0
+        assert sg.stats()["waves"] == 3
+        # the last wave (the last 40 SSSP queries) keeps its vectors
+        np.testing.assert_array_equal(np.stack([sg.fetch(160 + i) for i in range(40)]), ref)
+        sg.close()
