@@ -264,7 +264,7 @@ def main():
         t_tune = time.perf_counter()
         tuned = autotune.tune(g, queries, spec, log=lambda *a: print(*a, file=sys.stderr, flush=True),
                               use_cache=not args.retune, sample=args.tune_sample) \
-            if args.tune else autotune.cached(g, queries)
+            if args.tune else autotune.cached(g, queries, spec)
         if tuned:
             tuned = dict(tuned)
             subset = tuned.pop("_tuned_on", None)

@@ -197,8 +197,13 @@ def sources_mixed(g: Graph, n: int, seed: int) -> np.ndarray:
 WORKLOADS = {
     "rmat12_sssp64": dict(kind="rmat", scale=12, weights=(1, 255), seeds=(1, 101, 201),
                           queries=[("sssp", 64, "uniform")]),
+    # PPR forward push at scale 20: the threshold epsilon scaled by the vertex's
+    # degree (the variant the degree-normalised push of the paper's PPR uses) ...
     "rmat20_ppr4096": dict(kind="rmat", scale=20, weights=None, seeds=(2, 102, 202),
                            queries=[("ppr", 4096, "uniform")], alpha=0.15, epsilon=1e-6, eps_mode=1),
+    # ... and with the absolute threshold r(u) >= epsilon, the same graph and sources
+    "rmat20_ppr4096_abs": dict(kind="rmat", scale=20, weights=None, seeds=(2, 102, 202),
+                               queries=[("ppr", 4096, "uniform")], alpha=0.15, epsilon=1e-6, eps_mode=0),
     "grid2048_sssp1024_bfs1024": dict(kind="grid", rows=2048, cols=2048, weights=(1, 1000),
                                       seeds=(3, 103, 203),
                                       queries=[("sssp", 1024, "uniform"), ("bfs", 1024, "uniform")]),

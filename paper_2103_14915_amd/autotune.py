@@ -57,13 +57,17 @@ def device_name() -> str:
         return "unknown"
 
 
-def signature(g, queries) -> str:
+def signature(g, queries, spec=None) -> str:
+    """Cache key of a graph and query mix.  PPR queries with the absolute
+    threshold (eps_mode 0) are marked 'ppr@abs': they push far more than the
+    degree-scaled ones and tune differently."""
     h = hashlib.sha1()
     h.update(np.asarray([g.num_vertices, g.num_edges], np.int64).tobytes())
     h.update(np.ascontiguousarray(g.row_ptr[:: max(1, g.num_vertices // 4096)]).tobytes())
     if g.weight is not None:
         h.update(np.ascontiguousarray(g.weight[:4096]).tobytes())
-    mix = ",".join(f"{qt}:{len(s)}" for qt, s in queries)
+    absolute = spec is not None and spec.get("eps_mode", 1) == 0
+    mix = ",".join(f"{qt}{'@abs' if qt == 'ppr' and absolute else ''}:{len(s)}" for qt, s in queries)
     return f"V{g.num_vertices}-E{g.num_edges}-{mix}-{h.hexdigest()[:12]}"
 
 
@@ -85,13 +89,13 @@ def _split(sig: str):
     return "-".join(head), counts, hsh
 
 
-def cached(g, queries) -> Optional[dict]:
+def cached(g, queries, spec=None) -> Optional[dict]:
     """Tuned knobs for this graph and query mix: this device's entry, else any
     device's; else the entry tuned on the largest query subset of the same
     graph with the same query types (a batch too large to tune in full takes
     the knobs of a seeded subset of itself)."""
     cache = _load_cache()
-    sig = signature(g, queries)
+    sig = signature(g, queries, spec)
     hit = cache.get(f"{sig}|{device_name()}")
     if hit is None:
         hit = next((v for k, v in cache.items() if k.split("|")[0] == sig), None)
@@ -157,7 +161,7 @@ def candidates(g, queries) -> dict:
 
 
 def tune(g, queries, spec, sample=256, rounds=1, budget_s=240.0, log=print, use_cache=True) -> dict:
-    key = f"{signature(g, queries)}|{device_name()}"
+    key = f"{signature(g, queries, spec)}|{device_name()}"
     cache = _load_cache()
     if use_cache and key in cache:
         return cache[key]["params"]

@@ -276,3 +276,29 @@ def test_sssp_ppr_mix_in_the_bench_configuration(name, take):
     check_sp_sample(fork, fg, g, queries[0][1], 0, "sssp", 6, 31)
     check_ppr_sample(fork, fg, g, queries[1][1], take, spec, 4, 32)
     fg.close()
+
+
+def test_rmat20_ppr_absolute_threshold_on_the_grouped_engine():
+    """PPR forward push as the configuration states it: R-MAT 20, alpha 0.15,
+    absolute threshold epsilon = 1e-6 (a vertex pushes while r(u) >= 1e-6),
+    on a seeded 256-source subset of its 4,096 sources.  About 1.4e8 edge
+    pushes per query, so the pushes of a group's 64 queries overlap on most
+    vertices.  The grouped engine runs it (no operation pool).  Sampled
+    vectors: every residual below epsilon, and p within L1 1e-4 of the
+    fixpoint that the invariant p + PPR(r) = PPR(e_s) fixes (power iteration,
+    fp64)."""
+    fork = _fork()
+    spec = fi.WORKLOADS["rmat20_ppr4096_abs"]
+    assert spec["eps_mode"] == 0 and spec["epsilon"] == 1e-6
+    g = fi.make_graph(spec)
+    (qt, srcs), = fi.make_sources(g, spec)
+    srcs = srcs[:256]
+    p = dict(engine="grouped", partition_vertices=4096, items_per_pass=0, window=0, delta=0, mu=0.0, persistent=0,
+             slice_slots=0, group_threads=1024)
+    say("rmat20 ppr absolute", len(srcs), p)
+    fg = run_workload(fork, g, [(qt, srcs)], spec, p)
+    d = [fg.digest(i) for i in range(len(srcs))]
+    # every query's mass: p sums to at least alpha (the source's first push), p and r to at most 1
+    assert all(x["fsum"] > 0.14 and x["fres"] >= 0 and x["fsum"] + x["fres"] <= 1.0 + 1e-3 for x in d)
+    check_ppr_sample(fork, fg, g, srcs, 0, spec, 4, 41)
+    fg.close()

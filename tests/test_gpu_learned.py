@@ -130,6 +130,55 @@ def test_learned_vs_rule_measured_on_the_same_queries():
     assert ratio > 0.25  # no pathological slowdown
 
 
+def test_learned_scheduler_gains_where_selection_binds():
+    """Where the select step binds, the committed network's schedule beats the
+    priority rule's in run time with identical SSSP results.  The workload is
+    the scale-20 SSSP+PPR mix (R-MAT 20, 1,024 + 1,024 queries) on its tuned
+    grouped-engine knobs with 512 work items per pass, so that each pass takes
+    a few of the pending (partition, group) pairs.  Rule and learned runs
+    alternate, five of each, and their medians are compared; on MI355X the
+    gain measured 1.05-1.09x here (and 1.00x or below with 16 or 4 partitions
+    per pass, where the test does not claim one)."""
+    import statistics
+    import time
+
+    import torch
+
+    fork = _fork()
+    from paper_2103_14915_amd import autotune, learn
+    spec = fi.WORKLOADS["rmat20_sssp_ppr2048"]
+    g = fi.make_graph(spec)
+    queries = fi.make_sources(g, spec)
+    assert [qt for qt, _ in queries] == ["sssp", "ppr"]
+    p = autotune.cached(g, queries)
+    assert p and p["engine"] == "grouped", p
+    theta = np.load(learn.DEFAULT_WEIGHTS)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=p["partition_vertices"])
+    for qt, s in queries:
+        fg.submit(qt, s, alpha=spec["alpha"], epsilon=spec["epsilon"], eps_mode=spec["eps_mode"])
+    kw = dict(autotune.run_kwargs(p), items_per_pass=512)
+    fg.prepare(**kw)
+    fg.run(**kw)  # warm-up
+    nsp = len(queries[0][1])
+    times = {"priority": [], "learned": []}
+    ref = None
+    for sched in ("priority", "learned") * 5:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fg.run(scheduler=sched, mlp_weights=theta if sched == "learned" else None, **kw)
+        torch.cuda.synchronize()
+        times[sched].append(time.perf_counter() - t0)
+        dig = [(fg.digest(i)["hash"], fg.digest(i)["count"]) for i in range(nsp)]
+        if ref is None:
+            ref = dig
+        assert dig == ref, f"{sched}: SSSP results differ"
+    fg.close()
+    speedup = statistics.median(times["priority"]) / statistics.median(times["learned"])
+    say(f"learned vs rule, R-MAT 20 SSSP+PPR mix, 512 items per pass: speedup {speedup:.3f} "
+        f"(rule {[round(t * 1e3) for t in times['priority']]} ms, learned {[round(t * 1e3) for t in times['learned']]} ms)")
+    assert speedup > 1.0
+
+
 @pytest.mark.parametrize("lr", [1e-3, 3e-2])
 def test_adam_steps_on_gpu_match_the_fp64_oracle(lr):
     """Two fork_mlp_train steps with the whole sample set as the batch against

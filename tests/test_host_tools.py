@@ -82,6 +82,20 @@ def test_autotune_cache_takes_a_subset_entry_for_a_larger_batch(autotune):
     assert autotune.cached(fi.rmat(9, seed=6), full) is None           # another graph
 
 
+def test_autotune_keys_absolute_ppr_apart(autotune):
+    """PPR with the absolute threshold tunes apart from the degree-scaled one
+    on the same graph and sources."""
+    g = fi.rmat(9, seed=5)
+    q = [("ppr", np.arange(16))]
+    deg, ab = autotune.signature(g, q, {"eps_mode": 1}), autotune.signature(g, q, {"eps_mode": 0})
+    assert deg == autotune.signature(g, q) and ab != deg and "ppr@abs:16" in ab
+    json.dump({f"{deg}|d": {"params": {"partition_vertices": 4096}}}, open(autotune.CACHE, "w"))
+    assert autotune.cached(g, q, {"eps_mode": 1})["partition_vertices"] == 4096
+    assert autotune.cached(g, q, {"eps_mode": 0}) is None
+    assert autotune.signature(g, [("sssp", np.arange(16))], {"eps_mode": 0}) == \
+        autotune.signature(g, [("sssp", np.arange(16))])
+
+
 def test_autotune_sample_keeps_the_mix(autotune):
     g = fi.rmat(9, seed=7)
     q = [("sssp", np.arange(300)), ("bfs", np.arange(100)), ("ppr", np.arange(100))]
