@@ -840,7 +840,73 @@ __global__ __launch_bounds__(256) void k_gout(GroupDev G, uint32_t nv, uint32_t*
     }
 }
 
+// Digests of a wave's queries straight from the group rows (for waves whose
+// vectors are not kept, so that they need no transpose): the definition of
+// k_digest per lane.  One block sums a chunk of vertices of one group, its
+// four waves reduced in LDS; then one lane per query adds to the query's
+// digest (SSSP/BFS count, sum, hash; PPR count of p > 0, sum p, sum r, max p).
+// `out` starts zeroed.
+constexpr uint32_t GDCHUNK = 16384;
+__global__ __launch_bounds__(256) void k_gdigest(GroupDev G, uint32_t nv, const uint32_t* lq, unsigned long long* out,
+                                                 const uint32_t* orig) {
+    const uint32_t grp = blockIdx.y, v0 = blockIdx.x * GDCHUNK;
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t v1 = nv - v0 < GDCHUNK ? nv : v0 + GDCHUNK;
+    const bool ppr = G.gtype[grp] == Q_PPR;
+    const uint32_t* st = G.state + G.goff[grp];
+    unsigned long long cnt = 0, sum = 0, hash = 0;
+    double f0 = 0, f1 = 0;
+    float fmax = 0.f;
+    if (ppr) {
+        const float* r = (const float*)st;
+        const float* p = (const float*)(st + (unsigned long long)nv * GW);
+        for (uint32_t v = v0 + wv; v < v1; v += 4) {
+            const float pv = p[(unsigned long long)v * GW + lane];
+            cnt += pv > 0.f;
+            f0 += pv;
+            f1 += r[(unsigned long long)v * GW + lane];
+            fmax = pv > fmax ? pv : fmax;
+        }
+    } else {
+        for (uint32_t v = v0 + wv; v < v1; v += 4) {
+            const uint32_t x = st[(unsigned long long)v * GW + lane];
+            if (x != INF) {
+                ++cnt;
+                sum += x;
+                hash += mix64(((unsigned long long)(orig ? orig[v] : v) << 32) | x);
+            }
+        }
+    }
+    __shared__ unsigned long long s_u[3][4][GW];
+    __shared__ double s_d[2][4][GW];
+    __shared__ float s_m[4][GW];
+    s_u[0][wv][lane] = cnt; s_u[1][wv][lane] = sum; s_u[2][wv][lane] = hash;
+    s_d[0][wv][lane] = f0; s_d[1][wv][lane] = f1; s_m[wv][lane] = fmax;
+    __syncthreads();
+    if (wv != 0) return;
+    const uint32_t q = lq[grp * GW + lane];
+    if (q == 0xffffffffu) return;
+    for (int w = 1; w < 4; ++w) {
+        cnt += s_u[0][w][lane]; sum += s_u[1][w][lane]; hash += s_u[2][w][lane];
+        f0 += s_d[0][w][lane]; f1 += s_d[1][w][lane];
+        fmax = s_m[w][lane] > fmax ? s_m[w][lane] : fmax;
+    }
+    unsigned long long* o = out + (unsigned long long)q * 6;
+    if (cnt) { atomicAdd(&o[0], cnt); atomicAdd(&o[1], sum); atomicAdd(&o[2], hash); }
+    if (ppr) {
+        atomicAdd((double*)&o[3], f0);
+        atomicAdd((double*)&o[4], f1);
+        // non-negative doubles order as their bit patterns
+        atomicMax(&o[5], (unsigned long long)__double_as_longlong((double)fmax));
+    }
+}
+
 // ------------------------------------------------------------ launchers
+hipError_t launch_gdigest(const GroupDev& G, uint32_t nv, const uint32_t* lq, unsigned long long* out,
+                          const uint32_t* orig, hipStream_t s) {
+    hipLaunchKernelGGL(k_gdigest, dim3((nv + GDCHUNK - 1) / GDCHUNK, G.ng), dim3(256), 0, s, G, nv, lq, out, orig);
+    return hipGetLastError();
+}
 hipError_t launch_gprocess(const GraphDev& g, const GroupDev& G, const BufDev& B, const PassCfg& cfg, uint32_t blocks,
                            uint32_t nth, hipStream_t s) {
     if (nth != 256 && nth != 512 && nth != 1024) return hipErrorInvalidValue;

@@ -61,6 +61,7 @@ hipError_t launch_gsummaries(const GraphDev&, const GroupDev&, const BufDev&, co
 hipError_t launch_gworklist(const BufDev&, const GroupDev&, const PassCfg&, hipStream_t);
 hipError_t launch_gseed(const GraphDev&, const GroupDev&, const uint32_t*, hipStream_t);
 hipError_t launch_gout(const GroupDev&, uint32_t, uint32_t*, const unsigned long long*, const uint32_t*, hipStream_t);
+hipError_t launch_gdigest(const GroupDev&, uint32_t, const uint32_t*, unsigned long long*, const uint32_t*, hipStream_t);
 uint32_t train_nmax();
 hipError_t train_prepare();
 hipError_t train_scratch_address(void**);
@@ -160,6 +161,8 @@ struct fork_ctx {
     bool ran = false;
     uint32_t res_first = 0, res_n = 0;
     fk::QueryDev resQ{};        // queries of the resident (last) wave
+    bool res_grouped = false;   // its results are still in the grouped engine's rows (no vectors)
+    fk::GroupDev resG{};        // those rows
     bool dig_pending = false;   // their digests are computed on first request
     std::vector<unsigned long long> res_off;
     fork_stats_t stats{};
@@ -592,7 +595,12 @@ static int wave_digest(fork_ctx* c, hipStream_t s) {
     if (!c->dig_pending) return FORK_OK;
     const uint32_t q0 = c->res_first, nq = c->res_n;
     HIPCHK(hipEventRecord(c->ev[2], s));
-    HIPCHK(fk::launch_digest(c->resQ, c->nv, c->d_digest, c->d_orig, s));
+    if (c->res_grouped) {
+        HIPCHK(hipMemsetAsync(c->d_digest, 0, (size_t)nq * 6 * 8, s));
+        HIPCHK(fk::launch_gdigest(c->resG, c->nv, c->d_lq, c->d_digest, c->d_orig, s));
+    } else {
+        HIPCHK(fk::launch_digest(c->resQ, c->nv, c->d_digest, c->d_orig, s));
+    }
     HIPCHK(hipEventRecord(c->ev[3], s));
     std::vector<unsigned long long> dg((size_t)nq * 6);
     HIPCHK(hipMemcpyAsync(dg.data(), c->d_digest, dg.size() * 8, hipMemcpyDeviceToHost, s));
@@ -872,6 +880,7 @@ static int run_wave(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& 
     // or on the first request for the wave that stays resident
     c->resQ = Q;
     c->resQ.final_state = nullptr;
+    c->res_grouped = false;
     c->dig_pending = true;
     const fk::Ctl& h = *c->h_ctl;
     fork_stats_t& st = c->stats;
@@ -981,7 +990,7 @@ static int reserve_groups(fork_ctx* c, const std::vector<std::pair<uint32_t, uin
 // are written in the per-query layout of run_wave at the end, so fetch,
 // digests, sweeps and BC read them the same way.
 static int run_wave_group(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_opts& o, hipStream_t s,
-                          const fk::PassCfg& cfg, uint64_t& passes_left) {
+                          const fk::PassCfg& cfg, uint64_t& passes_left, bool keep_vectors) {
     constexpr uint32_t GW = 64;
     std::vector<uint32_t> qt(nq), qm(nq);
     std::vector<unsigned long long> qo(nq);
@@ -1136,13 +1145,17 @@ static int run_wave_group(fork_ctx* c, uint32_t q0, uint32_t nq, const fork_run_
         if (h.pending_parts == 0) break;
         batch = std::min<uint32_t>(batch * 2, 64);
     }
-    HIPCHK(fk::launch_gout(G, c->nv, c->d_state, c->d_qoff, c->d_lq, s));
+    // the last wave's vectors stay for fetch, sweeps and BC: transpose them to
+    // the per-query layout; earlier waves leave only digests, taken from the rows
+    if (keep_vectors) HIPCHK(fk::launch_gout(G, c->nv, c->d_state, c->d_qoff, c->d_lq, s));
     HIPCHK(hipEventRecord(c->ev[2], s));
     HIPCHK(hipStreamSynchronize(s));
     float t_init = 0, t_run = 0;
     hipEventElapsedTime(&t_init, c->ev[0], c->ev[1]);
     hipEventElapsedTime(&t_run, c->ev[1], c->ev[2]);
     c->resQ = Q;
+    c->res_grouped = !keep_vectors;
+    c->resG = G;
     c->dig_pending = true;
     const fk::Ctl& h = *c->h_ctl;
     fork_stats_t& st = c->stats;
@@ -1303,7 +1316,7 @@ static int run_impl(fork_ctx* c, const fork_run_opts* opts, bool prepare) {
         }
         uint64_t saved = passes_left;
         fork_stats_t saved_st = c->stats;
-        int rc = grouped ? run_wave_group(c, q0, n, o, s, cfg, passes_left)
+        int rc = grouped ? run_wave_group(c, q0, n, o, s, cfg, passes_left, wi + 1 == waves.size())
                          : run_wave(c, q0, n, o, s, cfg, passes_left, false);
         if (rc == FORK_OK && o.trace) {
             // traced re-run: the final state of the first run marks useful work
