@@ -300,21 +300,22 @@ int fork_prepare(fork_ctx *ctx, const fork_run_opts *opts);
 int fork_sweep(fork_ctx *ctx, uint32_t first_query_id, uint32_t n, uint32_t max_size, fork_sweep_t *out);
 
 /*
- * Betweenness centrality from resident BFS queries: the BC application
- * (Sections 2 and 6.1: BFSs from sampled sources, then Brandes'
- * accumulation of dependencies).  Shortest paths are counted as edge
- * sequences of the multigraph.  For queries first_query_id ..
- * first_query_id + n - 1 (all BFS and in the resident wave), writes
- * out[v] = sum over their sources s of delta_s(v), with delta_s(s) = 0, as
- * double[num_vertices] in the caller's ids (host memory).  Path counts are
- * kept in fp64 divided by each BFS level's largest count, so they do not
- * overflow on graphs with astronomically many shortest paths.  Device
- * scratch: about 20 bytes per vertex per query, allocated for the call.
- * Errors: FORK_E_INVALID (bad range or type), FORK_E_STATE (not resident),
- * FORK_E_CAPACITY (a query with more than 16,384 BFS levels, or path counts
- * within one level that differ by more than fp64's range, as between the
- * middle and the ends of a level of a grid of roughly 1,000 x 1,000 or more
- * seen from a corner; no non-finite value is ever returned).
+ * Betweenness centrality from resident BFS or SSSP queries: the BC
+ * application (Sections 2 and 6.1: BFSs from sampled sources, then Brandes'
+ * accumulation of dependencies; on a weighted graph the same over SSSP).  A
+ * BFS query counts unit steps, an SSSP query the graph's weights; shortest
+ * paths are counted as edge sequences of the multigraph.  For queries
+ * first_query_id .. first_query_id + n - 1 (BFS or SSSP, in the resident
+ * wave), writes out[v] = sum over their sources s of delta_s(v), with
+ * delta_s(s) = 0, as double[num_vertices] in the caller's ids (host memory).
+ * Path counts are kept as natural logarithms in fp64 (a 2048 x 2048 grid has
+ * about 10^1230 corner-to-corner shortest paths), so no count overflows.
+ * Device scratch: about 20 bytes per vertex per query, allocated for the
+ * call; the first call also builds the graph's reverse adjacency.
+ * Errors: FORK_E_INVALID (bad range, or a PPR query), FORK_E_STATE (not
+ * resident), FORK_E_CAPACITY (a query whose BFS levels or SSSP distances
+ * reach 65,536: its vertices are sorted by value with a counting sort of
+ * that range; no non-finite value is ever returned).
  */
 int fork_bc(fork_ctx *ctx, uint32_t first_query_id, uint32_t n, double *out);
 

@@ -267,7 +267,7 @@ class ForkGraph:
         return out
 
     def bc(self, first, n) -> np.ndarray:
-        """Betweenness centrality from resident BFS queries first .. first + n - 1
+        """Betweenness centrality from resident BFS or SSSP queries first .. first + n - 1
         (see fork_bc): float64 [V], the sum of the sources' dependencies."""
         out = np.empty(self.num_vertices, np.float64)
         _check(lib.fork_bc(self._ctx, first, n, ctypes.c_void_p(out.ctypes.data)))

@@ -31,15 +31,16 @@ hipError_t launch_seed(const GraphDev&, const QueryDev&, const BufDev&, const ui
 hipError_t launch_digest(const QueryDev&, uint32_t, unsigned long long*, const uint32_t*, hipStream_t);
 hipError_t launch_gather(const uint32_t*, const uint32_t*, uint32_t*, uint32_t, hipStream_t);
 hipError_t launch_indeg(const uint32_t*, unsigned long long, uint32_t*, hipStream_t);
-hipError_t launch_rfill(const uint32_t*, const uint32_t*, uint32_t, const uint32_t*, uint32_t*, uint32_t*, hipStream_t);
+hipError_t launch_rfill(const uint32_t*, const uint32_t*, uint32_t, const uint32_t*, uint32_t*, uint32_t*, uint32_t*,
+                        hipStream_t);
 hipError_t launch_sdeg(const uint32_t*, const uint32_t*, uint32_t, uint32_t*, hipStream_t);
 hipError_t launch_sweep(const uint32_t*, const unsigned long long*, uint32_t, uint32_t, const uint32_t*, const uint32_t*,
                         const uint32_t*, const uint32_t*, const uint32_t*, unsigned long long, uint32_t, void*,
                         hipStream_t);
 size_t sweep_out_bytes();
-hipError_t launch_bc(const uint32_t*, const unsigned long long*, const uint32_t*, uint32_t, uint32_t, const uint32_t*,
-                     const uint32_t*, const uint32_t*, const uint32_t*, uint32_t*, uint32_t*, double*, double*, double*,
-                     double*, uint32_t*, hipStream_t);
+hipError_t launch_bc(const uint32_t*, const unsigned long long*, const uint32_t*, const uint32_t*, uint32_t, uint32_t,
+                     const uint32_t*, const uint32_t*, const void*, uint32_t, const uint32_t*, const uint32_t*,
+                     const uint32_t*, uint32_t*, uint32_t*, double*, double*, double*, uint32_t*, hipStream_t);
 uint32_t bc_level_cap();
 hipError_t launch_rnorm(const QueryDev&, uint32_t, const uint32_t*, uint32_t, double*, hipStream_t);
 hipError_t launch_rescan_items(const BufDev&, uint32_t, const uint32_t*, unsigned long long, uint32_t, hipStream_t);
@@ -110,7 +111,7 @@ struct fork_ctx {
     uint32_t* d_orig = nullptr;    // [nv] caller id of internal vertex u
     uint32_t* d_gather = nullptr;  // [nv] staging for fetches to host memory
     // reverse adjacency and undirected degrees (sweep cuts; built on first use)
-    uint32_t *d_rrow = nullptr, *d_rcol = nullptr, *d_sdeg = nullptr;
+    uint32_t *d_rrow = nullptr, *d_rcol = nullptr, *d_sdeg = nullptr, *d_reid = nullptr;
     // graph
     uint32_t* d_rowptr = nullptr;
     uint32_t* d_col = nullptr;
@@ -240,7 +241,7 @@ extern "C" void fork_destroy(fork_ctx* c) {
                     c->d_ccount, c->d_ring, c->d_pcount, c->d_pbest_sp, c->d_pbest_lv, c->d_pbest_pr,
                     c->d_pfirst, c->d_plast, c->d_pvisits, c->d_pn, c->d_sel, c->d_pqn, c->d_pready, c->d_pqmin,
                     c->d_score, c->d_mlp,
-                    c->d_ctl, c->d_gstat, c->d_feat, c->d_tr, c->d_final, c->d_pos, c->d_orig, c->d_gather, c->d_rrow, c->d_rcol, c->d_sdeg};
+                    c->d_ctl, c->d_gstat, c->d_feat, c->d_tr, c->d_final, c->d_pos, c->d_orig, c->d_gather, c->d_rrow, c->d_rcol, c->d_sdeg, c->d_reid};
     for (void* p : ptrs) if (p) hipFree(p);
     void* gptrs[] = {c->d_gstate, c->d_gpend, c->d_gbits, c->d_icnt, c->d_ibest, c->d_ifirst, c->d_gmin, c->d_gtype,
                      c->d_lmode, c->d_lq, c->d_lsrc, c->d_goff, c->d_lalpha, c->d_leps};
@@ -1419,21 +1420,23 @@ static int build_reverse(fork_ctx* c) {
     if (e != hipSuccess) { hipFree(indeg); return fail(FORK_E_DEVICE, "in-degrees: %s", hipGetErrorString(e)); }
     std::vector<uint32_t> rrow(c->nv + 1, 0);
     for (uint32_t v = 0; v < c->nv; ++v) rrow[v + 1] = rrow[v] + h[v];
-    if ((rc = dalloc(&c->d_rrow, c->nv + 1)) || (rc = dalloc(&c->d_rcol, c->ne)) || (rc = dalloc(&c->d_sdeg, c->nv))) {
+    if ((rc = dalloc(&c->d_rrow, c->nv + 1)) || (rc = dalloc(&c->d_rcol, c->ne)) || (rc = dalloc(&c->d_sdeg, c->nv)) ||
+        (rc = dalloc(&c->d_reid, c->ne))) {
         hipFree(indeg);
-        hipFree(c->d_rrow); hipFree(c->d_rcol); hipFree(c->d_sdeg);
-        c->d_rrow = c->d_rcol = c->d_sdeg = nullptr;
+        hipFree(c->d_rrow); hipFree(c->d_rcol); hipFree(c->d_sdeg); hipFree(c->d_reid);
+        c->d_rrow = c->d_rcol = c->d_sdeg = c->d_reid = nullptr;
         return rc;
     }
     e = hipMemcpy(c->d_rrow, rrow.data(), (c->nv + 1ull) * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(indeg, 0, (size_t)c->nv * 4);  // reused as the fill cursor
-    if (e == hipSuccess) e = fk::launch_rfill(c->d_rowptr, c->d_col, c->nv, c->d_rrow, indeg, c->d_rcol, nullptr);
+    if (e == hipSuccess)
+        e = fk::launch_rfill(c->d_rowptr, c->d_col, c->nv, c->d_rrow, indeg, c->d_rcol, c->d_reid, nullptr);
     if (e == hipSuccess) e = fk::launch_sdeg(c->d_rowptr, c->d_rrow, c->nv, c->d_sdeg, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     hipFree(indeg);
     if (e != hipSuccess) {
-        hipFree(c->d_rrow); hipFree(c->d_rcol); hipFree(c->d_sdeg);
-        c->d_rrow = c->d_rcol = c->d_sdeg = nullptr;
+        hipFree(c->d_rrow); hipFree(c->d_rcol); hipFree(c->d_sdeg); hipFree(c->d_reid);
+        c->d_rrow = c->d_rcol = c->d_sdeg = c->d_reid = nullptr;
         return fail(FORK_E_DEVICE, "reverse adjacency: %s", hipGetErrorString(e));
     }
     return FORK_OK;
@@ -1483,7 +1486,7 @@ extern "C" int fork_bc(fork_ctx* c, uint32_t first, uint32_t n, double* out) {
     if ((uint64_t)first + n > c->queries.size()) return fail(FORK_E_INVALID, "query range out of bounds");
     if (n && !c->ran) return fail(FORK_E_STATE, "queries have not run");
     for (uint32_t i = first; i < first + n; ++i) {
-        if (c->queries[i].type != FORK_BFS) return fail(FORK_E_INVALID, "query %u is not BFS", i);
+        if (c->queries[i].type == FORK_PPR) return fail(FORK_E_INVALID, "query %u is PPR (BC takes BFS or SSSP)", i);
         if (i < c->res_first || i >= c->res_first + c->res_n)
             return fail(FORK_E_STATE, "query %u is not resident (only the last wave keeps vectors)", i);
     }
@@ -1495,23 +1498,23 @@ extern "C" int fork_bc(fork_ctx* c, uint32_t first, uint32_t n, double* out) {
     int rc = build_reverse(c);
     if (rc) return rc;
     std::vector<unsigned long long> off(n);
-    std::vector<uint32_t> src(n);
+    std::vector<uint32_t> src(n), qw(n);
     for (uint32_t i = 0; i < n; ++i) {
         off[i] = c->res_off[first + i - c->res_first];
         src[i] = c->queries[first + i].src;  // internal id
+        qw[i] = c->queries[first + i].type == FORK_SSSP && c->wbytes ? 1u : 0u;  // SSSP on the graph's weights
     }
     const size_t nv = c->nv, lcap = fk::bc_level_cap() + 2ull;
     unsigned long long* d_off = nullptr;
-    uint32_t *d_src = nullptr, *d_order = nullptr, *d_ls = nullptr, *d_err = nullptr;
-    double *d_sigma = nullptr, *d_delta = nullptr, *d_gain = nullptr, *d_bc = nullptr;
+    uint32_t *d_src = nullptr, *d_qw = nullptr, *d_order = nullptr, *d_ls = nullptr, *d_err = nullptr;
+    double *d_lsig = nullptr, *d_delta = nullptr, *d_bc = nullptr;
     auto release = [&]() {
-        hipFree(d_off); hipFree(d_src); hipFree(d_order); hipFree(d_ls); hipFree(d_err);
-        hipFree(d_sigma); hipFree(d_delta); hipFree(d_gain); hipFree(d_bc);
+        hipFree(d_off); hipFree(d_src); hipFree(d_qw); hipFree(d_order); hipFree(d_ls); hipFree(d_err);
+        hipFree(d_lsig); hipFree(d_delta); hipFree(d_bc);
     };
-    if ((rc = dalloc(&d_off, n)) || (rc = dalloc(&d_src, n)) || (rc = dalloc(&d_order, (size_t)n * nv)) ||
-        (rc = dalloc(&d_ls, (size_t)n * lcap)) || (rc = dalloc(&d_err, 1)) || (rc = dalloc(&d_sigma, (size_t)n * nv)) ||
-        (rc = dalloc(&d_delta, (size_t)n * nv)) || (rc = dalloc(&d_gain, (size_t)n * lcap)) ||
-        (rc = dalloc(&d_bc, nv))) {
+    if ((rc = dalloc(&d_off, n)) || (rc = dalloc(&d_src, n)) || (rc = dalloc(&d_qw, n)) ||
+        (rc = dalloc(&d_order, (size_t)n * nv)) || (rc = dalloc(&d_ls, (size_t)n * lcap)) || (rc = dalloc(&d_err, 1)) ||
+        (rc = dalloc(&d_lsig, (size_t)n * nv)) || (rc = dalloc(&d_delta, (size_t)n * nv)) || (rc = dalloc(&d_bc, nv))) {
         release();
         return rc;
     }
@@ -1519,20 +1522,21 @@ extern "C" int fork_bc(fork_ctx* c, uint32_t first, uint32_t n, double* out) {
     uint32_t herr = 0;
     hipError_t e = hipMemcpy(d_off, off.data(), n * 8ull, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_src, src.data(), n * 4ull, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_qw, qw.data(), n * 4ull, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(d_bc, 0, nv * sizeof(double));
     if (e == hipSuccess) e = hipMemset(d_err, 0, 4);
     if (e == hipSuccess)
-        e = fk::launch_bc(c->d_state, d_off, d_src, n, c->nv, c->d_rowptr, c->d_col, c->d_rrow, c->d_rcol, d_order,
-                          d_ls, d_sigma, d_delta, d_gain, d_bc, d_err, nullptr);
+        e = fk::launch_bc(c->d_state, d_off, d_src, d_qw, n, c->nv, c->d_rowptr, c->d_col, c->d_w, (uint32_t)c->wbytes,
+                          c->d_rrow, c->d_rcol, c->d_reid, d_order, d_ls, d_lsig, d_delta, d_bc, d_err, nullptr);
     if (e == hipSuccess) e = hipMemcpy(h.data(), d_bc, nv * sizeof(double), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(&herr, d_err, 4, hipMemcpyDeviceToHost);
     release();
     if (e != hipSuccess) return fail(FORK_E_DEVICE, "bc: %s", hipGetErrorString(e));
-    if (herr) return fail(FORK_E_CAPACITY, "a query has more than %u BFS levels", fk::bc_level_cap());
+    if (herr)
+        return fail(FORK_E_CAPACITY, "a query's BFS levels or SSSP distances reach %u or more (the value range "
+                    "fork_bc sorts by)", fk::bc_level_cap());
     for (size_t v = 0; v < nv; ++v)
-        if (!std::isfinite(h[v]))
-            return fail(FORK_E_CAPACITY, "path-count ratios within a BFS level leave the fp64 range (vertex %zu); "
-                        "the graph has too many shortest paths of too uneven counts", v);
+        if (!std::isfinite(h[v])) return fail(FORK_E_DEVICE, "bc: non-finite dependency at vertex %zu", v);
     if (c->h_pos.empty()) memcpy(out, h.data(), nv * sizeof(double));
     else for (size_t v = 0; v < nv; ++v) out[v] = h[c->h_pos[v]];
     return FORK_OK;

@@ -271,12 +271,16 @@ __global__ void k_indeg(const uint32_t* col, unsigned long long ne, uint32_t* in
          e += (unsigned long long)gridDim.x * blockDim.x)
         atomicAdd(&indeg[col[e]], 1u);
 }
+// In-edges: rcol[k] = source of in-edge k, reid[k] = its index among the
+// out-edges (for its weight).
 __global__ void k_rfill(const uint32_t* rowptr, const uint32_t* col, uint32_t nv, const uint32_t* rrow,
-                        uint32_t* cursor, uint32_t* rcol) {
+                        uint32_t* cursor, uint32_t* rcol, uint32_t* reid) {
     for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nv; u += gridDim.x * blockDim.x)
         for (uint32_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
             const uint32_t w = col[e];
-            rcol[rrow[w] + atomicAdd(&cursor[w], 1u)] = u;
+            const uint32_t k = rrow[w] + atomicAdd(&cursor[w], 1u);
+            rcol[k] = u;
+            reid[k] = e;
         }
 }
 __global__ void k_sdeg(const uint32_t* rowptr, const uint32_t* rrow, uint32_t nv, uint32_t* sdeg) {
@@ -289,8 +293,8 @@ hipError_t launch_indeg(const uint32_t* col, unsigned long long ne, uint32_t* in
     return hipGetLastError();
 }
 hipError_t launch_rfill(const uint32_t* rowptr, const uint32_t* col, uint32_t nv, const uint32_t* rrow,
-                        uint32_t* cursor, uint32_t* rcol, hipStream_t s) {
-    hipLaunchKernelGGL(k_rfill, dim3(2048), dim3(256), 0, s, rowptr, col, nv, rrow, cursor, rcol);
+                        uint32_t* cursor, uint32_t* rcol, uint32_t* reid, hipStream_t s) {
+    hipLaunchKernelGGL(k_rfill, dim3(2048), dim3(256), 0, s, rowptr, col, nv, rrow, cursor, rcol, reid);
     return hipGetLastError();
 }
 hipError_t launch_sdeg(const uint32_t* rowptr, const uint32_t* rrow, uint32_t nv, uint32_t* sdeg, hipStream_t s) {
@@ -309,52 +313,57 @@ hipError_t launch_sweep(const uint32_t* state, const unsigned long long* qoff, u
 size_t sweep_out_bytes() { return sizeof(SweepOut); }
 
 // ------------------------------------------------------------ betweenness
-// Brandes' accumulation over resident BFS queries (the BC application of
-// Sections 2 and 6.1: many BFSs from sampled sources, then dependencies).
-// One workgroup per query, in three steps over the query's levels:
-//   1. counting sort of the reached vertices by level (per-query scratch);
-//   2. sigma (shortest-path counts, fp64), level by level: sigma(v) = sum
-//      over in-edges (u, v) with level(u) = level(v) - 1 of sigma(u).  Counts
-//      grow exponentially with depth (a 2048 x 2048 grid has about 10^1230
-//      corner-to-corner paths), so each level is stored divided by its
-//      largest count m_l: s(v) = sigma(v) / (m_1 ... m_l), and only the
-//      per-level factor g_l = m_l (relative to the level before) is kept;
-//   3. delta, from the deepest level up: delta(v) = sum over out-edges (v, w)
-//      with level(w) = level(v) + 1 of sigma(v) / sigma(w) * (1 + delta(w)),
-//      where sigma(v) / sigma(w) = s(v) / (s(w) * g_(l+1)); every vertex but
-//      the source adds delta(v) to bc[v].
+// Brandes' accumulation over resident BFS or SSSP queries (the BC application
+// of Sections 2 and 6.1: many BFSs from sampled sources, then dependencies;
+// on a weighted graph the same with SSSP).  The shortest-path DAG of a source
+// holds the edges (u, v) with value(u) + w(u, v) = value(v), w = 1 for BFS.
+// One workgroup per query, in three steps:
+//   1. counting sort of the reached vertices by value (BFS level or SSSP
+//      distance; per-query scratch).  With weights >= 1 a DAG edge raises the
+//      value by at least one, so the vertices of one value are independent;
+//   2. path counts sigma in order of increasing value: sigma(v) = sum over
+//      DAG in-edges (u, v) of sigma(u).  Counts grow exponentially with depth
+//      (a 2048 x 2048 grid has about 10^1230 corner-to-corner paths), so each
+//      is kept as its natural logarithm, summed as log-sum-exp around the
+//      largest term;
+//   3. dependencies in order of decreasing value: delta(v) = sum over DAG
+//      out-edges (v, w) of sigma(v) / sigma(w) * (1 + delta(w)), the ratio
+//      taken as exp of the difference of logarithms (at most 1: sigma(w)
+//      includes sigma(v)); every vertex but the source adds delta(v) to bc[v].
 constexpr int BC_NT = 1024;
-constexpr uint32_t BC_LMAX = 16384;  // most levels per query (the scratch size)
+constexpr uint32_t BC_LMAX = 65536;  // values a query's reached vertices may span (the scratch size)
 
 struct BcScratch {
-    uint32_t* order;     // [nq][nv] vertices by level
-    uint32_t* lstart;    // [nq][BC_LMAX + 2] level starts (then fill cursors)
-    double* sigma;       // [nq][nv] path counts, scaled per level
+    uint32_t* order;     // [nq][nv] vertices by value
+    uint32_t* lstart;    // [nq][BC_LMAX + 2] value starts (then fill cursors)
+    double* lsig;        // [nq][nv] ln sigma
     double* delta;       // [nq][nv]
-    double* gain;        // [nq][BC_LMAX + 2] per-level scale factors
 };
 
+__device__ __forceinline__ uint32_t bc_weight(const void* w, uint32_t wb, uint32_t e) {
+    return wb == 0 ? 1u : wb == 1 ? ((const uint8_t*)w)[e] : wb == 2 ? ((const uint16_t*)w)[e] : ((const uint32_t*)w)[e];
+}
+
 __global__ __launch_bounds__(BC_NT) void k_bc(const uint32_t* state, const unsigned long long* qoff, const uint32_t* src,
-                                             uint32_t nv, const uint32_t* rowptr, const uint32_t* col,
-                                             const uint32_t* rrow, const uint32_t* rcol, BcScratch sc, double* bc,
+                                             const uint32_t* qweighted, uint32_t nv, const uint32_t* rowptr,
+                                             const uint32_t* col, const void* w, uint32_t wb, const uint32_t* rrow,
+                                             const uint32_t* rcol, const uint32_t* reid, BcScratch sc, double* bc,
                                              uint32_t* err) {
     const uint32_t t = threadIdx.x, q = blockIdx.x;
-    const uint32_t* level = state + qoff[q];
+    const uint32_t* val = state + qoff[q];
+    const uint32_t qwb = qweighted[q] ? wb : 0u;  // BFS: unit steps
     uint32_t* order = sc.order + (unsigned long long)q * nv;
     uint32_t* ls = sc.lstart + (unsigned long long)q * (BC_LMAX + 2);
-    double* sigma = sc.sigma + (unsigned long long)q * nv;
+    double* lsig = sc.lsig + (unsigned long long)q * nv;
     double* delta = sc.delta + (unsigned long long)q * nv;
-    double* gain = sc.gain + (unsigned long long)q * (BC_LMAX + 2);
     __shared__ uint32_t s_max, s_bad;
-    __shared__ unsigned long long s_lmax;
     __shared__ uint32_t s_w[BC_NT / WAVE];
     if (t == 0) { s_max = 0; s_bad = 0; }
     for (uint32_t i = t; i < BC_LMAX + 2; i += BC_NT) ls[i] = 0;
     __syncthreads();
-    // 1. level histogram
+    // 1. value histogram
     for (uint32_t v = t; v < nv; v += BC_NT) {
-        const uint32_t l = level[v];
-        sigma[v] = 0.0;
+        const uint32_t l = val[v];
         delta[v] = 0.0;
         if (l == INF) continue;
         if (l >= BC_LMAX) { s_bad = 1; continue; }
@@ -366,65 +375,67 @@ __global__ __launch_bounds__(BC_NT) void k_bc(const uint32_t* state, const unsig
         if (t == 0) atomicOr(err, 1u);
         return;
     }
-    const uint32_t L = s_max;  // deepest level
-    // exclusive prefix over levels 0..L (ls[l] = start of level l), chunked by the block
+    const uint32_t L = s_max;  // largest value
+    // exclusive prefix over values 0..L (ls[l] = start of value l), chunked by the block
     uint32_t carry = 0;
     for (uint32_t b0 = 0; b0 <= L + 1; b0 += BC_NT) {
         const uint32_t i = b0 + t;
         uint32_t x = i <= L + 1 ? ls[i] : 0u;
-        const uint32_t lane = t & (WAVE - 1), w = t / WAVE;
+        const uint32_t lane = t & (WAVE - 1), wv = t / WAVE;
         uint32_t incl = wscan_incl(x, lane);
-        if (lane == WAVE - 1) s_w[w] = incl;
+        if (lane == WAVE - 1) s_w[wv] = incl;
         __syncthreads();
         uint32_t before = 0, tot = 0;
-        for (uint32_t k = 0; k < BC_NT / WAVE; ++k) { before += k < w ? s_w[k] : 0u; tot += s_w[k]; }
+        for (uint32_t k = 0; k < BC_NT / WAVE; ++k) { before += k < wv ? s_w[k] : 0u; tot += s_w[k]; }
         __syncthreads();
-        if (i <= L + 1) ls[i] = carry + before + incl;  // inclusive over shifted counts = start of level i
+        if (i <= L + 1) ls[i] = carry + before + incl;  // inclusive over shifted counts = start of value i
         carry += tot;
         __syncthreads();
     }
-    // scatter: ls[l] (the start of level l) is level l's fill cursor, so it
-    // ends as the end of level l; level l then spans [ls[l - 1], ls[l]) (from 0 for l = 0)
+    // scatter: ls[l] (the start of value l) is value l's fill cursor, so it
+    // ends as the end of value l; value l then spans [ls[l - 1], ls[l]) (from 0 for l = 0)
     for (uint32_t v = t; v < nv; v += BC_NT) {
-        const uint32_t l = level[v];
+        const uint32_t l = val[v];
         if (l == INF) continue;
         order[atomicAdd(&ls[l], 1u)] = v;
     }
     __syncthreads();
-    // 2. sigma
-    if (t == 0) sigma[src[q]] = 1.0;
+    // 2. ln sigma (the source: ln 1 = 0)
+    if (t == 0) lsig[src[q]] = 0.0;
     __syncthreads();
     for (uint32_t l = 1; l <= L; ++l) {
         const uint32_t b = ls[l - 1], e = ls[l];
-        if (t == 0) s_lmax = 0ull;
-        __syncthreads();
         for (uint32_t i = b + t; i < e; i += BC_NT) {
             const uint32_t v = order[i];
-            double s = 0.0;
+            // log-sum-exp over the DAG in-edges: the largest term first, then the sum around it
+            double m = -INFINITY;
             for (uint32_t k = rrow[v]; k < rrow[v + 1]; ++k) {
                 const uint32_t u = rcol[k];
-                if (level[u] == l - 1) s += sigma[u];
+                const uint32_t du = val[u];
+                if (du != INF && (unsigned long long)du + bc_weight(w, qwb, reid[k]) == l) m = fmax(m, lsig[u]);
             }
-            sigma[v] = s;
-            atomicMax(&s_lmax, (unsigned long long)__double_as_longlong(s));  // positive doubles order like their bits
+            double sum = 0.0;
+            for (uint32_t k = rrow[v]; k < rrow[v + 1]; ++k) {
+                const uint32_t u = rcol[k];
+                const uint32_t du = val[u];
+                if (du != INF && (unsigned long long)du + bc_weight(w, qwb, reid[k]) == l) sum += exp(lsig[u] - m);
+            }
+            lsig[v] = m + log(sum);  // every reached vertex but the source has a DAG in-edge
         }
-        __syncthreads();
-        const double m = __longlong_as_double((long long)s_lmax);  // > 0: every vertex of the level has a predecessor
-        for (uint32_t i = b + t; i < e; i += BC_NT) sigma[order[i]] /= m;
-        if (t == 0) gain[l] = m;
         __syncthreads();
     }
     // 3. delta
     for (int l = (int)L - 1; l >= 0; --l) {
         const uint32_t b = l ? ls[l - 1] : 0u, e = ls[l];
-        const double gnext = gain[l + 1];
         for (uint32_t i = b + t; i < e; i += BC_NT) {
             const uint32_t v = order[i];
             double a = 0.0;
-            const double sv = sigma[v];
+            const double sv = lsig[v];
             for (uint32_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
-                const uint32_t w = col[k];
-                if (level[w] == (uint32_t)l + 1) a += sv / (sigma[w] * gnext) * (1.0 + delta[w]);
+                const uint32_t x = col[k];
+                const uint32_t dx = val[x];
+                if (dx != INF && (unsigned long long)l + bc_weight(w, qwb, k) == dx)
+                    a += exp(sv - lsig[x]) * (1.0 + delta[x]);
             }
             delta[v] = a;
         }
@@ -432,16 +443,18 @@ __global__ __launch_bounds__(BC_NT) void k_bc(const uint32_t* state, const unsig
     }
     const uint32_t s0 = src[q];
     for (uint32_t v = t; v < nv; v += BC_NT)
-        if (v != s0 && level[v] != INF && delta[v] != 0.0) atomicAdd(&bc[v], delta[v]);
+        if (v != s0 && val[v] != INF && delta[v] != 0.0) atomicAdd(&bc[v], delta[v]);
 }
 
-hipError_t launch_bc(const uint32_t* state, const unsigned long long* qoff, const uint32_t* src, uint32_t nq,
-                     uint32_t nv, const uint32_t* rowptr, const uint32_t* col, const uint32_t* rrow,
-                     const uint32_t* rcol, uint32_t* order, uint32_t* lstart, double* sigma, double* delta,
-                     double* gain, double* bc, uint32_t* err, hipStream_t s) {
+hipError_t launch_bc(const uint32_t* state, const unsigned long long* qoff, const uint32_t* src,
+                     const uint32_t* qweighted, uint32_t nq, uint32_t nv, const uint32_t* rowptr, const uint32_t* col,
+                     const void* w, uint32_t wb, const uint32_t* rrow, const uint32_t* rcol, const uint32_t* reid,
+                     uint32_t* order, uint32_t* lstart, double* lsig, double* delta, double* bc, uint32_t* err,
+                     hipStream_t s) {
     if (nq == 0) return hipSuccess;
-    BcScratch sc{order, lstart, sigma, delta, gain};
-    hipLaunchKernelGGL(k_bc, dim3(nq), dim3(BC_NT), 0, s, state, qoff, src, nv, rowptr, col, rrow, rcol, sc, bc, err);
+    BcScratch sc{order, lstart, lsig, delta};
+    hipLaunchKernelGGL(k_bc, dim3(nq), dim3(BC_NT), 0, s, state, qoff, src, qweighted, nv, rowptr, col, w, wb, rrow,
+                       rcol, reid, sc, bc, err);
     return hipGetLastError();
 }
 uint32_t bc_level_cap() { return BC_LMAX; }
