@@ -205,6 +205,8 @@ def main():
     ap.add_argument("--retune", action="store_true", help="with --tune: search again even if a result is cached")
     ap.add_argument("--tune-sample", type=int, default=1024, help="queries per autotuner trial")
     ap.add_argument("--no-tuned", action="store_true", help="ignore cached autotuner results")
+    ap.add_argument("--tune-from-cache", action="store_true",
+                    help="with --tune: start from the cached knobs (e.g. a smaller subset's) and keep their engine")
     ap.add_argument("--compare-learned", default="auto", help="MLP weights (.npy): also time the learned scheduler "
                     "on the same workload and report the speedup over the rule-based one ('auto': the weights "
                     "shipped with the package for this graph family; 'none': skip)")
@@ -262,8 +264,10 @@ def main():
     params, source = dict(autotune.DEFAULTS), "defaults"
     if not args.no_tuned:
         t_tune = time.perf_counter()
+        start = autotune.cached(g, queries, spec) if args.tune_from_cache else None
         tuned = autotune.tune(g, queries, spec, log=lambda *a: print(*a, file=sys.stderr, flush=True),
-                              use_cache=not args.retune, sample=args.tune_sample) \
+                              use_cache=not args.retune, sample=args.tune_sample, start=start,
+                              fixed=("engine",) if start else ()) \
             if args.tune else autotune.cached(g, queries, spec)
         if tuned:
             tuned = dict(tuned)

@@ -160,20 +160,27 @@ def candidates(g, queries) -> dict:
     return c
 
 
-def tune(g, queries, spec, sample=256, rounds=1, budget_s=240.0, log=print, use_cache=True) -> dict:
+def tune(g, queries, spec, sample=256, rounds=1, budget_s=240.0, log=print, use_cache=True, start=None,
+         fixed=()) -> dict:
+    """Coordinate descent from `start` (default: the defaults) over every
+    knob not named in `fixed`.  A large batch starts from the knobs of a tuned
+    subset and fixes the engine, so that no trial runs minutes on a slow
+    configuration."""
     key = f"{signature(g, queries, spec)}|{device_name()}"
     cache = _load_cache()
     if use_cache and key in cache:
         return cache[key]["params"]
     smp = _sample(queries, sample)
-    best = dict(DEFAULTS)
+    best = dict(DEFAULTS, **{k: v for k, v in (start or {}).items() if k in DEFAULTS})
     best_v = _trial(g, smp, spec, best)
-    log(f"[tune] default {best} -> {best_v:.1f} q/s")
+    log(f"[tune] start {best} -> {best_v:.1f} q/s")
     trials = [{"params": dict(best), "qps": best_v}]
     t_start = time.time()
     space = candidates(g, queries)
     for _ in range(rounds):
         for name, values in space.items():
+            if name in fixed:
+                continue
             for v in values:
                 if v == best[name] or time.time() - t_start > budget_s:
                     continue
