@@ -410,8 +410,9 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
     const uint32_t lane = lane_id();
     const bool ppr = c.qt == Q_PPR;
     const uint32_t ntask = (nedge + GW - 1) / GW;
-    // wave-uniform counts of this wave's tasks
-    uint32_t n_edges = 0, n_intra = 0, n_imp = 0, n_act = 0, n_tasks = 0;
+    // counts of this wave's tasks: wave-uniform, or per lane (summed at the end)
+    uint32_t n_imp = 0, n_act = 0, n_tasks = 0;
+    uint32_t n_lane_edges = 0, n_lane_intra = 0;
     // the mark begun in the previous step (one per lane 0..UNR-1): target,
     // priority and the mask's old value, finished while the next step's
     // memory operations are in flight
@@ -422,7 +423,7 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
     for (;;) {
         uint32_t task = 0;
         if (lane == 0) task = atomicAdd(&S.next, 1u);
-        task = __shfl(task, 0);
+        task = (uint32_t)__builtin_amdgcn_readfirstlane((int)task);
         if (task >= ntask) break;
         ++n_tasks;
         const uint32_t f = task * GW + lane;
@@ -438,21 +439,24 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
             if (!ppr && WB != 0 && c.qt != Q_BFS) myw = edge_w<WB>(c.g.w, e);
             if (ppr) mythr = (float)(c.g.rowptr[myu + 1] - c.g.rowptr[myu]);  // degree, scaled per lane below
         }
-        const bool my_intra = myu - c.v0 < c.nvp;
         uint32_t kprev = 0xffffffffu, dprev = INF;
         float sprev = 0.f;
         bool aprev = false;
+        // edge j0 + j's source, target and weight are the same for every lane:
+        // read them from lane (j0 + j) into scalar registers
         for (uint32_t j0 = 0; j0 < cnt; j0 += UNR) {
-            uint32_t u[UNR];   // targets of edges j0 .. j0 + UNR - 1
+            uint32_t u[UNR];   // targets of edges j0 .. j0 + UNR - 1 (wave-uniform)
             uint32_t x[UNR];   // SSSP/BFS: distance through the edge; PPR: the pushed share (float bits)
             uint32_t y[UNR];   // SSSP/BFS: the target's value, then its old value at the atomic min (0: none);
                                // PPR: the target's residual before the push (float bits)
             uint32_t actm = 0; // bit j: this lane relaxes / pushes along edge j0 + j
+            uint32_t imask = 0;  // bit j: edge j0 + j stays in the partition (wave-uniform)
 #pragma unroll
             for (int j = 0; j < UNR; ++j) {
-                const bool ok = j0 + j < cnt;
-                const uint32_t kj = __shfl(myk, (int)(j0 + j) & (GW - 1));
-                u[j] = __shfl(myu, (int)(j0 + j) & (GW - 1));
+                const uint32_t fj = j0 + j;
+                const bool ok = fj < cnt;
+                const uint32_t kj = (uint32_t)__builtin_amdgcn_readlane((int)myk, (int)(fj & (GW - 1)));
+                u[j] = (uint32_t)__builtin_amdgcn_readlane((int)myu, (int)(fj & (GW - 1)));
                 if (ok && kj != kprev) {  // a new source vertex (uniform): its mask and this lane's value
                     kprev = kj;
                     const unsigned long long m = S.rm[kj];
@@ -461,14 +465,17 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
                     else dprev = aprev ? SH.sd[kj][lane] : INF;
                 }
                 actm |= (ok && aprev) ? (1u << j) : 0u;
+                imask |= (ok && u[j] - c.v0 < c.nvp) ? (1u << j) : 0u;
                 if (ppr) {
                     x[j] = __float_as_uint(sprev);
                 } else {
-                    const uint32_t w = __shfl(myw, (int)(j0 + j) & (GW - 1));
-                    const unsigned long long sum = (unsigned long long)dprev + w;
-                    x[j] = sum >= INF ? INF - 1 : (uint32_t)sum;
+                    const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)myw, (int)(fj & (GW - 1)));
+                    const uint32_t sum = dprev + w;  // dprev < INF: no wrap unless the path is too long
+                    x[j] = (sum < dprev || sum >= INF) ? INF - 1 : sum;
                 }
             }
+            n_lane_edges += (uint32_t)__popc(actm);
+            n_lane_intra += (uint32_t)__popc(actm & imask);
             if (ppr) {
 #pragma unroll
                 for (int j = 0; j < UNR; ++j)
@@ -496,7 +503,8 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
                 bool hit;
                 uint32_t val;
                 if (ppr) {
-                    const float du = __shfl(mythr, (int)(j0 + j) & (GW - 1));
+                    const float du = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mythr),
+                                                                              (int)((j0 + j) & (GW - 1))));
                     const float thu = c.mode ? c.eps * du : c.eps;
                     const float old = __uint_as_float(y[j]);
                     const float nr_ = old + __uint_as_float(x[j]);
@@ -507,13 +515,11 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
                     val = x[j];
                 }
                 const unsigned long long bm = wballot(hit);
-                const uint32_t first = bm ? (uint32_t)(__ffsll(bm) - 1) : 0u;
-                const uint32_t vj = __shfl(val, (int)first);
-                if (lane == (uint32_t)j) { mine_bits = bm; mine_val = vj; mine_u = u[j]; }
-                const uint32_t na = (uint32_t)__popcll(wballot(act));
-                n_edges += na;
-                n_intra += __shfl(my_intra ? 1u : 0u, (int)(j0 + j) & (GW - 1)) * na;
-                n_imp += ppr ? 0u : (uint32_t)__popcll(bm);
+                if (bm) {  // uniform
+                    const uint32_t vj = (uint32_t)__builtin_amdgcn_readlane((int)val, __ffsll(bm) - 1);
+                    if (lane == (uint32_t)j) { mine_bits = bm; mine_val = vj; mine_u = u[j]; }
+                    n_imp += ppr ? 0u : (uint32_t)__popcll(bm);
+                }
             }
             if (mine_bits) {
                 pm_old = gmark_begin(c, mine_u, mine_bits);
@@ -524,8 +530,13 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
         }
     }
     if (pm_on) n_act += gmark_end(c, S, pm_u, pm_old, pm_val) ? 1u : 0u;
-    // n_act counted per lane (lanes 0..UNR-1 mark); the rest are wave-uniform
-    for (int o = 32; o; o >>= 1) n_act += __shfl_xor(n_act, o);
+    // n_act counted per lane (lanes 0..UNR-1 mark), and the lane-edges
+    uint32_t n_edges = n_lane_edges, n_intra = n_lane_intra;
+    for (int o = 32; o; o >>= 1) {
+        n_act += __shfl_xor(n_act, o);
+        n_edges += __shfl_xor(n_edges, o);
+        n_intra += __shfl_xor(n_intra, o);
+    }
     gcount(S, K_EDGES, n_edges);
     if (ppr) gcount(S, K_EDGES_PPR, n_edges);
     gcount(S, K_INTRA, n_intra);

@@ -139,6 +139,7 @@ inline uint32_t mbcnt_hi(uint32_t m, uint32_t acc) {
 #define __builtin_amdgcn_mbcnt_lo(m, a) simt::mbcnt_lo((m), (a))
 #define __builtin_amdgcn_mbcnt_hi(m, a) simt::mbcnt_hi((m), (a))
 #define __builtin_amdgcn_readfirstlane(v) ((uint32_t)simt::wave_op(4, (uint64_t)(uint32_t)(v), 0))
+#define __builtin_amdgcn_readlane(v, l) ((int)(uint32_t)simt::wave_op(0, (uint64_t)(uint32_t)(v), (int)(l)))
 #define __builtin_amdgcn_fence(o, s) __atomic_thread_fence(__ATOMIC_SEQ_CST)
 #define __builtin_amdgcn_wave_barrier() simt::wave_barrier()
 inline unsigned long long wall_clock64() {
