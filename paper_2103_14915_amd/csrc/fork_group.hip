@@ -405,10 +405,9 @@ __device__ void gfilter_ppr(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr) {
 // edge's source relaxes (SSSP/BFS: atomic min of the target row's entry) or
 // pushes to (PPR: atomic add of its share) the target, and the lanes
 // 0..UNR-1 mark the newly pending targets in parallel.
-template <int WB>
+template <int WB, bool ppr>
 __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t nedge) {
     const uint32_t lane = lane_id();
-    const bool ppr = c.qt == Q_PPR;
     const uint32_t ntask = (nedge + GW - 1) / GW;
     // counts of this wave's tasks: wave-uniform, or per lane (summed at the end)
     uint32_t n_imp = 0, n_act = 0, n_tasks = 0;
@@ -436,8 +435,10 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
             const uint32_t v = c.v0 + S.rv[myk];
             const uint32_t e = c.g.rowptr[v] + (f - S.rnt[myk]);
             myu = c.g.col[e];
-            if (!ppr && WB != 0 && c.qt != Q_BFS) myw = edge_w<WB>(c.g.w, e);
-            if (ppr) mythr = (float)(c.g.rowptr[myu + 1] - c.g.rowptr[myu]);  // degree, scaled per lane below
+            if constexpr (!ppr) {
+                if (WB != 0 && c.qt != Q_BFS) myw = edge_w<WB>(c.g.w, e);
+            }
+            if constexpr (ppr) mythr = (float)(c.g.rowptr[myu + 1] - c.g.rowptr[myu]);  // degree, scaled per lane below
         }
         uint32_t kprev = 0xffffffffu, dprev = INF;
         float sprev = 0.f;
@@ -461,12 +462,12 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
                     kprev = kj;
                     const unsigned long long m = S.rm[kj];
                     aprev = (m >> lane) & 1ull;
-                    if (ppr) sprev = SH.share[kj][lane];
+                    if constexpr (ppr) sprev = SH.share[kj][lane];
                     else dprev = aprev ? SH.sd[kj][lane] : INF;
                 }
                 actm |= (ok && aprev) ? (1u << j) : 0u;
                 imask |= (ok && u[j] - c.v0 < c.nvp) ? (1u << j) : 0u;
-                if (ppr) {
+                if constexpr (ppr) {
                     x[j] = __float_as_uint(sprev);
                 } else {
                     const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)myw, (int)(fj & (GW - 1)));
@@ -476,7 +477,7 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
             }
             n_lane_edges += (uint32_t)__popc(actm);
             n_lane_intra += (uint32_t)__popc(actm & imask);
-            if (ppr) {
+            if constexpr (ppr) {
 #pragma unroll
                 for (int j = 0; j < UNR; ++j)
                     y[j] = ((actm >> j) & 1u) ? __float_as_uint(__hip_atomic_fetch_add(
@@ -502,7 +503,7 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
                 const bool act = (actm >> j) & 1u;
                 bool hit;
                 uint32_t val;
-                if (ppr) {
+                if constexpr (ppr) {
                     const float du = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mythr),
                                                                               (int)((j0 + j) & (GW - 1))));
                     const float thu = c.mode ? c.eps * du : c.eps;
@@ -518,7 +519,7 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
                 if (bm) {  // uniform
                     const uint32_t vj = (uint32_t)__builtin_amdgcn_readlane((int)val, __ffsll(bm) - 1);
                     if (lane == (uint32_t)j) { mine_bits = bm; mine_val = vj; mine_u = u[j]; }
-                    n_imp += ppr ? 0u : (uint32_t)__popcll(bm);
+                    if constexpr (!ppr) n_imp += (uint32_t)__popcll(bm);
                 }
             }
             if (mine_bits) {
@@ -538,7 +539,7 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
         n_intra += __shfl_xor(n_intra, o);
     }
     gcount(S, K_EDGES, n_edges);
-    if (ppr) gcount(S, K_EDGES_PPR, n_edges);
+    if constexpr (ppr) gcount(S, K_EDGES_PPR, n_edges);
     gcount(S, K_INTRA, n_intra);
     gcount(S, K_IMPROVED, n_imp);
     gcount(S, K_ACT, n_act);
@@ -621,7 +622,8 @@ __device__ void gvisit(GCtx& c, GShared& S, GCtxShare& SH, const PassCfg& cfg) {
         if (t == 0) { S.next = 0; S.cnt[K_ROUNDS] += 1; }
         __syncthreads();
         phase(K_T_FILTER);
-        gtasks<WB>(c, S, SH, nr, nedge);
+        if (ppr) gtasks<WB, true>(c, S, SH, nr, nedge);
+        else gtasks<WB, false>(c, S, SH, nr, nedge);
         __syncthreads();
         phase(K_T_TASKS);
         if (budget && S.edges >= budget) break;
