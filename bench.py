@@ -205,6 +205,8 @@ def main():
     ap.add_argument("--retune", action="store_true", help="with --tune: search again even if a result is cached")
     ap.add_argument("--tune-sample", type=int, default=1024, help="queries per autotuner trial")
     ap.add_argument("--no-tuned", action="store_true", help="ignore cached autotuner results")
+    ap.add_argument("--tune-budget", type=float, default=240.0, help="seconds of autotuner trials")
+    ap.add_argument("--tune-knobs", default="", help="comma-separated knobs to search (default: all)")
     ap.add_argument("--tune-from-cache", action="store_true",
                     help="with --tune: start from the cached knobs (e.g. a smaller subset's) and keep their engine")
     ap.add_argument("--compare-learned", default="auto", help="MLP weights (.npy): also time the learned scheduler "
@@ -265,9 +267,10 @@ def main():
     if not args.no_tuned:
         t_tune = time.perf_counter()
         start = autotune.cached(g, queries, spec) if args.tune_from_cache else None
+        fixed = tuple(k for k in autotune.DEFAULTS if args.tune_knobs and k not in args.tune_knobs.split(","))
         tuned = autotune.tune(g, queries, spec, log=lambda *a: print(*a, file=sys.stderr, flush=True),
                               use_cache=not args.retune, sample=args.tune_sample, start=start,
-                              fixed=("engine",) if start else ()) \
+                              fixed=fixed or (("engine",) if start else ()), budget_s=args.tune_budget) \
             if args.tune else autotune.cached(g, queries, spec)
         if tuned:
             tuned = dict(tuned)
