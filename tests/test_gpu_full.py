@@ -220,6 +220,41 @@ def test_rmat20_ppr_certified_sample():
         assert np.all(P[k] >= 0) and err <= 1e-4, (int(i), err)
 
 
+def test_rmat20_ppr_certified_on_frontier_sized_partitions():
+    """The scale-20 PPR workload's graph and its first 32 sources in the
+    L1-certified mode, on 1,024-vertex partitions (the largest the certified
+    mode accepts, so a refinement never overflows a visit's frontier): every
+    query ends with ||r||_1 <= 0.9e-4, no visit retains more activated
+    vertices than its partition holds, and a seeded sample of 4 queries is
+    within 1e-4 of fp64 power iteration in L1, never above it."""
+    fork = _fork()
+    spec = fi.WORKLOADS["rmat20_ppr4096"]
+    g = fi.make_graph(spec)
+    queries = fi.make_sources(g, spec)
+    srcs = queries[0][1][:32]
+    say("rmat20 certified ppr32 on 1024-vertex partitions")
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=1024)
+    fg.submit("ppr", srcs, alpha=spec["alpha"], epsilon=spec["epsilon"], eps_mode=spec["eps_mode"], l1_target=1e-4)
+    fg.run(engine="buffered")
+    st = fg.stats()
+    say("refine rounds", st["refine_rounds"], "edges", st["edges"], "spill_max", st["spill_max"],
+        "run_ms", round(st["run_ms"], 1))
+    assert st["refine_rounds"] >= 1 and st["spill_max"] <= 1024
+    for i in range(len(srcs)):
+        d = fg.digest(i)
+        assert 0.0 <= d["fres"] <= 0.9e-4 * (1 + 1e-6), (i, d["fres"])
+    idx = np.sort(np.random.default_rng(7).choice(len(srcs), 4, replace=False))
+    P = np.stack([fg.fetch(int(i), fork.FIELD_P) for i in idx]).astype(np.float64)
+    R = np.stack([fg.fetch(int(i), fork.FIELD_R) for i in idx]).astype(np.float64)
+    fg.close()
+    pi = oracle.ppr_exact(g, srcs[idx], spec["alpha"])
+    for k, i in enumerate(idx):
+        err = float(np.abs(P[k] - pi[k]).sum())
+        say("query", int(i), "L1 to power iteration", err, "||r||_1", float(R[k].sum()))
+        assert np.all(P[k] >= 0) and err <= 1e-4, (int(i), err)
+        assert err <= R[k].sum() + 1e-5, (int(i), err, float(R[k].sum()))
+
+
 def test_grid2048_sssp_bfs_full():
     fork = _fork()
     spec = fi.WORKLOADS["grid2048_sssp1024_bfs1024"]
