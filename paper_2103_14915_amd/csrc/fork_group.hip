@@ -405,6 +405,12 @@ __device__ void gfilter_ppr(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr) {
 // edge's source relaxes (SSSP/BFS: atomic min of the target row's entry) or
 // pushes to (PPR: atomic add of its share) the target, and the lanes
 // 0..UNR-1 mark the newly pending targets in parallel.
+//
+// SSSP/BFS steps are software-pipelined: a step's atomic minima are issued,
+// then the next step's row loads, and only then are the minima's old values
+// waited for.  Whether a lane improved a target is still decided by the
+// value its own atomic returned, so the marks are what the unpipelined loop
+// makes.
 template <int WB, bool ppr>
 __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t nedge) {
     const uint32_t lane = lane_id();
@@ -418,6 +424,9 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
     bool pm_on = false;
     uint32_t pm_u = 0, pm_val = 0;
     unsigned long long pm_old = 0;
+    // SSSP/BFS: the marks a step decided, begun during the next step
+    unsigned long long mk_bits = 0;
+    uint32_t mk_u = 0, mk_val = 0;
     const __amdgpu_buffer_rsrc_t rsrc = row_rsrc(c.st, c.g.nv);
     for (;;) {
         uint32_t task = 0;
@@ -443,15 +452,15 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
         uint32_t kprev = 0xffffffffu, dprev = INF;
         float sprev = 0.f;
         bool aprev = false;
-        // edge j0 + j's source, target and weight are the same for every lane:
-        // read them from lane (j0 + j) into scalar registers
-        for (uint32_t j0 = 0; j0 < cnt; j0 += UNR) {
-            uint32_t u[UNR];   // targets of edges j0 .. j0 + UNR - 1 (wave-uniform)
-            uint32_t x[UNR];   // SSSP/BFS: distance through the edge; PPR: the pushed share (float bits)
-            uint32_t y[UNR];   // SSSP/BFS: the target's value, then its old value at the atomic min (0: none);
-                               // PPR: the target's residual before the push (float bits)
-            uint32_t actm = 0; // bit j: this lane relaxes / pushes along edge j0 + j
-            uint32_t imask = 0;  // bit j: edge j0 + j stays in the partition (wave-uniform)
+        // Step j0's edges: targets u (wave-uniform), this lane's value through
+        // each edge x (SSSP/BFS: distance; PPR: the pushed share's bits), and
+        // the masks actm (bit j: this lane relaxes / pushes along edge j0 + j)
+        // and imask (bit j: edge j0 + j stays in the partition).  Edge j0 + j's
+        // source, target and weight are the same for every lane: they are read
+        // from lane j0 + j into scalar registers.
+        auto gather = [&](uint32_t j0, uint32_t (&u)[UNR], uint32_t (&x)[UNR], uint32_t& actm, uint32_t& imask) {
+            actm = 0;
+            imask = 0;
 #pragma unroll
             for (int j = 0; j < UNR; ++j) {
                 const uint32_t fj = j0 + j;
@@ -475,9 +484,14 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
                     x[j] = (sum < dprev || sum >= INF) ? INF - 1 : sum;
                 }
             }
-            n_lane_edges += (uint32_t)__popc(actm);
-            n_lane_intra += (uint32_t)__popc(actm & imask);
-            if constexpr (ppr) {
+        };
+        if constexpr (ppr) {
+            for (uint32_t j0 = 0; j0 < cnt; j0 += UNR) {
+                uint32_t u[UNR], x[UNR], y[UNR];  // y: the target's residual before the push (float bits)
+                uint32_t actm, imask;
+                gather(j0, u, x, actm, imask);
+                n_lane_edges += (uint32_t)__popc(actm);
+                n_lane_intra += (uint32_t)__popc(actm & imask);
 #pragma unroll
                 for (int j = 0; j < UNR; ++j)
                     y[j] = ((actm >> j) & 1u) ? __float_as_uint(__hip_atomic_fetch_add(
@@ -485,52 +499,100 @@ __device__ void gtasks(GCtx& c, GShared& S, GCtxShare& SH, uint32_t nr, uint32_t
                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                                               : 0u;
                 if (pm_on) { pm_on = false; n_act += gmark_end(c, S, pm_u, pm_old, pm_val) ? 1u : 0u; }
-            } else {
+                // lane j marks the target of edge j0 + j for every lane that crossed its threshold
+                unsigned long long mine_bits = 0;
+                uint32_t mine_val = 0, mine_u = 0;
 #pragma unroll
-                for (int j = 0; j < UNR; ++j)
-                    y[j] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, ((actm >> j) & 1u) ? row_off(u[j], lane) : ROW_NONE,
-                                                                0, 0);
-                if (pm_on) { pm_on = false; n_act += gmark_end(c, S, pm_u, pm_old, pm_val) ? 1u : 0u; }
-#pragma unroll
-                for (int j = 0; j < UNR; ++j)
-                    y[j] = (((actm >> j) & 1u) && x[j] < y[j]) ? dev_min(rowp(c.st, u[j], lane), x[j]) : 0u;
-            }
-            // lane j marks the target of edge j0 + j for every lane that hit it
-            unsigned long long mine_bits = 0;
-            uint32_t mine_val = 0, mine_u = 0;
-#pragma unroll
-            for (int j = 0; j < UNR; ++j) {
-                const bool act = (actm >> j) & 1u;
-                bool hit;
-                uint32_t val;
-                if constexpr (ppr) {
+                for (int j = 0; j < UNR; ++j) {
+                    const bool act = (actm >> j) & 1u;
                     const float du = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mythr),
                                                                               (int)((j0 + j) & (GW - 1))));
                     const float thu = c.mode ? c.eps * du : c.eps;
                     const float old = __uint_as_float(y[j]);
                     const float nr_ = old + __uint_as_float(x[j]);
-                    hit = act && !ppr_active(old, thu) && ppr_active(nr_, thu);
-                    val = ~__float_as_uint(nr_);
-                } else {
-                    hit = x[j] < y[j];  // y[j] = 0 where no atomic was made
-                    val = x[j];
+                    const bool hit = act && !ppr_active(old, thu) && ppr_active(nr_, thu);
+                    const uint32_t val = ~__float_as_uint(nr_);
+                    const unsigned long long bm = wballot(hit);
+                    if (bm) {  // uniform
+                        const uint32_t vj = (uint32_t)__builtin_amdgcn_readlane((int)val, __ffsll(bm) - 1);
+                        if (lane == (uint32_t)j) { mine_bits = bm; mine_val = vj; mine_u = u[j]; }
+                    }
                 }
-                const unsigned long long bm = wballot(hit);
-                if (bm) {  // uniform
-                    const uint32_t vj = (uint32_t)__builtin_amdgcn_readlane((int)val, __ffsll(bm) - 1);
-                    if (lane == (uint32_t)j) { mine_bits = bm; mine_val = vj; mine_u = u[j]; }
-                    if constexpr (!ppr) n_imp += (uint32_t)__popcll(bm);
+                if (mine_bits) {
+                    pm_old = gmark_begin(c, mine_u, mine_bits);
+                    pm_u = mine_u;
+                    pm_val = mine_val;
+                    pm_on = true;
                 }
             }
-            if (mine_bits) {
-                pm_old = gmark_begin(c, mine_u, mine_bits);
-                pm_u = mine_u;
-                pm_val = mine_val;
-                pm_on = true;
+        } else {
+            // step A is the one being relaxed, step B the next one, whose row
+            // loads are in flight meanwhile
+            uint32_t uA[UNR], xA[UNR], yA[UNR], actA, imA;
+            gather(0, uA, xA, actA, imA);
+#pragma unroll
+            for (int j = 0; j < UNR; ++j)
+                yA[j] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, ((actA >> j) & 1u) ? row_off(uA[j], lane) : ROW_NONE,
+                                                             0, 0);
+            for (uint32_t j0 = 0; j0 < cnt; j0 += UNR) {
+                n_lane_edges += (uint32_t)__popc(actA);
+                n_lane_intra += (uint32_t)__popc(actA & imA);
+                // y: the target's value; then the old value at this lane's atomic min (0: none made).
+                // Which minima to make is decided for the whole step first (the empty asm keeps the
+                // mask opaque), so that every row load of the step is waited for before the first
+                // atomic is issued: a wait for one load issued after an atomic would wait for the
+                // atomic too.
+                uint32_t amask = 0;
+#pragma unroll
+                for (int j = 0; j < UNR; ++j) amask |= (((actA >> j) & 1u) && xA[j] < yA[j]) ? (1u << j) : 0u;
+                asm volatile("" : "+v"(amask));
+#pragma unroll
+                for (int j = 0; j < UNR; ++j)
+                    yA[j] = ((amask >> j) & 1u) ? dev_min(rowp(c.st, uA[j], lane), xA[j]) : 0u;
+                // the previous step's marks, begun now that this step's minima are in flight
+                if (mk_bits) {
+                    pm_old = gmark_begin(c, mk_u, mk_bits);
+                    pm_u = mk_u;
+                    pm_val = mk_val;
+                    pm_on = true;
+                    mk_bits = 0;
+                }
+                uint32_t uB[UNR], xB[UNR], yB[UNR], actB = 0, imB = 0;
+                const bool more = j0 + UNR < cnt;  // uniform
+                if (more) {
+                    gather(j0 + UNR, uB, xB, actB, imB);
+#pragma unroll
+                    for (int j = 0; j < UNR; ++j)
+                        yB[j] = __builtin_amdgcn_raw_buffer_load_b32(
+                            rsrc, ((actB >> j) & 1u) ? row_off(uB[j], lane) : ROW_NONE, 0, 0);
+                }
+                if (pm_on) { pm_on = false; n_act += gmark_end(c, S, pm_u, pm_old, pm_val) ? 1u : 0u; }
+                // lane j will mark the target of edge j0 + j for every lane that lowered it
+#pragma unroll
+                for (int j = 0; j < UNR; ++j) {
+                    const bool hit = xA[j] < yA[j];  // yA[j] = 0 where no atomic was made
+                    const unsigned long long bm = wballot(hit);
+                    if (bm) {  // uniform
+                        const uint32_t vj = (uint32_t)__builtin_amdgcn_readlane((int)xA[j], __ffsll(bm) - 1);
+                        if (lane == (uint32_t)j) { mk_bits = bm; mk_val = vj; mk_u = uA[j]; }
+                        n_imp += (uint32_t)__popcll(bm);
+                    }
+                }
+                if (more) {
+#pragma unroll
+                    for (int j = 0; j < UNR; ++j) {
+                        uA[j] = uB[j];
+                        xA[j] = xB[j];
+                        yA[j] = yB[j];
+                    }
+                    actA = actB;
+                    imA = imB;
+                }
             }
         }
     }
     if (pm_on) n_act += gmark_end(c, S, pm_u, pm_old, pm_val) ? 1u : 0u;
+    if (mk_bits) n_act += gmark(c, S, mk_u, mk_bits, mk_val) ? 1u : 0u;
     // n_act counted per lane (lanes 0..UNR-1 mark), and the lane-edges
     uint32_t n_edges = n_lane_edges, n_intra = n_lane_intra;
     for (int o = 32; o; o >>= 1) {
