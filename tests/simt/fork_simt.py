@@ -88,6 +88,11 @@ class SimtGraph:
         self._check(self.lib.fork_fetch(self.ctx, qid, field, out.ctypes.data, out.nbytes, 0))
         return out
 
+    def digest(self, qid):
+        d = fork.fork_digest()
+        self._check(self.lib.fork_fetch(self.ctx, qid, fork.FIELD_DIGEST, ctypes.byref(d), ctypes.sizeof(d), 0))
+        return {n: getattr(d, n) for n, _ in d._fields_}
+
     def stats(self):
         st = fork.fork_stats_t()
         self._check(self.lib.fork_stats(self.ctx, ctypes.byref(st), ctypes.sizeof(st)))

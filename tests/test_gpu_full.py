@@ -14,6 +14,7 @@ import pytest
 
 import fpp_inputs as fi
 import oracle
+from digests import sp_digest
 
 pytestmark = pytest.mark.gpu
 
@@ -39,23 +40,6 @@ RMAT_KNOBS = {"partition_vertices": 16384, "items_per_pass": 16384, "window": 16
 def knobs(g, queries, fallback=None):
     from paper_2103_14915_amd import autotune
     return autotune.cached(g, queries) or dict(fallback or autotune.DEFAULTS)
-
-
-def mix64(z):
-    """SplitMix64 finaliser (Steele, Lea, Flood 2014), vectorised over uint64."""
-    with np.errstate(over="ignore"):
-        z = (z + np.uint64(0x9E3779B97F4A7C15)).astype(np.uint64)
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-        return z ^ (z >> np.uint64(31))
-
-
-def sp_digest(vec):
-    v = np.flatnonzero(vec != np.int32(0x7FFFFFFF))
-    x = vec[v].astype(np.uint64)
-    with np.errstate(over="ignore"):
-        h = np.sum(mix64((v.astype(np.uint64) << np.uint64(32)) | x), dtype=np.uint64)
-    return int(v.size), int(x.sum()), int(h)
 
 
 def run_workload(fork, g, queries, spec, p):

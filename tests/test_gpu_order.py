@@ -8,6 +8,7 @@ import pytest
 
 import fpp_inputs as fi
 import oracle
+from digests import sp_digest
 from paper_2103_14915_amd import order
 
 pytestmark = pytest.mark.gpu
@@ -26,22 +27,6 @@ def _fork():
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def mix64(z):
-    with np.errstate(over="ignore"):
-        z = (z + np.uint64(0x9E3779B97F4A7C15)).astype(np.uint64)
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-        return z ^ (z >> np.uint64(31))
-
-
-def sp_digest(vec):
-    v = np.flatnonzero(vec != np.int32(0x7FFFFFFF))
-    x = vec[v].astype(np.uint64)
-    with np.errstate(over="ignore"):
-        h = np.sum(mix64((v.astype(np.uint64) << np.uint64(32)) | x), dtype=np.uint64)
-    return int(v.size), int(x.sum()), int(h)
 
 
 @pytest.mark.parametrize("seed,pv", [(1, 8), (2, 64), (3, 1024)])

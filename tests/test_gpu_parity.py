@@ -12,6 +12,7 @@ import pytest
 
 import fpp_inputs as fi
 import oracle
+from digests import sp_digest
 from golden_io import load_sp_fixture
 
 pytestmark = pytest.mark.gpu
@@ -152,28 +153,6 @@ def test_ppr_small_invariant(mode):
         R = np.stack([fg.fetch(i, fork.FIELD_R) for i in range(len(srcs))])
         fg.close()
         check_ppr(g, srcs, P, R, eps, mode)
-
-
-def mix64(z):
-    """SplitMix64 finaliser (Steele, Lea, Flood 2014), vectorised over uint64."""
-    with np.errstate(over="ignore"):
-        z = (z + np.uint64(0x9E3779B97F4A7C15)).astype(np.uint64)
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-        return z ^ (z >> np.uint64(31))
-
-
-def sp_digest(vec):
-    """(count, sum, hash) of an int32 distance vector, as the fork_digest docs define it."""
-    v = np.flatnonzero(vec != fork_inf())
-    x = vec[v].astype(np.uint64)
-    with np.errstate(over="ignore"):
-        h = np.sum(mix64((v.astype(np.uint64) << np.uint64(32)) | x), dtype=np.uint64)
-    return int(v.size), int(x.sum()), int(h)
-
-
-def fork_inf():
-    return np.int32(0x7FFFFFFF)
 
 
 def test_pool_exhaustion_splits_waves():

@@ -23,6 +23,7 @@ import pytest
 
 import fpp_inputs as fi
 import oracle
+from digests import sp_digest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, os.path.join(ROOT, "tests", "simt"))
@@ -45,22 +46,37 @@ def _clean(fs, lib):
 
 
 def test_sssp_and_bfs_exact_with_a_wrapping_free_ring(fs):
+    """A pool of 1,527 chunks reused many times over.  How many chunks are
+    held at once depends on how the workgroups interleave, so a run may also
+    split the queries into waves when the pool runs out (then only the last
+    wave's vectors stay resident): every query's digest is checked, and the
+    vectors of the resident ones."""
+    import paper_2103_14915_amd as fork
     lib = fs.load()
     fs.reset_checker(lib)
     g = fi.rmat(11, seed=21, weights=(1, 255), weight_seed=22)
     s_sp = fi.sources_uniform(g, 16, 1)
     s_bfs = fi.sources_uniform(g, 8, 2)
+    ref = list(oracle.sssp(g, s_sp)) + list(oracle.bfs(g, s_bfs))
     fg = fs.SimtGraph(lib, g, partition_vertices=128, pool_bytes=3 << 20)  # 1,527 chunks
     fg.submit("sssp", s_sp)
     fg.submit("bfs", s_bfs)
     fg.run(max_passes=100000)
-    d = np.stack([fg.fetch(i) for i in range(16)])
-    lv = np.stack([fg.fetch(16 + i) for i in range(8)])
     st = fg.stats()
+    resident = 0
+    for i in range(24):
+        d = fg.digest(i)
+        assert (d["count"], d["sum"], d["hash"]) == sp_digest(ref[i]), i
+        try:
+            got = fg.fetch(i)
+        except fork.ForkError as e:  # not resident
+            assert e.code == fork.FORK_E_STATE and st["waves"] > 1, i
+            continue
+        resident += 1
+        np.testing.assert_array_equal(got, ref[i], err_msg=f"query {i}")
     fg.close()
-    np.testing.assert_array_equal(d, oracle.sssp(g, s_sp))
-    np.testing.assert_array_equal(lv, oracle.bfs(g, s_bfs))
-    assert st["waves"] == 1 and st["chunks"] > 2 * 1527  # the pool's chunks were reused more than twice
+    assert resident >= 1 and (resident == 24) == (st["waves"] == 1)
+    assert st["chunks"] > 2 * 1527  # the pool's chunks were reused more than twice
     _clean(fs, lib)
 
 
