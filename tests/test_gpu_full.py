@@ -297,6 +297,34 @@ def test_sssp_ppr_mix_in_the_bench_configuration(name, take):
     fg.close()
 
 
+def test_rmat22_mixed_full_in_the_bench_configuration():
+    """All 16,384 queries of the scale-22 mixed batch (8,192 SSSP, 4,096 BFS,
+    4,096 PPR) on the knobs bench.py takes for it, tuned on a 512-per-type
+    subset of the same graph; the batch runs in several waves.  A seeded
+    sample per type is checked against the oracle: SSSP/BFS digests (and the
+    vectors of the last, resident wave) bit-exact, PPR digests within the mass
+    bounds and resident PPR vectors through the push gates."""
+    fork = _fork()
+    spec = fi.WORKLOADS["rmat22_mixed16384"]
+    g = fi.make_graph(spec)
+    queries = fi.make_sources(g, spec)
+    p = knobs(g, queries)
+    assert p.get("engine") == "grouped", p
+    say("rmat22 mixed, all queries", [len(s) for _, s in queries], p)
+    fg = run_workload(fork, g, queries, spec, p)
+    st = fg.stats()
+    say("waves", st["waves"], "passes", st["passes"])
+    assert st["waves"] >= 2
+    first = 0
+    for k, (qt, s) in enumerate(queries):
+        if qt == "ppr":
+            check_ppr_sample(fork, fg, g, s, first, spec, 3, 50 + k)
+        else:
+            check_sp_sample(fork, fg, g, s, first, qt, 4, 50 + k)
+        first += len(s)
+    fg.close()
+
+
 def test_rmat20_ppr_absolute_threshold_on_the_grouped_engine():
     """PPR forward push as the configuration states it: R-MAT 20, alpha 0.15,
     absolute threshold epsilon = 1e-6 (a vertex pushes while r(u) >= 1e-6),
