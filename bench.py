@@ -367,7 +367,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if "ppr" in kinds else "int32",
+        "dtype": "+".join((["int32"] if {"sssp", "bfs"} & set(kinds) else []) + (["f32"] if "ppr" in kinds else [])),
         "data": "synthetic",
         "config": {"workload": args.workload + (f"@scale{args.scale}" if args.scale else "")
                    + (f"@q{args.queries}" if args.queries else "")
