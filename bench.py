@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default: 0 on the scale-23 batch; "
                     "else 1)")
     ap.add_argument("--workload", default="rmat23_sssp_ppr65536")
+    ap.add_argument("--source-seed", type=int, default=-1,
+                    help="draw the sources with this seed instead of the workload's (same graph, same query mix)")
     ap.add_argument("--scheduler", default="priority")
     ap.add_argument("--engine", default="", choices=["", "buffered", "grouped"],
                     help="buffered: one work item per (partition, query); grouped: per (partition, 64 queries); "
@@ -254,6 +256,8 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
     spec = fi.WORKLOADS[args.workload]
+    if args.source_seed >= 0:
+        spec = dict(spec, seeds=(spec["seeds"][0], spec["seeds"][1], args.source_seed))
     t0 = time.perf_counter()
     g = fi.make_graph(spec, scale_override=args.scale or None)
     queries = fi.make_sources(g, spec)
@@ -331,10 +335,12 @@ def main():
     t0 = time.perf_counter()
     tot = None
     t_call = 0.0
+    step_ms = []
     for _ in range(args.steps):
         tc = time.perf_counter()
-        fg.run(**run_kw)
-        t_call += time.perf_counter() - tc
+        fg.run(**run_kw)  # returns when every buffer is empty
+        step_ms.append((time.perf_counter() - tc) * 1e3)
+        t_call += step_ms[-1] / 1e3
         st = fg.stats()
         tot = st if tot is None else {k: tot[k] + st[k] if isinstance(st[k], (int, float))
                                       else [a + b for a, b in zip(tot[k], st[k])] if isinstance(st[k], list)
@@ -346,7 +352,8 @@ def main():
     value = nq * args.steps / dt
     abytes = algorithmic_bytes(tot)
     kernel = "k_gprocess" if params["engine"] == "grouped" else "k_process"
-    prof = measured_traffic(args.workload, kernel) if not (args.scale or args.queries or args.l1_target) else None
+    prof = measured_traffic(args.workload, kernel) \
+        if not (args.scale or args.queries or args.l1_target or args.source_seed >= 0) else None
     launches = max(1, tot["process_launches"])
     avg_ms = tot["process_ms"] / launches
     # HBM bytes per launch: the profiled traffic over algorithmic bytes (per run; the number of passes
@@ -370,6 +377,7 @@ def main():
         "dtype": "+".join((["int32"] if {"sssp", "bfs"} & set(kinds) else []) + (["f32"] if "ppr" in kinds else [])),
         "data": "synthetic",
         "config": {"workload": args.workload + (f"@scale{args.scale}" if args.scale else "")
+                   + (f"@sources{args.source_seed}" if args.source_seed >= 0 else "")
                    + (f"@q{args.queries}" if args.queries else "")
                    + (f"+l1cert{args.l1_target:g}" if args.l1_target > 0 else ""), "queries": nq, "types": kinds, "vertices": g.num_vertices,
                    "edges": g.num_edges, "partitions": tot["num_partitions"], "scheduler": args.scheduler, "engine": params["engine"], "knobs": params, "knobs_source": source,
@@ -393,6 +401,7 @@ def main():
                    "prepare_s": t_prep,
                    "run_wall_ms_per_step": tot["wall_ms"] / args.steps, "setup_ms_per_step": tot["setup_ms"] / args.steps,
                    "python_run_ms_per_step": t_call * 1e3 / args.steps,
+                   "step_ms": step_ms, "step_ms_median": float(np.median(step_ms)),
                    "init_ms_per_step": tot["init_ms"] / args.steps, "run_ms_per_step": tot["run_ms"] / args.steps,
                    "process_ms_per_step": tot["process_ms"] / args.steps,
                    "passes_per_step": tot["passes"] / args.steps,
