@@ -176,6 +176,25 @@ def test_grouped_engine_exact_under_concurrency(fs):
     fg.close()
 
 
+@pytest.mark.parametrize("weights,seed", [((1, 1_000_000), 91), (None, 93)])
+def test_grouped_engine_other_weight_widths(fs, weights, seed):
+    """The grouped engine's SSSP edge steps with 4-byte weights (up to 10^6,
+    where the relaxed sum needs the overflow test) and on an unweighted graph
+    (unit weights), on the host with real concurrency: bit-exact, with a
+    partial group."""
+    lib = fs.load()
+    g = fi.rmat(10, seed=seed, weights=weights, weight_seed=seed + 1) if weights else fi.rmat(10, seed=seed)
+    srcs = fi.sources_uniform(g, 70, seed + 2)
+    fg = fs.SimtGraph(lib, g, partition_vertices=128)
+    fg.submit("sssp", srcs)
+    fg.run(max_passes=100000, engine="grouped")
+    st = fg.stats()
+    d = np.stack([fg.fetch(i) for i in range(len(srcs))])
+    fg.close()
+    assert st["weight_bytes"] == (4 if weights else 0), st["weight_bytes"]
+    np.testing.assert_array_equal(d, oracle.sssp(g, srcs))
+
+
 def test_no_alloc_training_on_the_host_build(fs):
     """fork_mlp_train_noalloc against fork_mlp_train in the host build (where
     device pointers are host pointers): two calls in a row, the second with
