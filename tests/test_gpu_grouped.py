@@ -36,6 +36,25 @@ def check_ppr(fork, fg, g, srcs, first, eps, mode):
         assert oracle.ppr_invariant_l1(g, s, p.astype(np.float64), r.astype(np.float64), ALPHA) <= 1e-4, i
 
 
+@pytest.mark.parametrize("weights,seed", [((1, 1_000_000), 91), (None, 93)])
+def test_grouped_sssp_other_weight_widths(weights, seed):
+    """R-MAT 13 SSSP on the grouped engine with 4-byte weights (up to 10^6)
+    and on an unweighted graph (unit weights): bit-exact, with a partial
+    group, at 1,024 threads per workgroup as the tuned runs use."""
+    fork = _fork()
+    g = fi.rmat(13, seed=seed, weights=weights, weight_seed=seed + 1) if weights else fi.rmat(13, seed=seed)
+    srcs = fi.sources_uniform(g, 100, seed + 2)
+    say("grouped sssp weights", weights)
+    fg = fork.ForkGraph.from_graph(g, partition_vertices=1024)
+    fg.submit("sssp", srcs)
+    fg.run(engine="grouped", group_threads=1024, max_passes=200000)
+    st = fg.stats()
+    d = np.stack([fg.fetch(i) for i in range(len(srcs))])
+    fg.close()
+    assert st["weight_bytes"] == (4 if weights else 0), st["weight_bytes"]
+    np.testing.assert_array_equal(d, oracle.sssp(g, srcs))
+
+
 @pytest.mark.parametrize("pv,sched", [(64, "priority"), (512, "priority"), (4096, "fifo"), (16384, "random"),
                                       (512, "maxops")])
 def test_grouped_mixed_batch_exact(pv, sched):
